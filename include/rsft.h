@@ -1,0 +1,314 @@
+/*
+ * rsft.h - C ABI of the MI355X (gfx950) RSFT library.
+ *
+ * RSFT: S. Wang, V. M. Patel, A. Petropulu, "An Efficient High-Dimensional
+ * Sparse Fourier Transform". The library runs the Location procedure of
+ * Algorithm 1 (Sec. III-C) on batches of complex frames in any fixed
+ * dimension D <= 4 and returns sparse frequency locations, each with an
+ * off-grid frequency estimate:
+ *
+ *   pre-permutation window W           (Sec. III-A, Sec. III-C.1)
+ *   permutation P_{sigma,0}            (Definition 1, per dimension)
+ *   flat window Wbar                   (Sec. IV-B)
+ *   aliasing into B buckets            (Definition 2, eq. l)
+ *   B-point N-D DFT                    (eq. f)
+ *   |.|^2 and first-stage NP detection (eq. exp, eq. tpd)
+ *   reverse mapping + accumulation     (Definition 4, eq. a_i)
+ *   second-stage detection             (Sec. III-C.5)
+ *   off-grid estimate per detected cell
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns rsft_status (RSFT_OK == 0); no C++ exception crosses
+ *   this interface. On error, rsft_last_error() returns a thread-local
+ *   message describing the most recent failure on the calling thread.
+ * - "Device pointer" means memory from hipMalloc (or a torch tensor's
+ *   data_ptr()) on the device the plan was created on. "Host pointer" means
+ *   ordinary process memory.
+ * - `stream` arguments are hipStream_t values passed as void*; NULL means the
+ *   default stream of the current device.
+ * - Frames are row-major [N_0][N_1]...[N_{D-1}] with the last dimension
+ *   contiguous; complex values are interleaved (re, im); complex64 = two
+ *   floats, complex128 = two doubles.
+ * - A plan owns all its device tables and workspace. It is immutable after
+ *   creation except for rsft_set_option, is used by one stream at a time,
+ *   and is independent of every other plan. Calls on one plan are not
+ *   thread-safe; different plans may be used from different threads.
+ */
+#ifndef RSFT_H
+#define RSFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSFT_MAX_DIMS 4
+#define RSFT_MAX_ROUNDS 32
+
+typedef enum {
+  RSFT_OK = 0,
+  RSFT_ERROR_INVALID_ARGUMENT = 1, /* NULL pointer, out-of-range value */
+  RSFT_ERROR_NOT_POW2 = 2,         /* N_d or B_d not a power of two */
+  RSFT_ERROR_BAD_SIGMA = 3,        /* sigma even (not invertible) or outside [1, N_d) */
+  RSFT_ERROR_UNSUPPORTED = 4,      /* valid for the paper, beyond this library's limits */
+  RSFT_ERROR_OUT_OF_MEMORY = 5,    /* a device or host allocation failed */
+  RSFT_ERROR_DEVICE = 6,           /* a HIP runtime call failed */
+  RSFT_ERROR_CAPACITY = 7,         /* detection records truncated (counts stay exact) */
+  RSFT_ERROR_NOT_READY = 8         /* results requested before any execute */
+} rsft_status;
+
+enum { RSFT_C64 = 0, RSFT_C128 = 1 };                  /* input element type */
+enum { RSFT_NOISE_KNOWN = 0, RSFT_NOISE_ESTIMATED = 1 };
+
+/*
+ * One frame shape and the paper's parameter set (Problem 1, Sec. IV-A):
+ * signal dimensions, windows, bucket counts, permutations, Pfa.
+ *
+ * ndim            D, 1..4.
+ * n[d], b[d]      N_d and B_d, powers of two with 1 <= B_d < N_d (Sec. II
+ *                 notation; Definition 2 requires B < N). Entries d >= ndim
+ *                 are ignored. N = prod N_d must be < 2^40.
+ * rounds          T, 1..RSFT_MAX_ROUNDS: iterations of Algorithm 1 over the
+ *                 same frame with independent permutations.
+ * sigma           host pointer to T*ndim permutation factors, round-major
+ *                 (sigma[s*ndim + d]); each odd and in [1, N_d) (Definition 1:
+ *                 sigma invertible mod N_d). NULL: drawn from `seed`,
+ *                 uniformly over the odd integers of [1, N_d), independently
+ *                 per round and dimension (splitmix64 counter stream). Copied
+ *                 at plan creation.
+ * seed            see sigma.
+ * window_atten_db sidelobe attenuation of the Dolph-Chebyshev pre-permutation
+ *                 window (Sec. III-C.1); 0 = rectangular window.
+ * flat_atten_db   attenuation of the Chebyshev base of the flat window
+ *                 (Sec. IV-B); < 0: same as window_atten_db; 0: rectangular
+ *                 base (an exact box of N_d/B_d bins).
+ * pfa             design false-alarm probability of one grid cell after the
+ *                 second stage, in (0, 1).
+ * mu              second-stage threshold 1..T (a cell is declared when at
+ *                 least mu of its T buckets were flagged); 0 means T.
+ * noise_mode      RSFT_NOISE_KNOWN: first-stage threshold of round s is
+ *                 gamma_s = noise_var * beta(sigma_s) * ln(1/p1) (eq. tpd with
+ *                 beta of eq. alpha_beta), p1 solving P[Bin(T,p1) >= mu] = pfa.
+ *                 RSFT_NOISE_ESTIMATED: noise_var*beta(sigma_s) is replaced by
+ *                 an FP64 order-statistic estimate from the round's own
+ *                 buckets (lower median X_(h), h = B/2, divided by
+ *                 sum_{i<h} 1/(B-i)).
+ * noise_var       sigma_n^2 for RSFT_NOISE_KNOWN (> 0).
+ * dtype           RSFT_C64 or RSFT_C128 (every frame of a plan must agree).
+ * max_detections  record capacity per frame, 1..2^24; 0 = 16384.
+ * max_batch       frames per execute for a uniform plan (nframes == 1),
+ *                 >= 1; 0 = 1. Ignored when nframes > 1.
+ */
+typedef struct {
+  int32_t ndim;
+  int32_t rounds;
+  int64_t n[RSFT_MAX_DIMS];
+  int64_t b[RSFT_MAX_DIMS];
+  const int64_t* sigma;
+  uint64_t seed;
+  double window_atten_db;
+  double flat_atten_db;
+  double pfa;
+  int32_t mu;
+  int32_t noise_mode;
+  double noise_var;
+  int32_t dtype;
+  int32_t max_detections;
+  int64_t max_batch;
+} rsft_params;
+
+/*
+ * One detected grid cell.
+ * frame      index of the frame in the batch.
+ * idx[d]     grid cell per dimension (row-major order defines sorting).
+ * votes      abar_i, the number of rounds whose bucket was flagged (>= mu).
+ * is_peak    1 when the cell's gain-corrected magnitude is a local maximum
+ *            over its 3^D - 1 circular neighbours (ties go to the lower
+ *            row-major index), else 0.
+ * magnitude  gain-corrected magnitude: median over the estimation rounds of
+ *            |fhat_s[M(i, sigma_s)]| divided by the flat-window response,
+ *            an estimate of |DFT(W r)| at the cell (FP32 inputs, FP64 math).
+ * freq[d]    off-grid frequency estimate in cycles/sample, in [0, 1):
+ *            (idx[d] + offset)/N_d, offset = vertex of a parabola through the
+ *            log magnitudes of the cell and its two neighbours along d,
+ *            clamped to [-1/2, 1/2] (FP64).
+ */
+typedef struct {
+  int64_t frame;
+  int64_t idx[RSFT_MAX_DIMS];
+  int32_t votes;
+  int32_t is_peak;
+  float magnitude;
+  float reserved;
+  double freq[RSFT_MAX_DIMS];
+} rsft_detection;
+
+/* Derived per-frame quantities (host FP64), for reproducibility and tests. */
+typedef struct {
+  int32_t ndim, rounds, mu, noise_mode;
+  int64_t n[RSFT_MAX_DIMS], b[RSFT_MAX_DIMS];
+  int64_t sigma[RSFT_MAX_ROUNDS][RSFT_MAX_DIMS];
+  int64_t sigma_inv[RSFT_MAX_ROUNDS][RSFT_MAX_DIMS]; /* eq. mod_inv */
+  int64_t tau[RSFT_MAX_ROUNDS][RSFT_MAX_DIMS];       /* sigma_inv mod B_d */
+  double beta[RSFT_MAX_ROUNDS];                      /* eq. alpha_beta */
+  double gamma[RSFT_MAX_ROUNDS];                     /* KNOWN-mode thresholds */
+  double p1;                                         /* first-stage Pfa per round */
+  double eta_m;              /* product over d of the window's 6-dB width (bins) */
+  double max_sparsity;       /* B / eta_m: by Remark 2 (Sec. IV-C) RSFT fails for
+                                K >= this many tones, whatever their SNR */
+  int32_t estimation_rounds; /* bit s set: round s feeds magnitude estimates */
+  int32_t reserved;
+} rsft_plan_info_t;
+
+typedef struct rsft_plan_s* rsft_plan_t;
+
+/*
+ * Create a plan on the current HIP device. `frames` holds nframes frame
+ * descriptors (host memory, copied).
+ *   nframes == 1: uniform batch; every execute processes `batch` frames
+ *                 (1..max_batch) of that shape packed back to back, all
+ *                 sharing one sigma set.
+ *   nframes  > 1: uneven batch; execute's batch must equal nframes and the
+ *                 frames are packed back to back in descriptor order (each
+ *                 frame occupies prod N_d elements). Shapes, sigma, windows
+ *                 and Pfa may differ per frame; rounds, mu and dtype may not.
+ * Builds the windows, permuted weight tables, thresholds and DFT tables on
+ * the host in FP64 and uploads them (one blocking copy). *out is set to NULL
+ * on failure. Errors: INVALID_ARGUMENT, NOT_POW2, BAD_SIGMA, UNSUPPORTED
+ * (B_d > 128 in some dimension, B > 16384 buckets per frame, N_d > 2^30,
+ * N >= 2^40), OUT_OF_MEMORY, DEVICE.
+ */
+rsft_status rsft_plan(const rsft_params* frames, int64_t nframes, rsft_plan_t* out);
+
+/*
+ * Enqueue the whole hot path for `batch` frames on `stream` and return
+ * (asynchronous). d_input: device pointer to the frames (dtype of the plan),
+ * owned by the caller, which keeps it alive and unmodified until the stream
+ * has passed this work. Results stay in the plan until the next execute.
+ * batch == 0 is a no-op. Errors: INVALID_ARGUMENT (batch out of range,
+ * NULL input with batch > 0), DEVICE.
+ */
+rsft_status rsft_execute(rsft_plan_t plan, const void* d_input, int64_t batch,
+                         void* stream);
+
+/*
+ * The same detections computed the plain way, as a comparator: for each
+ * frame and each round separately, gather the permuted samples, window,
+ * alias, DFT, threshold (Algorithm 1 literally, one launch chain per frame),
+ * then vote over all N cells of the frame. Same arguments and results as
+ * rsft_execute; much slower.
+ */
+rsft_status rsft_execute_per_frame(rsft_plan_t plan, const void* d_input,
+                                   int64_t batch, void* stream);
+
+/*
+ * Synchronize `stream` and copy the detections of the last execute to the
+ * host. h_out: host array of `capacity` records; receives the records sorted
+ * by (frame, row-major cell index). h_counts: host array with one entry per
+ * frame of the last execute (may be NULL); receives the exact number of
+ * detections of each frame, including any beyond the per-frame
+ * max_detections. n_written (may be NULL) receives the number of records
+ * written to h_out. A frame with more than max_detections detections keeps
+ * its first max_detections in row-major order. Returns RSFT_ERROR_CAPACITY
+ * when records were dropped (h_out too small, or a frame over its
+ * max_detections). Errors: NOT_READY, INVALID_ARGUMENT, DEVICE.
+ */
+rsft_status rsft_detect(rsft_plan_t plan, void* stream, rsft_detection* h_out,
+                        int64_t capacity, int64_t* h_counts, int64_t* n_written);
+
+/* Total number of detections of the last execute (synchronizes). */
+rsft_status rsft_detection_count(rsft_plan_t plan, void* stream, int64_t* total);
+
+/*
+ * Copy the buckets fhat_s of the last execute (eq. f; bucket j in the
+ * paper's indexing, i.e. after the permutation) to d_out, a device buffer of
+ * complex64: for each frame in batch order, [T][B_0]...[B_{D-1}]. Async on
+ * `stream`. Size: sum over frames of T*B*8 bytes.
+ */
+rsft_status rsft_get_buckets(rsft_plan_t plan, void* d_out, void* stream);
+
+/*
+ * Copy the first-stage flags c_s of the last execute to d_out (device,
+ * uint32): for each frame, [T][ceil(B/32)] words; bucket j (row-major
+ * flattened) is bit (j % 32) of word j / 32. Async on `stream`.
+ */
+rsft_status rsft_get_flags(rsft_plan_t plan, uint32_t* d_out, void* stream);
+
+/*
+ * Replace the flags of the last execute by d_flags (device, layout of
+ * rsft_get_flags) and redo the reverse mapping, second-stage detection and
+ * estimates from them (buckets unchanged). Lets a caller check the voting
+ * stage against known flags. Async on `stream`.
+ */
+rsft_status rsft_vote_flags(rsft_plan_t plan, const uint32_t* d_flags, void* stream);
+
+/* Per-frame derived parameters; frame indexes the descriptors of rsft_plan. */
+rsft_status rsft_plan_info(rsft_plan_t plan, int64_t frame, rsft_plan_info_t* out);
+
+/* Options (rsft_set_option). */
+enum {
+  RSFT_OPT_GRAPH = 0,  /* 1: replay the launch sequence as a captured hipGraph
+                          (cached per input pointer and batch); 0: launch
+                          kernels one by one. Default 1. */
+  RSFT_OPT_TIMING = 1  /* 1: record hipEvents around each stage in eager mode
+                          and accumulate their durations (forces GRAPH=0
+                          while set). Default 0. */
+};
+rsft_status rsft_set_option(rsft_plan_t plan, int32_t option, int64_t value);
+
+/* Stages reported by rsft_stage_times. */
+enum {
+  RSFT_STAGE_FOLD = 0,    /* window + permutation + flat window + aliasing */
+  RSFT_STAGE_DFT = 1,     /* B-point N-D DFT + |.|^2 + first-stage detection */
+  RSFT_STAGE_VOTE = 2,    /* reverse mapping + accumulation + second stage */
+  RSFT_STAGE_ESTIMATE = 3, /* sort + off-grid estimates + record output */
+  RSFT_NUM_STAGES = 4
+};
+/*
+ * Average device duration (ms) of each stage over the executes made with
+ * RSFT_OPT_TIMING on since the last reset (synchronizes the events). avg_ms:
+ * host array of RSFT_NUM_STAGES; count: number of executes averaged.
+ * reset != 0 clears the accumulators after reading.
+ */
+rsft_status rsft_stage_times(rsft_plan_t plan, double* avg_ms, int64_t* count,
+                             int32_t reset);
+
+/* Free the plan and everything it owns. NULL is ignored. */
+void rsft_destroy(rsft_plan_t plan);
+
+const char* rsft_status_string(rsft_status status);
+const char* rsft_last_error(void);
+
+/* ---- Host-only design functions (no device work; usable without a GPU) ---- */
+
+/* Dolph-Chebyshev window of length n (>= 1) with sidelobes atten_db (>= 0)
+ * below the main lobe, scaled so out[n/2] = 1 (Sec. III-C.1, Fig. 2).
+ * periodic != 0: the DFT-even variant (length n+1 symmetric, last sample
+ * dropped). atten_db = 0: all ones. out: host array of n doubles. */
+rsft_status rsft_chebyshev_window(int64_t n, double atten_db, int32_t periodic,
+                                  double* out);
+
+/* Flat window of length n for b buckets (Sec. IV-B), complex:
+ * out[2m] + j out[2m+1] = c0[m] * sum_{k=-(L-1)}^{0} exp(j 2 pi k m / n),
+ * L = n/b, c0 = periodic Chebyshev at atten_db (0: rectangular) rotated so
+ * its peak is at m = 0 and scaled to c0[0] = 1. out: host array of 2n. */
+rsft_status rsft_flat_window(int64_t n, int64_t b, double atten_db, double* out);
+
+/* sigma^{-1} mod n (eq. mod_inv). BAD_SIGMA if not invertible. */
+rsft_status rsft_mod_inverse(int64_t sigma, int64_t n, int64_t* out);
+
+/* p1 with P[Binomial(T, p1) >= mu] = pfa (FP64 bisection). */
+rsft_status rsft_stage1_probability(double pfa, int32_t rounds, int32_t mu,
+                                    double* out);
+
+/* The permutation factors a NULL-sigma plan would draw: out[s*ndim + d]. */
+rsft_status rsft_draw_sigma(uint64_t seed, int32_t rounds, int32_t ndim,
+                            const int64_t* n, int64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSFT_H */

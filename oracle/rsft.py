@@ -125,6 +125,21 @@ def rsft_round(r, plan, s):
     return np.fft.fftn(f)                                   # fhat <- NDFFT(f)
 
 
+def estimated_noise_floor(fhat):
+    """Noise floor sigma_n^2 beta(sigma_s) of one round estimated from the
+    round's own buckets (for when sigma_n^2 is unknown; the paper assumes it
+    known). Under H0 the B powers |fhat|^2 are exponential with that mean
+    (eq. exp); by the Renyi representation of exponential order statistics
+    E[X_(h)] = mean * sum_{i<h} 1/(B - i), so with h = B/2 (the lower median,
+    insensitive to the few buckets holding tones) X_(h) / sum_{i<h} 1/(B - i)
+    is unbiased."""
+    p = np.sort(np.abs(np.asarray(fhat)).ravel() ** 2)
+    B = p.size
+    h = max(B // 2, 1)
+    H = sum(1.0 / (B - i) for i in range(h))
+    return p[h - 1] / H
+
+
 def reverse_map_into(abar, flags, plan, s):
     """Reverse mapping + accumulation of one round (Def. 4, eq. a_i): every
     flagged bucket j adds one vote to each cell of R(j, sigma_s^{-1}), formed
@@ -136,22 +151,30 @@ def reverse_map_into(abar, flags, plan, s):
         abar[np.ix_(*sets)] += 1
 
 
-def rsft(r, plan):
+def rsft(r, plan, noise="known"):
     """Algorithm 1. Returns a dict with the per-round buckets fhat_s, the
-    first-stage flags c_s, the accumulated votes abar and the detections o
-    (row-major flat cell indices, ascending)."""
+    first-stage flags c_s, the thresholds used, the accumulated votes abar and
+    the detections o (row-major flat cell indices, ascending). noise="known"
+    uses gamma_s = sigma_n^2 beta(sigma_s) ln(1/p1); "estimated" replaces
+    sigma_n^2 beta(sigma_s) by estimated_noise_floor of the round."""
     buckets = []
     flags = []
+    gammas = []
     abar = np.zeros(plan.shape, dtype=np.int64)
     for s in range(plan.T):
         fhat = rsft_round(r, plan, s)
-        c = np.abs(fhat) ** 2 >= plan.gamma[s]              # NPdet1
+        if noise == "known":
+            gamma = plan.gamma[s]
+        else:
+            gamma = estimated_noise_floor(fhat) * math.log(1.0 / plan.p1)
+        gammas.append(gamma)
+        c = np.abs(fhat) ** 2 >= gamma                      # NPdet1
         reverse_map_into(abar, c, plan, s)                  # Reverse + accumulate
         buckets.append(fhat)
         flags.append(c)
     o = np.flatnonzero(abar >= plan.mu)                     # NPdet2
     return {"buckets": np.stack(buckets), "flags": np.stack(flags),
-            "votes": abar, "detections": o}
+            "gamma": np.array(gammas), "votes": abar, "detections": o}
 
 
 def votes_by_mapping(flags, plan):

@@ -1,0 +1,12 @@
+"""MI355X-native RSFT: batched, fused high-dimensional sparse FFT detection.
+
+The compute path is the HIP library librsft.so (C ABI in include/rsft.h);
+this package is its thin ctypes binding. Loading fails loudly when the
+library has not been built.
+"""
+
+from .binding import (  # noqa: F401
+    DETECTION_DTYPE, OPT_GRAPH, OPT_TIMING, STAGES, SYMBOLS, Plan, RsftError,
+    chebyshev_window, draw_sigma, flat_window, load_library, mod_inverse,
+    stage1_probability,
+)

@@ -1,0 +1,971 @@
+// HIP kernels of the RSFT hot path for gfx950 (CDNA4, wave64).
+//
+// Stage map (Algorithm 1 of the paper, Location procedure):
+//   fold      window W, permutation P_sigma, flat window Wbar and aliasing,
+//             all T rounds from one pass over the input (Def. 1, 2; eq. l)
+//   dft       B-point N-D DFT of each round's buckets on MFMA (eq. f), then
+//             |.|^2, first-stage NP threshold (eq. exp, eq. tpd) and flags
+//   vote      reverse mapping + accumulation + second stage (Def. 3-4,
+//             eq. a_i), enumerating only the preimages of flagged buckets
+//   scan      per-frame record offsets
+//   estimate  sort detections, gain-corrected magnitudes, peak test and
+//             log-parabolic off-grid offsets
+//
+// Why the fold reads the input in natural order: with tau = 0 the round-s
+// bucket before the DFT is f_s[b] = sum_{n = b mod B} wbar[n] y[[sigma n]_N].
+// Substituting m = [sigma n]_N and using B | N,
+//   n mod B = [sigma^{-1} m]_N mod B = (tau_s (m mod B)) mod B,
+//   tau_s = sigma^{-1} mod B,
+// so f_s[tau_s c] = sum_{m = c mod B} w[m] wbar[[sigma^{-1} m]_N] r[m]: a fold
+// of the unpermuted input by residue class c = m mod B with per-round weights
+// W_s[m] = w[m] wbar[[sigma^{-1} m]_N], followed by the relabel c -> tau_s c
+// mod B. The permutation becomes weight tables plus a bucket relabel, and
+// every input sample is loaded once, coalesced, for all rounds. The relabel
+// commutes with the DFT: fhat_s[j] = DFT(acc_s)[tau_s j mod B] per dimension.
+// Per dimension everything is separable, so in N-D the weight of a sample is
+// a row factor (leading dimensions) times a column factor (last dimension).
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "rsft_internal.h"
+
+namespace rsft {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ const FrameDesc& desc_of(const DevPtrs& p, int64_t f) {
+  return p.descs[p.uniform ? 0 : f];
+}
+__device__ __forceinline__ int64_t rel_of(const DevPtrs& p, int64_t f) {
+  return p.uniform ? f : 0;
+}
+
+// ---------------------------------------------------------------------------
+// fold: one work-group per tile = (frame, residue class of the leading
+// dimensions, chunk of columns). The class fixes (m_0 mod B_0, ...,
+// m_{D-2} mod B_{D-2}); its rows are listed in rowlist. Threads own V
+// consecutive columns; per column they sum the row-weighted samples of the
+// class's rows (4 FMAs per round per sample), multiply once by the column
+// weight, and keep the result per residue slot (columns P apart share a
+// residue because B_{D-1} divides P). A deterministic LDS reduction over the
+// slots of each residue finishes the tile: T x B_{D-1} partial buckets.
+// When a row is shorter than P the work-group splits into G = P / N_{D-1}
+// row groups that take every G-th row of the class.
+// ---------------------------------------------------------------------------
+
+template <bool C128, int V>
+__device__ __forceinline__ void load_vec(const void* base, int64_t idx, float2 (&x)[V]) {
+  if constexpr (!C128) {
+    const float4* p4 = reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(base) + idx);
+#pragma unroll
+    for (int q = 0; q < V / 2; ++q) {
+      const float4 v = p4[q];
+      x[2 * q] = make_float2(v.x, v.y);
+      x[2 * q + 1] = make_float2(v.z, v.w);
+    }
+  } else {
+    const double2* p2 = reinterpret_cast<const double2*>(base) + idx;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const double2 v = p2[q];
+      x[q] = make_float2(float(v.x), float(v.y));
+    }
+  }
+}
+
+template <int TG, int V, int THREADS, bool C128>
+__global__ __launch_bounds__(THREADS) void fold_kernel(DevPtrs p, const void* __restrict__ input,
+                                                       int64_t tiles_per_frame, int round0, int T) {
+  constexpr int P = THREADS * V;
+  __shared__ float2 red[TG * P];
+
+  const int tid = threadIdx.x;
+  int64_t f;
+  int cls, chunk;
+  if (p.uniform) {
+    const FrameDesc& d0 = p.descs[0];
+    f = int64_t(blockIdx.x) / tiles_per_frame;
+    const int64_t rem = int64_t(blockIdx.x) - f * tiles_per_frame;
+    cls = int(rem / d0.nchunks);
+    chunk = int(rem - int64_t(cls) * d0.nchunks);
+  } else {
+    const int32_t* t = p.tiles + 3 * int64_t(blockIdx.x);
+    f = t[0];
+    cls = t[1];
+    chunk = t[2];
+  }
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  const int nl = d.n_last, bl = d.b_last, R = d.rows_per_class, rows_total = d.rows_total;
+  const float2* __restrict__ wrow = p.wrow + d.wrow_off;
+  const float2* __restrict__ wcol = p.wcol + d.wcol_off;
+  const int32_t* __restrict__ rl = p.rowlist + d.rowlist_off + int64_t(cls) * R;
+  const int64_t in_base = d.in_off + rel * d.in_stride;
+  const void* in = C128 ? static_cast<const void*>(static_cast<const double2*>(input) + in_base)
+                        : static_cast<const void*>(static_cast<const float2*>(input) + in_base);
+
+  float ar[TG][V], ai[TG][V];
+#pragma unroll
+  for (int s = 0; s < TG; ++s)
+#pragma unroll
+    for (int v = 0; v < V; ++v) ar[s][v] = ai[s][v] = 0.f;
+
+  if (nl >= P) {
+    // every thread walks all rows of the class; the row is uniform
+    const int npass = d.chunk_cols / P;
+    for (int pass = 0; pass < npass; ++pass) {
+      const int col = chunk * d.chunk_cols + pass * P + tid * V;
+      float cr[TG][V], ci[TG][V];
+#pragma unroll
+      for (int s = 0; s < TG; ++s)
+#pragma unroll
+        for (int v = 0; v < V; ++v) cr[s][v] = ci[s][v] = 0.f;
+#pragma unroll 4
+      for (int i = 0; i < R; ++i) {
+        const int row = rl[i];
+        float2 x[V];
+        load_vec<C128, V>(in, int64_t(row) * nl + col, x);
+#pragma unroll
+        for (int s = 0; s < TG; ++s) {
+          const float2 w = wrow[int64_t(round0 + s) * rows_total + row];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            cr[s][v] = fmaf(w.x, x[v].x, fmaf(-w.y, x[v].y, cr[s][v]));
+            ci[s][v] = fmaf(w.x, x[v].y, fmaf(w.y, x[v].x, ci[s][v]));
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < TG; ++s)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const float2 w = wcol[int64_t(round0 + s) * nl + col + v];
+          ar[s][v] = fmaf(w.x, cr[s][v], fmaf(-w.y, ci[s][v], ar[s][v]));
+          ai[s][v] = fmaf(w.x, ci[s][v], fmaf(w.y, cr[s][v], ai[s][v]));
+        }
+    }
+  } else {
+    // short rows: G row groups, each covering the whole row
+    const int G = P / nl;
+    const int g = (tid * V) / nl;
+    const int col = (tid * V) - g * nl;
+    float cr[TG][V], ci[TG][V];
+#pragma unroll
+    for (int s = 0; s < TG; ++s)
+#pragma unroll
+      for (int v = 0; v < V; ++v) cr[s][v] = ci[s][v] = 0.f;
+#pragma unroll 2
+    for (int i = g; i < R; i += G) {
+      const int row = rl[i];
+      float2 x[V];
+      load_vec<C128, V>(in, int64_t(row) * nl + col, x);
+#pragma unroll
+      for (int s = 0; s < TG; ++s) {
+        const float2 w = wrow[int64_t(round0 + s) * rows_total + row];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          cr[s][v] = fmaf(w.x, x[v].x, fmaf(-w.y, x[v].y, cr[s][v]));
+          ci[s][v] = fmaf(w.x, x[v].y, fmaf(w.y, x[v].x, ci[s][v]));
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < TG; ++s)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const float2 w = wcol[int64_t(round0 + s) * nl + col + v];
+        ar[s][v] = w.x * cr[s][v] - w.y * ci[s][v];
+        ai[s][v] = w.x * ci[s][v] + w.y * cr[s][v];
+      }
+  }
+
+#pragma unroll
+  for (int s = 0; s < TG; ++s)
+#pragma unroll
+    for (int v = 0; v < V; ++v) red[s * P + tid * V + v] = make_float2(ar[s][v], ai[s][v]);
+  __syncthreads();
+
+  // slot q holds residue q mod B_{D-1}; sum the P / B_{D-1} slots of each
+  // residue in a fixed order
+  const int tg = (T - round0) < TG ? (T - round0) : TG;
+  const int nslots = P / bl;
+  float2* part = p.part + d.part_off + rel * d.part_stride;
+  for (int o = tid; o < tg * bl; o += THREADS) {
+    const int s = o / bl;
+    const int rho = o - s * bl;
+    float sr = 0.f, si = 0.f;
+    for (int k = 0; k < nslots; ++k) {
+      const float2 v = red[s * P + rho + k * bl];
+      sr += v.x;
+      si += v.y;
+    }
+    part[(int64_t(chunk) * T + round0 + s) * d.B + int64_t(cls) * bl + rho] = make_float2(sr, si);
+  }
+}
+
+template <int TG, int V, int THREADS>
+static hipError_t launch_fold_t(const DevPtrs& p, const void* input, int dtype, int64_t tpf,
+                                int64_t ntiles, int round0, int T, hipStream_t st) {
+  if (dtype == RSFT_C128)
+    hipLaunchKernelGGL((fold_kernel<TG, V, THREADS, true>), dim3(unsigned(ntiles)), dim3(THREADS), 0,
+                       st, p, input, tpf, round0, T);
+  else
+    hipLaunchKernelGGL((fold_kernel<TG, V, THREADS, false>), dim3(unsigned(ntiles)), dim3(THREADS), 0,
+                       st, p, input, tpf, round0, T);
+  return hipGetLastError();
+}
+
+template <int V, int THREADS>
+static hipError_t launch_fold_v(const DevPtrs& p, const void* input, int dtype, int64_t tpf,
+                                int64_t ntiles, int round0, int rounds, int T, hipStream_t st) {
+  switch (rounds) {
+    case 1: return launch_fold_t<1, V, THREADS>(p, input, dtype, tpf, ntiles, round0, T, st);
+    case 2: return launch_fold_t<2, V, THREADS>(p, input, dtype, tpf, ntiles, round0, T, st);
+    case 3: return launch_fold_t<3, V, THREADS>(p, input, dtype, tpf, ntiles, round0, T, st);
+    default: return launch_fold_t<4, V, THREADS>(p, input, dtype, tpf, ntiles, round0, T, st);
+  }
+}
+
+int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
+                int64_t tiles_per_frame, int64_t ntiles, int round0, int rounds, int T,
+                const FoldConfig& cfg, void* stream) {
+  (void)nframes;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ntiles <= 0) return hipSuccess;
+  if (cfg.vec == 4) {
+    switch (cfg.threads) {
+      case 256: return launch_fold_v<4, 256>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
+      case 512: return launch_fold_v<4, 512>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
+      case 1024: return launch_fold_v<4, 1024>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (cfg.vec == 2) {
+    switch (cfg.threads) {
+      case 256: return launch_fold_v<2, 256>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
+      case 512: return launch_fold_v<2, 512>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// dft: one work-group per (round, frame). The round's B partial buckets are
+// summed over column chunks into LDS (separate re / im planes), then the DFT
+// is applied along each dimension in place as complex matrix products on
+// MFMA (v_mfma_f32_16x16x4_f32): for a dimension of length n, the lines
+// along it are the columns of an n x (B/n) matrix X and Y = D_n X with
+// D_n[k][b] = exp(-2 pi i ((k b) mod n) / n), the phase reduced exactly as
+// an integer before the table lookup. Each wave owns 16 lines at a time and
+// keeps all n outputs of its lines in registers until written back, so the
+// transform can be done in place. The epilogue reads the transform at the
+// relabelled index (tau_s j mod B_d per dimension), writes the buckets in
+// the paper's indexing, and sets flag bits |fhat|^2 >= gamma_s with ballots.
+// ---------------------------------------------------------------------------
+
+constexpr int kDftThreads = 256;
+constexpr int kMaxKTiles = 8;  // n <= 128 per dimension
+
+__device__ __forceinline__ void mode_product(float* __restrict__ re, float* __restrict__ im,
+                                             const float2* __restrict__ tw, int n, int inner_shift,
+                                             int nlines, int grp) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15;
+  const int krow = lane >> 4;
+  const int line = grp * 16 + col;
+  const bool lvalid = line < nlines;
+  const int inner = 1 << inner_shift;
+  const int o = line >> inner_shift;
+  const int ii = line & (inner - 1);
+  const int base = o * n * inner + ii;
+  const int nkt = (n + 15) >> 4;
+  floatx4 accR[kMaxKTiles], accI[kMaxKTiles];
+#pragma unroll
+  for (int kt = 0; kt < kMaxKTiles; ++kt) {
+    accR[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    accI[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  for (int b0 = 0; b0 < n; b0 += 4) {
+    const int b = b0 + krow;
+    float xr = 0.f, xi = 0.f;
+    if (lvalid && b < n) {
+      xr = re[base + b * inner];
+      xi = im[base + b * inner];
+    }
+#pragma unroll
+    for (int kt = 0; kt < kMaxKTiles; ++kt) {
+      if (kt < nkt) {
+        const int k = kt * 16 + col;
+        float dr = 0.f, di = 0.f;
+        if (k < n && b < n) {
+          const float2 t = tw[(k * b) & (n - 1)];
+          dr = t.x;
+          di = t.y;
+        }
+        accR[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xr, accR[kt], 0, 0, 0);
+        accR[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-di, xi, accR[kt], 0, 0, 0);
+        accI[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xi, accI[kt], 0, 0, 0);
+        accI[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(di, xr, accI[kt], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int kt = 0; kt < kMaxKTiles; ++kt) {
+    if (kt < nkt) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = kt * 16 + krow * 4 + r;
+        if (k < n && lvalid) {
+          re[base + k * inner] = accR[kt][r];
+          im[base + k * inner] = accI[kt][r];
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int maxB, int frame0,
+                                                          int identity, int nchunks_override) {
+  extern __shared__ float smem[];
+  float* re = smem;
+  float* im = smem + maxB;
+  float2* tws = reinterpret_cast<float2*>(smem + 2 * maxB);
+  __shared__ uint32_t sel_prefix, sel_rank;
+  __shared__ uint32_t hist[256];
+
+  const int s = blockIdx.x;
+  const int64_t f = frame0 + int64_t(blockIdx.y);
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  const int B = d.B;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  constexpr int nwaves = kDftThreads / 64;
+
+  if (s == 0) {
+    if (tid == 0) p.counts[f] = 0u;
+    for (int c = tid; c < d.cchunks; c += kDftThreads)
+      p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = 0u;
+  }
+
+  // twiddles of each dimension, concatenated
+  int twoff[kMaxDims];
+  {
+    int acc = 0;
+    for (int dd = 0; dd < d.ndim; ++dd) {
+      twoff[dd] = acc;
+      for (int m = tid; m < d.b[dd]; m += kDftThreads) tws[acc + m] = p.tw[d.tw_off[dd] + m];
+      acc += d.b[dd];
+    }
+  }
+  // sum the column-chunk partials of this round
+  const int nch = nchunks_override > 0 ? nchunks_override : d.nchunks;
+  const float2* part = p.part + d.part_off + rel * d.part_stride;
+  for (int idx = tid; idx < B; idx += kDftThreads) {
+    float sr = 0.f, si = 0.f;
+    for (int c = 0; c < nch; ++c) {
+      const float2 v = part[(int64_t(c) * T + s) * B + idx];
+      sr += v.x;
+      si += v.y;
+    }
+    re[idx] = sr;
+    im[idx] = si;
+  }
+  __syncthreads();
+
+  for (int dd = 0; dd < d.ndim; ++dd) {
+    const int n = d.b[dd];
+    const int nlines = B / n;
+    const int groups = (nlines + 15) >> 4;
+    for (int grp = wave; grp < groups; grp += nwaves)
+      mode_product(re, im, tws + twoff[dd], n, d.bshift[dd], nlines, grp);
+    __syncthreads();
+  }
+
+  float2* bout = p.buckets + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
+  uint32_t* fout = p.flags + d.flag_off + rel * d.flag_stride + int64_t(s) * d.words;
+
+  auto relabel = [&](int j) {
+    int kf = 0;
+    for (int dd = 0; dd < d.ndim; ++dd) {
+      const int jd = (j >> d.bshift[dd]) & (d.b[dd] - 1);
+      const int kd = identity ? jd : ((d.tau[s][dd] * jd) & (d.b[dd] - 1));
+      kf |= kd << d.bshift[dd];
+    }
+    return kf;
+  };
+
+  double gamma = d.gamma[s];
+  if (d.noise_mode == RSFT_NOISE_ESTIMATED) {
+    // pass 1: buckets out, powers into the re plane (relabel is a bijection)
+    for (int j = tid; j < B; j += kDftThreads) {
+      const int kf = relabel(j);
+      const float xr = re[kf], xi = im[kf];
+      bout[j] = make_float2(xr, xi);
+      re[kf] = xr * xr + xi * xi;
+    }
+    __syncthreads();
+    // lower median X_(h), h = B/2, by 4 passes of 8-bit radix selection
+    // (non-negative floats order like their bit patterns)
+    uint32_t prefix = 0u, pmask = 0u, rank = uint32_t(B / 2 > 0 ? B / 2 : 1);
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      for (int q = tid; q < 256; q += kDftThreads) hist[q] = 0u;
+      __syncthreads();
+      for (int idx = tid; idx < B; idx += kDftThreads) {
+        const uint32_t u = __float_as_uint(re[idx]);
+        if ((u & pmask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t cum = 0u;
+        for (uint32_t dg = 0; dg < 256u; ++dg) {
+          if (cum + hist[dg] >= rank) {
+            sel_prefix = prefix | (dg << shift);
+            sel_rank = rank - cum;
+            break;
+          }
+          cum += hist[dg];
+        }
+      }
+      __syncthreads();
+      prefix = sel_prefix;
+      rank = sel_rank;
+      pmask |= 255u << shift;
+      __syncthreads();
+    }
+    const double xh = double(__uint_as_float(prefix));
+    gamma = xh / d.renyi_h * d.log_inv_p1;
+    for (int j0 = wave * 64; j0 < B; j0 += kDftThreads) {
+      const int j = j0 + lane;
+      bool flag = false;
+      if (j < B) flag = double(re[relabel(j)]) >= gamma;
+      const unsigned long long m = __ballot(flag);
+      if (lane == 0) {
+        const int w = j0 >> 5;
+        fout[w] = uint32_t(m & 0xffffffffull);
+        if (w + 1 < d.words) fout[w + 1] = uint32_t(m >> 32);
+      }
+    }
+  } else {
+    for (int j0 = wave * 64; j0 < B; j0 += kDftThreads) {
+      const int j = j0 + lane;
+      bool flag = false;
+      if (j < B) {
+        const int kf = relabel(j);
+        const float xr = re[kf], xi = im[kf];
+        bout[j] = make_float2(xr, xi);
+        flag = double(xr * xr + xi * xi) >= gamma;
+      }
+      const unsigned long long m = __ballot(flag);
+      if (lane == 0) {
+        const int w = j0 >> 5;
+        fout[w] = uint32_t(m & 0xffffffffull);
+        if (w + 1 < d.words) fout[w + 1] = uint32_t(m >> 32);
+      }
+    }
+  }
+}
+
+int launch_dft(const DevPtrs& p, int64_t nframes, int T, int maxB, int sum_tw, int identity,
+               int nchunks_override, void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  const size_t shmem = size_t(2 * maxB) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
+  hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), unsigned(nframes)), dim3(kDftThreads), shmem,
+                     static_cast<hipStream_t>(stream), p, T, maxB, 0, identity, nchunks_override);
+  return hipGetLastError();
+}
+
+static int launch_dft_frame(const DevPtrs& p, int64_t frame, int T, int maxB, int sum_tw,
+                            hipStream_t st) {
+  const size_t shmem = size_t(2 * maxB) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
+  hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), 1u), dim3(kDftThreads), shmem, st, p, T, maxB,
+                     int(frame), 1, 1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// vote: abar_i = sum_s c_s[M(i, sigma_s)] with M_d(i) = [sigma_{s,d} i_d] >>
+// log2 L_d (Def. 3). A cell with at least mu votes has a flag in one of the
+// rounds 0..T-mu, so only preimages R(j, sigma_{s0}^{-1}) of buckets flagged
+// in those rounds are visited (Def. 4): cell i_d = [sigma_inv u_d] for u_d in
+// [j_d L_d, (j_d + 1) L_d). A cell reached from round s0 is skipped when an
+// earlier candidate round also flags it, so each cell is visited once (the
+// preimages of one round are disjoint, Property 4). Work-group = 256 buckets
+// of one candidate round of one frame. A detected cell sets its bit in the
+// frame's bitmap and bumps its frame and compaction-chunk counters. Index
+// products are taken modulo 2^32 and masked, which equals the product modulo
+// N_d (a power of two).
+// ---------------------------------------------------------------------------
+
+constexpr int kVoteThreads = 256;
+
+__device__ __forceinline__ void mark_cell(const DevPtrs& p, const FrameDesc& d, int64_t rel, int64_t f,
+                                          bool hit, unsigned long long flat) {
+  const unsigned long long m = __ballot(hit);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  if (lane == __ffsll((long long)m) - 1) atomicAdd(&p.counts[f], uint32_t(__popcll(m)));
+  if (hit) {
+    atomicOr(&p.bitmap[d.bitmap_off + rel * d.bitmap_stride + int64_t(flat >> 5)], 1u << (flat & 31ull));
+    atomicAdd(&p.chunk_counts[d.chunk_off + rel * d.chunk_stride + int64_t(flat >> kCompactShift)], 1u);
+  }
+}
+
+__global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, int mu) {
+  extern __shared__ uint32_t sflags[];
+  __shared__ int list[kVoteThreads];
+  __shared__ int wave_count[kVoteThreads / 64];
+
+  const int chunk = blockIdx.x;
+  const int s0 = blockIdx.y;
+  const int64_t f = blockIdx.z;
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  const int B = d.B;
+  if (chunk * kVoteThreads >= B) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int words = d.words;
+
+  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
+  for (int w = tid; w < T * words; w += kVoteThreads) sflags[w] = fl[w];
+  __syncthreads();
+
+  const int j = chunk * kVoteThreads + tid;
+  const bool set = j < B && ((sflags[s0 * words + (j >> 5)] >> (j & 31)) & 1u);
+  const unsigned long long m = __ballot(set);
+  if (lane == 0) wave_count[wave] = __popcll(m);
+  __syncthreads();
+  int off = 0, nb = 0;
+  for (int w = 0; w < kVoteThreads / 64; ++w) {
+    if (w < wave) off += wave_count[w];
+    nb += wave_count[w];
+  }
+  if (set) list[off + __popcll(m & ((1ull << lane) - 1ull))] = j;
+  __syncthreads();
+  if (nb == 0) return;
+
+  const int Ls = d.Lshift;
+  const int64_t total = int64_t(nb) << Ls;
+  const int64_t nloop = (total + kVoteThreads - 1) / kVoteThreads * kVoteThreads;
+  for (int64_t w = tid; w < nloop; w += kVoteThreads) {
+    bool hit = false;
+    unsigned long long flat = 0ull;
+    if (w < total) {
+      const int jj = list[w >> Ls];
+      const uint32_t t = uint32_t(w & ((int64_t(1) << Ls) - 1));
+      uint32_t cell[kMaxDims];
+      for (int dd = 0; dd < d.ndim; ++dd) {
+        const uint32_t jd = uint32_t(jj >> d.bshift[dd]) & uint32_t(d.b[dd] - 1);
+        const uint32_t td = (t >> d.tshift[dd]) & uint32_t(d.l[dd] - 1);
+        const uint32_t u = (jd << d.lshift[dd]) | td;
+        cell[dd] = (uint32_t(d.sigma_inv[s0][dd]) * u) & uint32_t(d.n[dd] - 1);
+        flat |= (unsigned long long)cell[dd] << d.nshift[dd];
+      }
+      int votes = 0;
+      bool skip = false;
+      for (int s = 0; s < T; ++s) {
+        uint32_t jf = 0u;
+        for (int dd = 0; dd < d.ndim; ++dd) {
+          const uint32_t uu = (uint32_t(d.sigma[s][dd]) * cell[dd]) & uint32_t(d.n[dd] - 1);
+          jf |= (uu >> d.lshift[dd]) << d.bshift[dd];
+        }
+        const int bit = int((sflags[s * words + (jf >> 5)] >> (jf & 31u)) & 1u);
+        if (s < s0 && bit) skip = true;
+        votes += bit;
+      }
+      hit = !skip && votes >= mu;
+    }
+    mark_cell(p, d, rel, f, hit, flat);
+  }
+}
+
+int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_chunks, int max_words,
+                void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  const size_t shmem = size_t(T) * size_t(max_words) * sizeof(uint32_t);
+  hipLaunchKernelGGL(vote_kernel, dim3(unsigned(max_chunks), unsigned(T - mu + 1), unsigned(nframes)),
+                     dim3(kVoteThreads), shmem, static_cast<hipStream_t>(stream), p, T, mu);
+  return hipGetLastError();
+}
+
+// counters of a frame are cleared by the dft stage of round 0; this kernel
+// does the same for a re-vote from given flags
+__global__ void zero_counts_kernel(DevPtrs p) {
+  const int64_t f = blockIdx.x;
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  if (threadIdx.x == 0) p.counts[f] = 0u;
+  for (int c = threadIdx.x; c < d.cchunks; c += blockDim.x)
+    p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = 0u;
+}
+
+int launch_zero_counts(const DevPtrs& p, int64_t nframes, void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_counts_kernel, dim3(unsigned(nframes)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scan: offsets[f] = sum_{g<f} min(count_g, cap_g), offsets[nframes] = total;
+// chunk_offsets = rank of each compaction chunk's first detection in its
+// frame (running sum of the chunk counters, in row-major cell order).
+// ---------------------------------------------------------------------------
+
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t nframes) {
+  __shared__ int64_t buf[kScanThreads];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x;
+  for (int64_t f = tid; f < nframes; f += kScanThreads) {
+    const FrameDesc& d = desc_of(p, f);
+    const int64_t rel = rel_of(p, f);
+    int64_t run = 0;
+    for (int c = 0; c < d.cchunks; ++c) {
+      p.chunk_offsets[d.chunk_off + rel * d.chunk_stride + c] = run;
+      run += p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c];
+    }
+  }
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int64_t start = 0; start < nframes; start += kScanThreads) {
+    const int64_t f = start + tid;
+    int64_t v = 0;
+    if (f < nframes) {
+      const int64_t c = p.counts[f];
+      const int64_t cap = desc_of(p, f).cap;
+      v = c < cap ? c : cap;
+    }
+    buf[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const int64_t add = tid >= off ? buf[tid - off] : 0;
+      __syncthreads();
+      buf[tid] += add;
+      __syncthreads();
+    }
+    if (f < nframes) p.offsets[f + 1] = carry + buf[tid];
+    __syncthreads();
+    if (tid == kScanThreads - 1) carry += buf[tid];
+    __syncthreads();
+  }
+  if (tid == 0) p.offsets[0] = 0;
+}
+
+int launch_scan(const DevPtrs& p, int64_t nframes, void* stream) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, static_cast<hipStream_t>(stream), p,
+                     nframes);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// estimate: one work-group per (compaction chunk of 2^15 cells, frame). It
+// reads the chunk's bitmap words in row-major order (clearing them for the
+// next execute), turns set bits into an ordered list in LDS (popcount + block
+// prefix sum), and for each detected cell writes its record at its rank in
+// the frame: votes recounted from the flags, gain-corrected magnitude
+// (median over the estimation rounds of |fhat_s[M(i, sigma_s)]| divided by
+// the flat-window response at the cell's offset inside its bucket), a peak
+// test against the 3^D - 1 circular neighbours (strictly above lower-index
+// neighbours, at least equal to higher-index ones) and per dimension the
+// vertex of a parabola through the log magnitudes at offsets -1, 0, +1,
+// clamped to [-1/2, 1/2]. FP32 bucket values, FP64 arithmetic.
+// ---------------------------------------------------------------------------
+
+constexpr int kEstThreads = 256;
+
+__device__ double cell_magnitude(const DevPtrs& p, const FrameDesc& d, int64_t rel, int T,
+                                 const uint32_t* cell) {
+  double vals[kMaxRounds];
+  int m = 0;
+  const float2* bk = p.buckets + d.bucket_off + rel * d.bucket_stride;
+  for (int s = 0; s < T; ++s) {
+    if (!((d.est_mask >> s) & 1)) continue;
+    uint32_t jf = 0u;
+    double g = 1.0;
+    for (int dd = 0; dd < d.ndim; ++dd) {
+      const uint32_t u = (uint32_t(d.sigma[s][dd]) * cell[dd]) & uint32_t(d.n[dd] - 1);
+      const uint32_t jd = u >> d.lshift[dd];
+      const uint32_t t = u & uint32_t(d.l[dd] - 1);
+      g *= p.gains[d.gain_off[dd] + t];
+      jf |= jd << d.bshift[dd];
+    }
+    const float2 v = bk[int64_t(s) * d.B + jf];
+    const double mag = sqrt(double(v.x) * double(v.x) + double(v.y) * double(v.y));
+    const double a = mag / g;
+    int q = m;
+    while (q > 0 && vals[q - 1] > a) {
+      vals[q] = vals[q - 1];
+      --q;
+    }
+    vals[q] = a;
+    ++m;
+  }
+  if (m == 0) return 0.0;
+  return (m & 1) ? vals[m / 2] : 0.5 * (vals[m / 2 - 1] + vals[m / 2]);
+}
+
+__device__ __forceinline__ double log_parabola_offset(double am, double a0, double ap) {
+  const double tiny = 1e-300;
+  const double lm = log(am > tiny ? am : tiny);
+  const double l0 = log(a0 > tiny ? a0 : tiny);
+  const double lp = log(ap > tiny ? ap : tiny);
+  const double den = 2.0 * l0 - lm - lp;
+  if (!(den > 0.0)) return 0.0;
+  double v = 0.5 * (lp - lm) / den;
+  v = v < -0.5 ? -0.5 : v;
+  v = v > 0.5 ? 0.5 : v;
+  return v;
+}
+
+__device__ void write_record(const DevPtrs& p, const FrameDesc& d, int64_t rel, int64_t f, int T,
+                             unsigned long long flat, int64_t out) {
+  const int D = d.ndim;
+  uint32_t cell[kMaxDims];
+  for (int dd = 0; dd < D; ++dd) cell[dd] = uint32_t(flat >> d.nshift[dd]) & uint32_t(d.n[dd] - 1);
+  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
+  int votes = 0;
+  for (int s = 0; s < T; ++s) {
+    uint32_t jf = 0u;
+    for (int dd = 0; dd < D; ++dd) {
+      const uint32_t u = (uint32_t(d.sigma[s][dd]) * cell[dd]) & uint32_t(d.n[dd] - 1);
+      jf |= (u >> d.lshift[dd]) << d.bshift[dd];
+    }
+    votes += int((fl[int64_t(s) * d.words + (jf >> 5)] >> (jf & 31u)) & 1u);
+  }
+  const double a0 = cell_magnitude(p, d, rel, T, cell);
+  int npow3 = 1;
+  for (int dd = 0; dd < D; ++dd) npow3 *= 3;
+  bool peak = true;
+  for (int code = 0; code < npow3; ++code) {
+    int c = code;
+    bool centre = true;
+    uint32_t nb[kMaxDims];
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      if (o != 0) centre = false;
+      nb[dd] = uint32_t(int64_t(cell[dd]) + o + d.n[dd]) & uint32_t(d.n[dd] - 1);
+    }
+    if (centre) continue;
+    unsigned long long nflat = 0ull;
+    for (int dd = 0; dd < D; ++dd) nflat |= (unsigned long long)nb[dd] << d.nshift[dd];
+    if (nflat == flat) continue;
+    const double an = cell_magnitude(p, d, rel, T, nb);
+    if (nflat < flat) {
+      if (!(a0 > an)) peak = false;
+    } else {
+      if (!(a0 >= an)) peak = false;
+    }
+  }
+  rsft_detection rec;
+  rec.frame = f;
+  for (int dd = 0; dd < kMaxDims; ++dd) {
+    rec.idx[dd] = 0;
+    rec.freq[dd] = 0.0;
+  }
+  for (int dd = 0; dd < D; ++dd) {
+    uint32_t mcell[kMaxDims], pcell[kMaxDims];
+    for (int e = 0; e < D; ++e) mcell[e] = pcell[e] = cell[e];
+    mcell[dd] = (cell[dd] + uint32_t(d.n[dd]) - 1u) & uint32_t(d.n[dd] - 1);
+    pcell[dd] = (cell[dd] + 1u) & uint32_t(d.n[dd] - 1);
+    const double am = cell_magnitude(p, d, rel, T, mcell);
+    const double ap = cell_magnitude(p, d, rel, T, pcell);
+    const double delta = log_parabola_offset(am, a0, ap);
+    double fr = (double(cell[dd]) + delta) / double(d.n[dd]);
+    if (fr < 0.0) fr += 1.0;
+    if (fr >= 1.0) fr -= 1.0;
+    rec.idx[dd] = cell[dd];
+    rec.freq[dd] = fr;
+  }
+  rec.votes = votes;
+  rec.is_peak = peak ? 1 : 0;
+  rec.magnitude = float(a0);
+  rec.reserved = 0.f;
+  p.records[out] = rec;
+}
+
+__global__ __launch_bounds__(kEstThreads) void estimate_kernel(DevPtrs p, int T) {
+  constexpr int kWordsPerPass = kEstThreads;
+  __shared__ uint32_t list[kWordsPerPass * 32];
+  __shared__ uint32_t wsum[kEstThreads / 64];
+  const int c = blockIdx.x;
+  const int64_t f = blockIdx.y;
+  const FrameDesc& d = desc_of(p, f);
+  if (c >= d.cchunks) return;
+  const int64_t rel = rel_of(p, f);
+  const int64_t ck = d.chunk_off + rel * d.chunk_stride + c;
+  if (p.chunk_counts[ck] == 0u) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t rank0 = p.chunk_offsets[ck];
+  const int64_t out0 = p.offsets[f];
+  const int64_t cap = d.cap;
+  uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride;
+  const int w0 = c << (kCompactShift - 5);
+  const int wend = min(d.bitmap_words, w0 + (1 << (kCompactShift - 5)));
+  int64_t running = 0;
+  for (int wb = w0; wb < wend; wb += kWordsPerPass) {
+    const int w = wb + tid;
+    uint32_t word = 0u;
+    if (w < wend) {
+      word = bm[w];
+      if (word) bm[w] = 0u;
+    }
+    // block exclusive prefix of the popcounts
+    const int pc = __popc(word);
+    int incl = pc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = uint32_t(incl);
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int q = 0; q < kEstThreads / 64; ++q) {
+      if (q < wave) base += int(wsum[q]);
+      total += int(wsum[q]);
+    }
+    int k = base + incl - pc;
+    while (word) {
+      const int bit = __ffs(word) - 1;
+      word &= word - 1u;
+      list[k++] = (uint32_t(w - w0) << 5) | uint32_t(bit);
+    }
+    __syncthreads();
+    for (int q = tid; q < total; q += kEstThreads) {
+      const int64_t rank = rank0 + running + q;
+      if (rank < cap) {
+        const unsigned long long flat =
+            ((unsigned long long)c << kCompactShift) | (unsigned long long)list[q];
+        write_record(p, d, rel, f, T, flat, out0 + rank);
+      }
+    }
+    running += total;
+    __syncthreads();
+  }
+}
+
+int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(estimate_kernel, dim3(unsigned(max_cchunks), unsigned(nframes)), dim3(kEstThreads), 0,
+                     static_cast<hipStream_t>(stream), p, T);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-frame comparator: Algorithm 1 taken literally for one frame and one
+// round at a time. plain_fold gathers the permuted samples (Def. 1, tau = 0),
+// applies both windows and aliases (Def. 2): one wave per bucket b sums
+// z[b + B l] = wbar[n] w[[sigma n]] r[[sigma n]] over the L terms, n_d =
+// b_d + B_d l_d. Buckets are written in the paper's indexing (no relabel).
+// plain_vote evaluates abar_i = sum_s c_s[M(i, sigma_s)] for every cell.
+// ---------------------------------------------------------------------------
+
+constexpr int kPlainThreads = 256;
+
+template <bool C128>
+__global__ __launch_bounds__(kPlainThreads) void plain_fold_kernel(DevPtrs p, const void* __restrict__ input,
+                                                                   int64_t f, int s) {
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (kPlainThreads / 64) + (threadIdx.x >> 6);
+  if (b >= d.B) return;
+  const int64_t in_base = d.in_off + rel * d.in_stride;
+  const int64_t L = int64_t(1) << d.Lshift;
+  float accr = 0.f, acci = 0.f;
+  for (int64_t l = lane; l < L; l += 64) {
+    unsigned long long src = 0ull;
+    float wr = 1.f, wi = 0.f;
+    for (int dd = 0; dd < d.ndim; ++dd) {
+      const uint32_t bd = uint32_t(b >> d.bshift[dd]) & uint32_t(d.b[dd] - 1);
+      const uint32_t ld = uint32_t(l >> d.tshift[dd]) & uint32_t(d.l[dd] - 1);
+      const uint32_t nd = bd + uint32_t(d.b[dd]) * ld;
+      const uint32_t md = (uint32_t(d.sigma[s][dd]) * nd) & uint32_t(d.n[dd] - 1);
+      const float w = p.win[d.win_off[dd] + md];
+      const float2 fb = p.flat[d.flat_off[dd] + nd];
+      const float tr = wr * fb.x - wi * fb.y;
+      const float ti = wr * fb.y + wi * fb.x;
+      wr = tr * w;
+      wi = ti * w;
+      src |= (unsigned long long)md << d.nshift[dd];
+    }
+    float xr, xi;
+    if constexpr (C128) {
+      const double2 v = static_cast<const double2*>(input)[in_base + int64_t(src)];
+      xr = float(v.x);
+      xi = float(v.y);
+    } else {
+      const float2 v = static_cast<const float2*>(input)[in_base + int64_t(src)];
+      xr = v.x;
+      xi = v.y;
+    }
+    accr = fmaf(wr, xr, fmaf(-wi, xi, accr));
+    acci = fmaf(wr, xi, fmaf(wi, xr, acci));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    accr += __shfl_down(accr, off);
+    acci += __shfl_down(acci, off);
+  }
+  if (lane == 0) {
+    float2* part = p.part + d.part_off + rel * d.part_stride;
+    part[int64_t(s) * d.B + b] = make_float2(accr, acci);
+  }
+}
+
+int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t frame, int round, int B,
+                      void* stream) {
+  const unsigned blocks = unsigned((B + kPlainThreads / 64 - 1) / (kPlainThreads / 64));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == RSFT_C128)
+    hipLaunchKernelGGL(plain_fold_kernel<true>, dim3(blocks), dim3(kPlainThreads), 0, st, p, input,
+                       frame, round);
+  else
+    hipLaunchKernelGGL(plain_fold_kernel<false>, dim3(blocks), dim3(kPlainThreads), 0, st, p, input,
+                       frame, round);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kPlainThreads) void plain_vote_kernel(DevPtrs p, int64_t f) {
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  const int64_t i = int64_t(blockIdx.x) * kPlainThreads + threadIdx.x;
+  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
+  bool hit = false;
+  if (i < d.N) {
+    int votes = 0;
+    for (int s = 0; s < d.T; ++s) {
+      uint32_t jf = 0u;
+      for (int dd = 0; dd < d.ndim; ++dd) {
+        const uint32_t cell = uint32_t(i >> d.nshift[dd]) & uint32_t(d.n[dd] - 1);
+        const uint32_t u = (uint32_t(d.sigma[s][dd]) * cell) & uint32_t(d.n[dd] - 1);
+        jf |= (u >> d.lshift[dd]) << d.bshift[dd];
+      }
+      votes += int((fl[int64_t(s) * d.words + (jf >> 5)] >> (jf & 31u)) & 1u);
+    }
+    hit = votes >= d.mu;
+  }
+  mark_cell(p, d, rel, f, hit, (unsigned long long)i);
+}
+
+int launch_plain_vote(const DevPtrs& p, int64_t frame, int64_t N, void* stream) {
+  const unsigned blocks = unsigned((N + kPlainThreads - 1) / kPlainThreads);
+  hipLaunchKernelGGL(plain_vote_kernel, dim3(blocks), dim3(kPlainThreads), 0,
+                     static_cast<hipStream_t>(stream), p, frame);
+  return hipGetLastError();
+}
+
+int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int maxB, int sum_tw, void* stream) {
+  return launch_dft_frame(p, frame, T, maxB, sum_tw, static_cast<hipStream_t>(stream));
+}
+
+}  // namespace rsft

@@ -1,0 +1,876 @@
+// Host side of the C ABI: plan construction (FP64 tables), launch
+// orchestration, optional hipGraph replay, result copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "design.h"
+#include "rsft.h"
+#include "rsft_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rsft_status fail(rsft_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(RSFT_ERROR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_TRY(expr)                                                           \
+  do {                                                                             \
+    int e_ = (expr);                                                               \
+    if (e_ != 0)                                                                   \
+      return fail(RSFT_ERROR_DEVICE, std::string(#expr) + ": " +                   \
+                                         hipGetErrorString(hipError_t(e_)));       \
+  } while (0)
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+
+struct DeviceBuffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct TimingSet {
+  hipEvent_t ev[RSFT_NUM_STAGES + 1] = {};  // stage boundaries
+  bool pending = false;
+};
+
+}  // namespace
+
+struct rsft_plan_s {
+  int device = 0;
+  bool uniform = true;
+  int64_t ndesc = 0;
+  int64_t max_frames = 0;      // frames one execute may process
+  int T = 0, mu = 0, dtype = 0;
+  std::vector<rsft::FrameDesc> descs;
+  std::vector<rsft_plan_info_t> info;
+  rsft::FoldConfig fold{256, 4};
+  int maxB = 0, max_words = 0, max_cchunks = 0, max_vote_chunks = 0, sum_tw_max = 0;
+  int64_t tiles_per_frame = 0;   // uniform plans
+  int64_t ntiles_uneven = 0;     // uneven plans
+  // device arrays
+  DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles;
+  DeviceBuffer d_part, d_buckets, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
+      d_offsets, d_records;
+  rsft::DevPtrs ptrs{};
+  // state of the last execute
+  int64_t last_batch = -1;
+  // graph replay
+  bool use_graph = true;
+  hipStream_t capture_stream = nullptr;
+  std::map<std::pair<const void*, int64_t>, hipGraphExec_t> graphs;
+  std::vector<std::pair<const void*, int64_t>> graph_order;
+  // stage timing
+  bool timing = false;
+  std::vector<TimingSet> timing_sets;
+  size_t timing_next = 0;
+  double stage_ms[RSFT_NUM_STAGES] = {0, 0, 0, 0};
+  int64_t timed = 0;
+};
+
+namespace {
+
+rsft_status validate(const rsft_params& p, int64_t idx) {
+  const std::string at = "frame descriptor " + std::to_string(idx) + ": ";
+  if (p.ndim < 1 || p.ndim > RSFT_MAX_DIMS) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "ndim must be 1..4");
+  if (p.rounds < 1 || p.rounds > RSFT_MAX_ROUNDS)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "rounds must be 1..32");
+  int64_t N = 1, B = 1;
+  for (int d = 0; d < p.ndim; ++d) {
+    if (!is_pow2(p.n[d]) || !is_pow2(p.b[d]))
+      return fail(RSFT_ERROR_NOT_POW2, at + "N_d and B_d must be powers of two");
+    if (p.b[d] >= p.n[d]) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "need B_d < N_d");
+    if (p.n[d] > (int64_t(1) << 30)) return fail(RSFT_ERROR_UNSUPPORTED, at + "N_d > 2^30");
+    if (p.b[d] > 128) return fail(RSFT_ERROR_UNSUPPORTED, at + "B_d > 128 per dimension");
+    N *= p.n[d];
+    B *= p.b[d];
+  }
+  if (N >= (int64_t(1) << 40)) return fail(RSFT_ERROR_UNSUPPORTED, at + "N >= 2^40");
+  if (B > rsft::kMaxBuckets) return fail(RSFT_ERROR_UNSUPPORTED, at + "B > 16384 buckets");
+  if ((N / B) > (int64_t(1) << 30)) return fail(RSFT_ERROR_UNSUPPORTED, at + "N / B > 2^30");
+  if (!(p.pfa > 0.0 && p.pfa < 1.0)) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "pfa must be in (0, 1)");
+  if (p.mu < 0 || p.mu > p.rounds) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "mu must be 0..T");
+  if (p.noise_mode != RSFT_NOISE_KNOWN && p.noise_mode != RSFT_NOISE_ESTIMATED)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "unknown noise_mode");
+  if (p.noise_mode == RSFT_NOISE_KNOWN && !(p.noise_var > 0.0))
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "noise_var must be > 0");
+  if (p.dtype != RSFT_C64 && p.dtype != RSFT_C128) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "unknown dtype");
+  if (p.window_atten_db < 0.0 || !std::isfinite(p.window_atten_db))
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "window_atten_db must be >= 0");
+  if (!std::isfinite(p.flat_atten_db)) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "flat_atten_db not finite");
+  if (p.max_detections < 0 || p.max_detections > rsft::kMaxDetectionsPerFrame)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "max_detections must be 0..2^24");
+  if (p.max_batch < 0) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "max_batch must be >= 0");
+  if (p.sigma) {
+    for (int s = 0; s < p.rounds; ++s)
+      for (int d = 0; d < p.ndim; ++d) {
+        const int64_t v = p.sigma[s * p.ndim + d];
+        if (v < 1 || v >= p.n[d] || (v & 1) == 0)
+          return fail(RSFT_ERROR_BAD_SIGMA, at + "sigma must be odd and in [1, N_d)");
+      }
+  }
+  return RSFT_OK;
+}
+
+template <typename T>
+rsft_status upload(DeviceBuffer& buf, const std::vector<T>& host) {
+  buf.bytes = std::max<size_t>(host.size() * sizeof(T), 16);
+  HIP_TRY(hipMalloc(&buf.ptr, buf.bytes));
+  if (!host.empty()) HIP_TRY(hipMemcpy(buf.ptr, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+  return RSFT_OK;
+}
+
+rsft_status alloc(DeviceBuffer& buf, size_t bytes) {
+  buf.bytes = std::max<size_t>(bytes, 16);
+  const hipError_t e = hipMalloc(&buf.ptr, buf.bytes);
+  if (e == hipErrorOutOfMemory) return fail(RSFT_ERROR_OUT_OF_MEMORY, "device allocation failed");
+  if (e != hipSuccess) return fail(RSFT_ERROR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return RSFT_OK;
+}
+
+void release(DeviceBuffer& buf) {
+  if (buf.ptr) (void)hipFree(buf.ptr);
+  buf.ptr = nullptr;
+  buf.bytes = 0;
+}
+
+// Host tables of one descriptor, appended to the plan-wide arrays.
+struct HostTables {
+  std::vector<float2> wrow, wcol, tw, flat;
+  std::vector<int32_t> rowlist;
+  std::vector<double> gains;
+  std::vector<float> win;
+};
+
+// Rounds feeding magnitude estimates: a round is clean when no dimension d
+// and k in {1, 2} has |[sigma_{s,d} k]_{N_d}| (circular) < L_d + 2, i.e. the
+// main-lobe bins of one tone never share a bucket; all clean rounds are used,
+// else the one whose worst distance is largest (first on ties).
+int estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma) {
+  std::vector<int64_t> score(static_cast<size_t>(p.rounds));
+  int mask = 0;
+  for (int s = 0; s < p.rounds; ++s) {
+    int64_t worst = INT64_MAX;
+    for (int d = 0; d < p.ndim; ++d) {
+      const int64_t n = p.n[d], L = p.n[d] / p.b[d];
+      for (int k = 1; k <= 2; ++k) {
+        const int64_t u = (sigma[size_t(s * p.ndim + d)] * k) % n;
+        const int64_t dist = std::min(u, n - u) - (L + 2);
+        worst = std::min(worst, dist);
+      }
+    }
+    score[size_t(s)] = worst;
+    if (worst >= 0) mask |= 1 << s;
+  }
+  if (mask) return mask;
+  int best = 0;
+  for (int s = 1; s < p.rounds; ++s)
+    if (score[size_t(s)] > score[size_t(best)]) best = s;
+  return 1 << best;
+}
+
+rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan_info_t& info,
+                             HostTables& ht, int fold_p) {
+  std::memset(&d, 0, sizeof(d));
+  std::memset(&info, 0, sizeof(info));
+  const int D = p.ndim, T = p.rounds;
+  const int mu = p.mu == 0 ? T : p.mu;
+  d.ndim = D;
+  d.T = T;
+  d.mu = mu;
+  d.noise_mode = p.noise_mode;
+  int64_t N = 1, B = 1;
+  for (int k = 0; k < D; ++k) {
+    d.n[k] = int32_t(p.n[k]);
+    d.b[k] = int32_t(p.b[k]);
+    d.l[k] = int32_t(p.n[k] / p.b[k]);
+    d.lshift[k] = ilog2(d.l[k]);
+    N *= p.n[k];
+    B *= p.b[k];
+  }
+  for (int k = 0; k < D; ++k) {
+    int ns = 0, bs = 0, ts = 0;
+    for (int e = k + 1; e < D; ++e) {
+      ns += ilog2(p.n[e]);
+      bs += ilog2(p.b[e]);
+      ts += ilog2(p.n[e] / p.b[e]);
+    }
+    d.nshift[k] = ns;
+    d.bshift[k] = bs;
+    d.tshift[k] = ts;
+  }
+  d.N = N;
+  d.B = int32_t(B);
+  d.Lshift = ilog2(N / B);
+  d.words = int32_t((B + 31) / 32);
+  d.cap = p.max_detections == 0 ? rsft::kDefaultDetections : p.max_detections;
+
+  // permutation factors
+  std::vector<int64_t> sigma(static_cast<size_t>(T * D));
+  for (int s = 0; s < T; ++s)
+    for (int k = 0; k < D; ++k)
+      sigma[size_t(s * D + k)] = p.sigma ? p.sigma[s * D + k] : rsft::draw_sigma(p.seed, s * D + k, p.n[k]);
+  std::vector<int64_t> sigma_inv(sigma.size());
+  for (int s = 0; s < T; ++s)
+    for (int k = 0; k < D; ++k) {
+      int64_t inv = 0;
+      if (!rsft::mod_inverse(sigma[size_t(s * D + k)], p.n[k], &inv))
+        return fail(RSFT_ERROR_BAD_SIGMA, "sigma not invertible");
+      sigma_inv[size_t(s * D + k)] = inv;
+      d.sigma[s][k] = int32_t(sigma[size_t(s * D + k)]);
+      d.sigma_inv[s][k] = int32_t(inv);
+      d.tau[s][k] = int32_t(inv % p.b[k]);
+    }
+  d.est_mask = estimation_mask(p, sigma);
+
+  // windows (Sec. III-C.1, Sec. IV-B) per dimension, FP64
+  const double flat_db = p.flat_atten_db < 0.0 ? p.window_atten_db : p.flat_atten_db;
+  std::vector<std::vector<double>> w(static_cast<size_t>(D));
+  std::vector<std::vector<std::complex<double>>> wbar(static_cast<size_t>(D));
+  double eta = 1.0;
+  for (int k = 0; k < D; ++k) {
+    w[size_t(k)] = rsft::chebyshev_window(p.n[k], p.window_atten_db);
+    wbar[size_t(k)] = rsft::flat_window(p.n[k], p.b[k], flat_db);
+    eta *= rsft::six_db_width(w[size_t(k)]);
+  }
+  // permuted weights W_{s,d}[m] = w_d[m] wbar_d[[sigma^{-1} m]_{N_d}]
+  std::vector<std::vector<std::complex<double>>> W(static_cast<size_t>(T * D));
+  for (int s = 0; s < T; ++s)
+    for (int k = 0; k < D; ++k) {
+      auto& v = W[size_t(s * D + k)];
+      v.resize(size_t(p.n[k]));
+      const int64_t inv = sigma_inv[size_t(s * D + k)];
+      for (int64_t m = 0; m < p.n[k]; ++m)
+        v[size_t(m)] = w[size_t(k)][size_t(m)] * wbar[size_t(k)][size_t((inv * m) % p.n[k])];
+    }
+  // beta(sigma_s) = ||Wbar P_sigma w||^2 (eq. alpha_beta), separable over dims
+  const double p1 = rsft::stage1_probability(p.pfa, T, mu);
+  d.log_inv_p1 = std::log(1.0 / p1);
+  for (int s = 0; s < T; ++s) {
+    double beta = 1.0;
+    for (int k = 0; k < D; ++k) {
+      long double acc = 0.0L;
+      const int64_t sg = sigma[size_t(s * D + k)];
+      for (int64_t n = 0; n < p.n[k]; ++n) {
+        const double a = std::norm(wbar[size_t(k)][size_t(n)]);
+        const double b = w[size_t(k)][size_t((sg * n) % p.n[k])];
+        acc += (long double)a * b * b;
+      }
+      beta *= double(acc);
+    }
+    info.beta[s] = beta;
+    d.gamma[s] = p.noise_var * beta * d.log_inv_p1;   // eq. tpd with Pfa~ = p1
+    info.gamma[s] = d.gamma[s];
+  }
+  {
+    const int64_t h = std::max<int64_t>(B / 2, 1);
+    long double H = 0.0L;
+    for (int64_t i = 0; i < h; ++i) H += 1.0L / (long double)(B - i);
+    d.renyi_h = double(H);
+  }
+
+  // fold view: rows = leading dims flattened, columns = last dim
+  const int64_t nl = p.n[D - 1], bl = p.b[D - 1];
+  const int64_t rows_total = N / nl;
+  const int64_t classes = B / bl;
+  const int64_t R = rows_total / classes;
+  d.n_last = int32_t(nl);
+  d.b_last = int32_t(bl);
+  d.rows_total = int32_t(rows_total);
+  d.classes = int32_t(classes);
+  d.rows_per_class = int32_t(R);
+  if (nl >= fold_p) {
+    int64_t k = 1;
+    const int64_t target = 32768;  // elements per tile
+    while (R * fold_p * k * 2 <= target && fold_p * k * 2 <= nl) k *= 2;
+    d.chunk_cols = int32_t(fold_p * k);
+  } else {
+    d.chunk_cols = int32_t(nl);
+  }
+  d.nchunks = int32_t(nl / d.chunk_cols);
+
+  d.wrow_off = int64_t(ht.wrow.size());
+  for (int s = 0; s < T; ++s)
+    for (int64_t r = 0; r < rows_total; ++r) {
+      std::complex<double> v(1.0, 0.0);
+      int64_t rem = r;
+      for (int k = D - 2; k >= 0; --k) {
+        const int64_t m = rem % p.n[k];
+        rem /= p.n[k];
+        v *= W[size_t(s * D + k)][size_t(m)];
+      }
+      ht.wrow.push_back(make_float2(float(v.real()), float(v.imag())));
+    }
+  d.wcol_off = int64_t(ht.wcol.size());
+  for (int s = 0; s < T; ++s)
+    for (int64_t c = 0; c < nl; ++c) {
+      const auto v = W[size_t(s * D + D - 1)][size_t(c)];
+      ht.wcol.push_back(make_float2(float(v.real()), float(v.imag())));
+    }
+  d.rowlist_off = int64_t(ht.rowlist.size());
+  for (int64_t cls = 0; cls < classes; ++cls) {
+    // class = row-major (c_0, ..., c_{D-2}) over B_0 x ... x B_{D-2}
+    int64_t c[RSFT_MAX_DIMS] = {0, 0, 0, 0};
+    int64_t rem = cls;
+    for (int k = D - 2; k >= 0; --k) {
+      c[k] = rem % p.b[k];
+      rem /= p.b[k];
+    }
+    for (int64_t li = 0; li < R; ++li) {
+      int64_t lrem = li, row = 0, stride = 1;
+      int64_t m[RSFT_MAX_DIMS] = {0, 0, 0, 0};
+      for (int k = D - 2; k >= 0; --k) {
+        const int64_t L = p.n[k] / p.b[k];
+        m[k] = c[k] + p.b[k] * (lrem % L);
+        lrem /= L;
+      }
+      for (int k = D - 2; k >= 0; --k) {
+        row += m[k] * stride;
+        stride *= p.n[k];
+      }
+      ht.rowlist.push_back(int32_t(row));
+    }
+  }
+  for (int k = 0; k < D; ++k) {
+    d.tw_off[k] = int64_t(ht.tw.size());
+    for (int64_t m = 0; m < p.b[k]; ++m) {
+      const double ang = -2.0 * M_PI * double(m) / double(p.b[k]);
+      ht.tw.push_back(make_float2(float(std::cos(ang)), float(std::sin(ang))));
+    }
+    d.gain_off[k] = int64_t(ht.gains.size());
+    const auto g = rsft::flat_gain(wbar[size_t(k)], p.n[k] / p.b[k]);
+    ht.gains.insert(ht.gains.end(), g.begin(), g.end());
+    d.win_off[k] = int64_t(ht.win.size());
+    for (int64_t m = 0; m < p.n[k]; ++m) ht.win.push_back(float(w[size_t(k)][size_t(m)]));
+    d.flat_off[k] = int64_t(ht.flat.size());
+    for (int64_t m = 0; m < p.n[k]; ++m)
+      ht.flat.push_back(make_float2(float(wbar[size_t(k)][size_t(m)].real()),
+                                    float(wbar[size_t(k)][size_t(m)].imag())));
+  }
+
+  info.ndim = D;
+  info.rounds = T;
+  info.mu = mu;
+  info.noise_mode = p.noise_mode;
+  for (int k = 0; k < D; ++k) {
+    info.n[k] = p.n[k];
+    info.b[k] = p.b[k];
+  }
+  for (int s = 0; s < T; ++s)
+    for (int k = 0; k < D; ++k) {
+      info.sigma[s][k] = sigma[size_t(s * D + k)];
+      info.sigma_inv[s][k] = sigma_inv[size_t(s * D + k)];
+      info.tau[s][k] = sigma_inv[size_t(s * D + k)] % p.b[k];
+    }
+  info.p1 = p1;
+  info.eta_m = eta;
+  info.max_sparsity = double(B) / eta;
+  info.estimation_rounds = d.est_mask;
+  return RSFT_OK;
+}
+
+void free_plan(rsft_plan_s* pl) {
+  for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+  pl->graphs.clear();
+  for (auto& ts : pl->timing_sets)
+    for (auto& e : ts.ev)
+      if (e) (void)hipEventDestroy(e);
+  if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
+  DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
+                          &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_part,
+                          &pl->d_buckets, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
+                          &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records};
+  for (auto* b : bufs) release(*b);
+  delete pl;
+}
+
+rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s* pl) {
+  pl->uniform = nframes == 1;
+  pl->ndesc = nframes;
+  pl->T = frames[0].rounds;
+  pl->mu = frames[0].mu == 0 ? frames[0].rounds : frames[0].mu;
+  pl->dtype = frames[0].dtype;
+  pl->max_frames = pl->uniform ? std::max<int64_t>(frames[0].max_batch, 1) : nframes;
+
+  // fold launch shape: P = threads * vec covers the largest B_{D-1}
+  int64_t max_bl = 1;
+  for (int64_t i = 0; i < nframes; ++i) max_bl = std::max<int64_t>(max_bl, frames[i].b[frames[i].ndim - 1]);
+  // each thread loads `vec` consecutive complex samples of one row, so rows
+  // must hold at least that many
+  int64_t min_nl = INT64_MAX;
+  for (int64_t i = 0; i < nframes; ++i) min_nl = std::min<int64_t>(min_nl, frames[i].n[frames[i].ndim - 1]);
+  pl->fold = rsft::FoldConfig{256, min_nl >= 4 ? 4 : 2};
+  while (int64_t(pl->fold.threads) * pl->fold.vec < max_bl) pl->fold.threads *= 2;
+  if (pl->fold.threads > 512) return fail(RSFT_ERROR_UNSUPPORTED, "last-dimension B too large");
+  const int fold_p = pl->fold.threads * pl->fold.vec;
+
+  HostTables ht;
+  pl->descs.resize(size_t(nframes));
+  pl->info.resize(size_t(nframes));
+  for (int64_t i = 0; i < nframes; ++i) {
+    rsft_status st = build_descriptor(frames[i], pl->descs[size_t(i)], pl->info[size_t(i)], ht, fold_p);
+    if (st != RSFT_OK) return st;
+  }
+
+  // workspace layout
+  int64_t in_off = 0, part_off = 0, bucket_off = 0, flag_off = 0, bitmap_off = 0, chunk_off = 0,
+          rec_total = 0;
+  for (int64_t i = 0; i < nframes; ++i) {
+    auto& d = pl->descs[size_t(i)];
+    const int64_t mult = pl->uniform ? pl->max_frames : 1;
+    d.in_off = in_off;
+    d.in_stride = d.N;
+    d.part_off = part_off;
+    d.part_stride = int64_t(d.nchunks) * d.T * d.B;
+    d.bucket_off = bucket_off;
+    d.bucket_stride = int64_t(d.T) * d.B;
+    d.flag_off = flag_off;
+    d.flag_stride = int64_t(d.T) * d.words;
+    d.bitmap_words = int32_t((d.N + 31) / 32);
+    d.cchunks = int32_t((d.N + (int64_t(1) << rsft::kCompactShift) - 1) >> rsft::kCompactShift);
+    d.bitmap_off = bitmap_off;
+    d.bitmap_stride = d.bitmap_words;
+    d.chunk_off = chunk_off;
+    d.chunk_stride = d.cchunks;
+    in_off += mult * d.in_stride;
+    part_off += mult * d.part_stride;
+    bucket_off += mult * d.bucket_stride;
+    flag_off += mult * d.flag_stride;
+    bitmap_off += mult * d.bitmap_stride;
+    chunk_off += mult * d.chunk_stride;
+    rec_total += mult * d.cap;
+    pl->maxB = std::max(pl->maxB, d.B);
+    pl->max_words = std::max(pl->max_words, d.words);
+    pl->max_cchunks = std::max(pl->max_cchunks, d.cchunks);
+    pl->max_vote_chunks = std::max(pl->max_vote_chunks, (d.B + 255) / 256);
+    int sum_tw = 0;
+    for (int k = 0; k < d.ndim; ++k) sum_tw += d.b[k];
+    pl->sum_tw_max = std::max(pl->sum_tw_max, sum_tw);
+  }
+  if (size_t(2 * pl->maxB) * 4 + size_t(pl->sum_tw_max) * 8 > 160 * 1024)
+    return fail(RSFT_ERROR_UNSUPPORTED, "buckets per frame exceed the DFT stage's LDS");
+
+  // fold tiles
+  std::vector<int32_t> tiles;
+  if (pl->uniform) {
+    pl->tiles_per_frame = int64_t(pl->descs[0].classes) * pl->descs[0].nchunks;
+  } else {
+    struct Tile { int64_t bytes; int32_t f, c, k; };
+    std::vector<Tile> tl;
+    for (int64_t i = 0; i < nframes; ++i) {
+      const auto& d = pl->descs[size_t(i)];
+      const int64_t bytes = int64_t(d.rows_per_class) * std::min<int64_t>(d.chunk_cols, d.n_last);
+      for (int c = 0; c < d.classes; ++c)
+        for (int k = 0; k < d.nchunks; ++k) tl.push_back({bytes, int32_t(i), c, k});
+    }
+    // largest tiles first: the hardware dispatcher then balances the tail
+    std::stable_sort(tl.begin(), tl.end(), [](const Tile& a, const Tile& b) { return a.bytes > b.bytes; });
+    for (const auto& t : tl) {
+      tiles.push_back(t.f);
+      tiles.push_back(t.c);
+      tiles.push_back(t.k);
+    }
+    pl->ntiles_uneven = int64_t(tl.size());
+  }
+
+  rsft_status st;
+  if ((st = upload(pl->d_descs, pl->descs)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_wrow, ht.wrow)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_wcol, ht.wcol)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_rowlist, ht.rowlist)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_tw, ht.tw)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_gains, ht.gains)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_win, ht.win)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_flat, ht.flat)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_tiles, tiles)) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_part, size_t(part_off) * sizeof(float2))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_buckets, size_t(bucket_off) * sizeof(float2))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_flags, size_t(flag_off) * sizeof(uint32_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_bitmap, size_t(bitmap_off) * sizeof(uint32_t))) != RSFT_OK) return st;
+  HIP_TRY(hipMemset(pl->d_bitmap.ptr, 0, pl->d_bitmap.bytes));  // kept clear by the compaction
+  if ((st = alloc(pl->d_chunk_counts, size_t(chunk_off) * sizeof(uint32_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_chunk_offsets, size_t(chunk_off) * sizeof(int64_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_counts, size_t(pl->max_frames) * sizeof(uint32_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_offsets, size_t(pl->max_frames + 1) * sizeof(int64_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_records, size_t(rec_total) * sizeof(rsft_detection))) != RSFT_OK) return st;
+  HIP_TRY(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
+
+  auto& q = pl->ptrs;
+  q.descs = static_cast<const rsft::FrameDesc*>(pl->d_descs.ptr);
+  q.uniform = pl->uniform ? 1 : 0;
+  q.wrow = static_cast<const float2*>(pl->d_wrow.ptr);
+  q.wcol = static_cast<const float2*>(pl->d_wcol.ptr);
+  q.rowlist = static_cast<const int32_t*>(pl->d_rowlist.ptr);
+  q.tw = static_cast<const float2*>(pl->d_tw.ptr);
+  q.gains = static_cast<const double*>(pl->d_gains.ptr);
+  q.win = static_cast<const float*>(pl->d_win.ptr);
+  q.flat = static_cast<const float2*>(pl->d_flat.ptr);
+  q.part = static_cast<float2*>(pl->d_part.ptr);
+  q.buckets = static_cast<float2*>(pl->d_buckets.ptr);
+  q.flags = static_cast<uint32_t*>(pl->d_flags.ptr);
+  q.bitmap = static_cast<uint32_t*>(pl->d_bitmap.ptr);
+  q.chunk_counts = static_cast<uint32_t*>(pl->d_chunk_counts.ptr);
+  q.chunk_offsets = static_cast<int64_t*>(pl->d_chunk_offsets.ptr);
+  q.counts = static_cast<uint32_t*>(pl->d_counts.ptr);
+  q.offsets = static_cast<int64_t*>(pl->d_offsets.ptr);
+  q.records = static_cast<rsft_detection*>(pl->d_records.ptr);
+  q.tiles = static_cast<const int32_t*>(pl->d_tiles.ptr);
+  return RSFT_OK;
+}
+
+rsft_status check_batch(rsft_plan_s* pl, const void* d_input, int64_t batch) {
+  if (batch < 0) return fail(RSFT_ERROR_INVALID_ARGUMENT, "batch must be >= 0");
+  if (pl->uniform) {
+    if (batch > pl->max_frames) return fail(RSFT_ERROR_INVALID_ARGUMENT, "batch exceeds max_batch of the plan");
+  } else if (batch != 0 && batch != pl->ndesc) {
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "an uneven plan executes exactly its frames");
+  }
+  if (batch > 0 && d_input == nullptr) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL input");
+  if (reinterpret_cast<uintptr_t>(d_input) % 16 != 0)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "input must be 16-byte aligned");
+  return RSFT_OK;
+}
+
+// The hot path, stage by stage; `ev` (optional) brackets the stages.
+rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStream_t st,
+                    hipEvent_t* ev) {
+  const auto& q = pl->ptrs;
+  if (ev) HIP_TRY(hipEventRecord(ev[0], st));
+  const int64_t ntiles = pl->uniform ? batch * pl->tiles_per_frame : pl->ntiles_uneven;
+  for (int r0 = 0; r0 < pl->T; r0 += rsft::kFoldRoundGroup) {
+    const int rounds = std::min(rsft::kFoldRoundGroup, pl->T - r0);
+    LAUNCH_TRY(rsft::launch_fold(q, d_input, pl->dtype, batch, pl->tiles_per_frame, ntiles, r0, rounds,
+                                 pl->T, pl->fold, st));
+  }
+  if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+  LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->maxB, pl->sum_tw_max, 0, 0, st));
+  if (ev) HIP_TRY(hipEventRecord(ev[2], st));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_vote_chunks, pl->max_words, st));
+  if (ev) HIP_TRY(hipEventRecord(ev[3], st));
+  LAUNCH_TRY(rsft::launch_scan(q, batch, st));
+  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, st));
+  if (ev) HIP_TRY(hipEventRecord(ev[4], st));
+  return RSFT_OK;
+}
+
+rsft_status drain_timing(rsft_plan_s* pl, TimingSet& ts) {
+  if (!ts.pending) return RSFT_OK;
+  HIP_TRY(hipEventSynchronize(ts.ev[RSFT_NUM_STAGES]));
+  for (int k = 0; k < RSFT_NUM_STAGES; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ts.ev[k], ts.ev[k + 1]));
+    pl->stage_ms[k] += ms;
+  }
+  pl->timed += 1;
+  ts.pending = false;
+  return RSFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rsft_status rsft_plan(const rsft_params* frames, int64_t nframes, rsft_plan_t* out) {
+  if (out) *out = nullptr;
+  if (!frames || !out || nframes < 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument or nframes < 1");
+  // argument errors are reported before any device call
+  for (int64_t i = 0; i < nframes; ++i) {
+    const rsft_status vs = validate(frames[i], i);
+    if (vs != RSFT_OK) return vs;
+    const int mu_i = frames[i].mu == 0 ? frames[i].rounds : frames[i].mu;
+    const int mu_0 = frames[0].mu == 0 ? frames[0].rounds : frames[0].mu;
+    if (frames[i].rounds != frames[0].rounds || mu_i != mu_0 || frames[i].dtype != frames[0].dtype)
+      return fail(RSFT_ERROR_INVALID_ARGUMENT, "rounds, mu and dtype must agree across frame descriptors");
+  }
+  auto* pl = new (std::nothrow) rsft_plan_s();
+  if (!pl) return fail(RSFT_ERROR_OUT_OF_MEMORY, "host allocation failed");
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    delete pl;
+    return fail(RSFT_ERROR_DEVICE, "no HIP device");
+  }
+  rsft_status st;
+  try {
+    st = create_plan(frames, nframes, pl);
+  } catch (const std::bad_alloc&) {
+    st = fail(RSFT_ERROR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    st = fail(RSFT_ERROR_INVALID_ARGUMENT, e.what());
+  }
+  if (st != RSFT_OK) {
+    free_plan(pl);
+    return st;
+  }
+  *out = pl;
+  return RSFT_OK;
+}
+
+rsft_status rsft_execute(rsft_plan_t pl, const void* d_input, int64_t batch, void* stream) {
+  if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
+  rsft_status st = check_batch(pl, d_input, batch);
+  if (st != RSFT_OK) return st;
+  hipStream_t user = static_cast<hipStream_t>(stream);
+  pl->last_batch = batch;
+  if (batch == 0) return RSFT_OK;
+  if (pl->timing) {
+    if (pl->timing_sets.empty()) {
+      pl->timing_sets.resize(64);
+      for (auto& ts : pl->timing_sets)
+        for (auto& e : ts.ev) HIP_TRY(hipEventCreate(&e));
+    }
+    TimingSet& ts = pl->timing_sets[pl->timing_next];
+    pl->timing_next = (pl->timing_next + 1) % pl->timing_sets.size();
+    if ((st = drain_timing(pl, ts)) != RSFT_OK) return st;
+    if ((st = enqueue(pl, d_input, batch, user, ts.ev)) != RSFT_OK) return st;
+    ts.pending = true;
+    return RSFT_OK;
+  }
+  if (!pl->use_graph) return enqueue(pl, d_input, batch, user, nullptr);
+  const auto key = std::make_pair(d_input, batch);
+  auto it = pl->graphs.find(key);
+  if (it == pl->graphs.end()) {
+    if (pl->graphs.size() >= 4) {
+      const auto old = pl->graph_order.front();
+      pl->graph_order.erase(pl->graph_order.begin());
+      (void)hipGraphExecDestroy(pl->graphs[old]);
+      pl->graphs.erase(old);
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(pl->capture_stream, hipStreamCaptureModeThreadLocal));
+    st = enqueue(pl, d_input, batch, pl->capture_stream, nullptr);
+    hipError_t e = hipStreamEndCapture(pl->capture_stream, &graph);
+    if (st != RSFT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(RSFT_ERROR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(RSFT_ERROR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    it = pl->graphs.emplace(key, exec).first;
+    pl->graph_order.push_back(key);
+  }
+  HIP_TRY(hipGraphLaunch(it->second, user));
+  return RSFT_OK;
+}
+
+rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t batch, void* stream) {
+  if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
+  rsft_status st = check_batch(pl, d_input, batch);
+  if (st != RSFT_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  pl->last_batch = batch;
+  const auto& q = pl->ptrs;
+  for (int64_t f = 0; f < batch; ++f) {
+    const auto& d = pl->descs[size_t(pl->uniform ? 0 : f)];
+    for (int r = 0; r < pl->T; ++r) LAUNCH_TRY(rsft::launch_plain_fold(q, d_input, pl->dtype, f, r, d.B, s));
+    LAUNCH_TRY(rsft::launch_plain_dft(q, f, pl->T, pl->maxB, pl->sum_tw_max, s));
+    LAUNCH_TRY(rsft::launch_plain_vote(q, f, d.N, s));
+  }
+  if (batch > 0) {
+    LAUNCH_TRY(rsft::launch_scan(q, batch, s));
+    LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, s));
+  }
+  return RSFT_OK;
+}
+
+rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* stream) {
+  if (!pl || !d_flags) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  if (pl->last_batch < 0) return fail(RSFT_ERROR_NOT_READY, "no execute yet");
+  const int64_t batch = pl->last_batch;
+  if (batch == 0) return RSFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  size_t words = 0;
+  for (int64_t f = 0; f < batch; ++f) words += size_t(pl->descs[size_t(pl->uniform ? 0 : f)].flag_stride);
+  HIP_TRY(hipMemcpyAsync(pl->d_flags.ptr, d_flags, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  const auto& q = pl->ptrs;
+  LAUNCH_TRY(rsft::launch_zero_counts(q, batch, s));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_vote_chunks, pl->max_words, s));
+  LAUNCH_TRY(rsft::launch_scan(q, batch, s));
+  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, s));
+  return RSFT_OK;
+}
+
+rsft_status rsft_detection_count(rsft_plan_t pl, void* stream, int64_t* total) {
+  if (!pl || !total) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  if (pl->last_batch < 0) return fail(RSFT_ERROR_NOT_READY, "no execute yet");
+  const int64_t batch = pl->last_batch;
+  *total = 0;
+  if (batch == 0) return RSFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<uint32_t> counts(static_cast<size_t>(batch));
+  HIP_TRY(hipMemcpy(counts.data(), pl->d_counts.ptr, counts.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  for (auto c : counts) *total += c;
+  return RSFT_OK;
+}
+
+rsft_status rsft_detect(rsft_plan_t pl, void* stream, rsft_detection* h_out, int64_t capacity,
+                        int64_t* h_counts, int64_t* n_written) {
+  if (n_written) *n_written = 0;
+  if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (capacity < 0 || (capacity > 0 && !h_out)) return fail(RSFT_ERROR_INVALID_ARGUMENT, "bad output buffer");
+  if (pl->last_batch < 0) return fail(RSFT_ERROR_NOT_READY, "no execute yet");
+  const int64_t batch = pl->last_batch;
+  if (batch == 0) return RSFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<uint32_t> counts(static_cast<size_t>(batch));
+  std::vector<int64_t> offsets(static_cast<size_t>(batch + 1));
+  HIP_TRY(hipMemcpy(counts.data(), pl->d_counts.ptr, counts.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(offsets.data(), pl->d_offsets.ptr, offsets.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  bool truncated = false;
+  for (int64_t f = 0; f < batch; ++f) {
+    if (h_counts) h_counts[f] = counts[size_t(f)];
+    if (counts[size_t(f)] > uint32_t(pl->descs[size_t(pl->uniform ? 0 : f)].cap)) truncated = true;
+  }
+  const int64_t stored = offsets[size_t(batch)];
+  const int64_t ncopy = std::min(stored, capacity);
+  if (ncopy > 0)
+    HIP_TRY(hipMemcpy(h_out, pl->d_records.ptr, size_t(ncopy) * sizeof(rsft_detection), hipMemcpyDeviceToHost));
+  if (n_written) *n_written = std::max<int64_t>(ncopy, 0);
+  if (ncopy < stored) truncated = true;
+  if (truncated) return fail(RSFT_ERROR_CAPACITY, "detection records truncated; counts are exact");
+  return RSFT_OK;
+}
+
+rsft_status rsft_get_buckets(rsft_plan_t pl, void* d_out, void* stream) {
+  if (!pl || !d_out) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  if (pl->last_batch < 0) return fail(RSFT_ERROR_NOT_READY, "no execute yet");
+  size_t n = 0;
+  for (int64_t f = 0; f < pl->last_batch; ++f) n += size_t(pl->descs[size_t(pl->uniform ? 0 : f)].bucket_stride);
+  if (n) HIP_TRY(hipMemcpyAsync(d_out, pl->d_buckets.ptr, n * sizeof(float2), hipMemcpyDeviceToDevice,
+                               static_cast<hipStream_t>(stream)));
+  return RSFT_OK;
+}
+
+rsft_status rsft_get_flags(rsft_plan_t pl, uint32_t* d_out, void* stream) {
+  if (!pl || !d_out) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  if (pl->last_batch < 0) return fail(RSFT_ERROR_NOT_READY, "no execute yet");
+  size_t n = 0;
+  for (int64_t f = 0; f < pl->last_batch; ++f) n += size_t(pl->descs[size_t(pl->uniform ? 0 : f)].flag_stride);
+  if (n) HIP_TRY(hipMemcpyAsync(d_out, pl->d_flags.ptr, n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                               static_cast<hipStream_t>(stream)));
+  return RSFT_OK;
+}
+
+rsft_status rsft_plan_info(rsft_plan_t pl, int64_t frame, rsft_plan_info_t* out) {
+  if (!pl || !out) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  if (frame < 0 || frame >= pl->ndesc) return fail(RSFT_ERROR_INVALID_ARGUMENT, "frame out of range");
+  *out = pl->info[size_t(frame)];
+  return RSFT_OK;
+}
+
+rsft_status rsft_set_option(rsft_plan_t pl, int32_t option, int64_t value) {
+  if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
+  switch (option) {
+    case RSFT_OPT_GRAPH: pl->use_graph = value != 0; return RSFT_OK;
+    case RSFT_OPT_TIMING: pl->timing = value != 0; return RSFT_OK;
+    default: return fail(RSFT_ERROR_INVALID_ARGUMENT, "unknown option");
+  }
+}
+
+rsft_status rsft_stage_times(rsft_plan_t pl, double* avg_ms, int64_t* count, int32_t reset) {
+  if (!pl || !avg_ms) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  for (auto& ts : pl->timing_sets) {
+    rsft_status st = drain_timing(pl, ts);
+    if (st != RSFT_OK) return st;
+  }
+  for (int k = 0; k < RSFT_NUM_STAGES; ++k) avg_ms[k] = pl->timed ? pl->stage_ms[k] / double(pl->timed) : 0.0;
+  if (count) *count = pl->timed;
+  if (reset) {
+    for (double& v : pl->stage_ms) v = 0.0;
+    pl->timed = 0;
+  }
+  return RSFT_OK;
+}
+
+void rsft_destroy(rsft_plan_t pl) {
+  if (!pl) return;
+  (void)hipDeviceSynchronize();
+  free_plan(pl);
+}
+
+const char* rsft_status_string(rsft_status s) {
+  switch (s) {
+    case RSFT_OK: return "RSFT_OK";
+    case RSFT_ERROR_INVALID_ARGUMENT: return "RSFT_ERROR_INVALID_ARGUMENT";
+    case RSFT_ERROR_NOT_POW2: return "RSFT_ERROR_NOT_POW2";
+    case RSFT_ERROR_BAD_SIGMA: return "RSFT_ERROR_BAD_SIGMA";
+    case RSFT_ERROR_UNSUPPORTED: return "RSFT_ERROR_UNSUPPORTED";
+    case RSFT_ERROR_OUT_OF_MEMORY: return "RSFT_ERROR_OUT_OF_MEMORY";
+    case RSFT_ERROR_DEVICE: return "RSFT_ERROR_DEVICE";
+    case RSFT_ERROR_CAPACITY: return "RSFT_ERROR_CAPACITY";
+    case RSFT_ERROR_NOT_READY: return "RSFT_ERROR_NOT_READY";
+  }
+  return "unknown rsft_status";
+}
+
+const char* rsft_last_error(void) { return g_last_error.c_str(); }
+
+// ---- host-only design functions ----
+
+rsft_status rsft_chebyshev_window(int64_t n, double atten_db, int32_t periodic, double* out) {
+  if (n < 1 || !out || !(atten_db >= 0.0)) return fail(RSFT_ERROR_INVALID_ARGUMENT, "bad window arguments");
+  const auto w = periodic ? rsft::chebyshev_window_periodic(n, atten_db) : rsft::chebyshev_window(n, atten_db);
+  std::copy(w.begin(), w.end(), out);
+  return RSFT_OK;
+}
+
+rsft_status rsft_flat_window(int64_t n, int64_t b, double atten_db, double* out) {
+  if (!out || !is_pow2(n) || !is_pow2(b) || b > n || !(atten_db >= 0.0))
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "bad flat window arguments");
+  const auto w = rsft::flat_window(n, b, atten_db);
+  for (int64_t m = 0; m < n; ++m) {
+    out[2 * m] = w[size_t(m)].real();
+    out[2 * m + 1] = w[size_t(m)].imag();
+  }
+  return RSFT_OK;
+}
+
+rsft_status rsft_mod_inverse(int64_t sigma, int64_t n, int64_t* out) {
+  if (!out || n < 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, "bad arguments");
+  if (!rsft::mod_inverse(sigma, n, out)) return fail(RSFT_ERROR_BAD_SIGMA, "sigma not invertible modulo n");
+  return RSFT_OK;
+}
+
+rsft_status rsft_stage1_probability(double pfa, int32_t rounds, int32_t mu, double* out) {
+  if (!out || !(pfa > 0.0 && pfa < 1.0) || rounds < 1 || mu < 1 || mu > rounds)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "bad arguments");
+  *out = rsft::stage1_probability(pfa, rounds, mu);
+  return RSFT_OK;
+}
+
+rsft_status rsft_draw_sigma(uint64_t seed, int32_t rounds, int32_t ndim, const int64_t* n, int64_t* out) {
+  if (!n || !out || rounds < 1 || ndim < 1 || ndim > RSFT_MAX_DIMS) return fail(RSFT_ERROR_INVALID_ARGUMENT, "bad arguments");
+  for (int d = 0; d < ndim; ++d)
+    if (!is_pow2(n[d]) || n[d] < 2) return fail(RSFT_ERROR_NOT_POW2, "N_d must be a power of two >= 2");
+  for (int s = 0; s < rounds; ++s)
+    for (int d = 0; d < ndim; ++d) out[s * ndim + d] = rsft::draw_sigma(seed, s * ndim + d, n[d]);
+  return RSFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include "rsft.h"
+
+namespace rsft {
+
+constexpr int kMaxDims = RSFT_MAX_DIMS;
+constexpr int kMaxRounds = RSFT_MAX_ROUNDS;
+constexpr int kMaxBuckets = 16384;        // B per frame (DFT stage keeps a frame's round in LDS)
+constexpr int kMaxLastBuckets = 4096;     // B_{D-1} (fold stage residue slots per pass)
+constexpr int kMaxDetectionsPerFrame = 1 << 24;
+constexpr int kDefaultDetections = 16384;
+constexpr int kCompactShift = 15;         // cells per compaction chunk = 2^15
+constexpr int kFoldRoundGroup = 4;        // rounds folded per pass over the input
+
+// Everything a kernel needs to know about one frame descriptor. Lives in
+// device memory (one per descriptor); POD so host and device share it.
+struct FrameDesc {
+  int32_t ndim, T, mu, noise_mode;
+  int32_t n[kMaxDims];        // N_d
+  int32_t b[kMaxDims];        // B_d
+  int32_t l[kMaxDims];        // L_d = N_d / B_d
+  int32_t lshift[kMaxDims];   // log2 L_d
+  int32_t nshift[kMaxDims];   // sum_{e>d} log2 N_e  (row-major cell strides)
+  int32_t bshift[kMaxDims];   // sum_{e>d} log2 B_e  (row-major bucket strides)
+  int32_t tshift[kMaxDims];   // sum_{e>d} log2 L_e  (offset inside a bucket's preimage)
+  int64_t N;                  // prod N_d
+  int32_t B;                  // prod B_d
+  int32_t Lshift;             // log2(N / B)
+  // fold view: rows = flattened leading dims, columns = last dim
+  int32_t n_last, b_last, rows_total, classes, rows_per_class;
+  int32_t chunk_cols, nchunks;
+  int32_t words;              // flag words per round = ceil(B / 32)
+  int32_t cap;                // detection capacity of a frame
+  int32_t est_mask;           // rounds used for magnitude estimates
+  int32_t sigma[kMaxRounds][kMaxDims];
+  int32_t sigma_inv[kMaxRounds][kMaxDims];
+  int32_t tau[kMaxRounds][kMaxDims];      // sigma_inv mod B_d
+  double gamma[kMaxRounds];               // KNOWN-mode thresholds
+  double log_inv_p1;                      // ln(1 / p1)
+  double renyi_h;                         // sum_{i<B/2} 1/(B-i)
+  // offsets into the plan's table arrays
+  int64_t wrow_off;       // float2 [T][rows_total]
+  int64_t wcol_off;       // float2 [T][n_last]
+  int64_t rowlist_off;    // int32  [rows_total], grouped by residue class
+  int64_t tw_off[kMaxDims];    // float2 [B_d]: exp(-2 pi i m / B_d)
+  int64_t gain_off[kMaxDims];  // double [L_d]: flat-window response / N_d
+  int64_t win_off[kMaxDims];   // float  [N_d]: pre-permutation window (per-frame path)
+  int64_t flat_off[kMaxDims];  // float2 [N_d]: flat window (per-frame path)
+  // workspace offsets of the descriptor's first frame, and per-frame strides
+  // (uniform plans: frame f of the batch uses off + f * stride)
+  int64_t in_off, in_stride;           // input elements
+  int64_t part_off, part_stride;       // float2: [nchunks][T][B]
+  int64_t bucket_off, bucket_stride;   // float2: [T][B]
+  int64_t flag_off, flag_stride;       // uint32: [T][words]
+  int64_t bitmap_off, bitmap_stride;   // uint32: [ceil(N / 32)] detected-cell bits
+  int64_t chunk_off, chunk_stride;     // uint32 counts / int64 ranks: [cchunks]
+  int32_t cchunks;                     // compaction chunks = ceil(N / 2^15)
+  int32_t bitmap_words;                // ceil(N / 32)
+};
+
+// Device-side view of a launch: pointers into the plan's arrays.
+struct DevPtrs {
+  const FrameDesc* descs;
+  int uniform;                 // 1: one descriptor for every frame
+  const float2* wrow;
+  const float2* wcol;
+  const int32_t* rowlist;
+  const float2* tw;
+  const double* gains;
+  const float* win;
+  const float2* flat;
+  float2* part;
+  float2* buckets;
+  uint32_t* flags;
+  uint32_t* bitmap;            // detected cells, cleared again by the compaction
+  uint32_t* chunk_counts;      // detections per compaction chunk
+  int64_t* chunk_offsets;      // rank of a chunk's first detection within its frame
+  uint32_t* counts;            // [frames]
+  int64_t* offsets;            // [frames + 1]
+  rsft_detection* records;
+  const int32_t* tiles;        // uneven plans: [ntiles][3] (frame, class, chunk)
+};
+
+// Launch configuration of the fold stage, chosen per plan.
+struct FoldConfig {
+  int threads;   // work-group size
+  int vec;       // complex elements per thread per row
+};
+
+// Launchers (kernels.hip). All enqueue on `stream` and return hipError_t.
+int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
+                int64_t tiles_per_frame, int64_t ntiles, int round0, int rounds,
+                int T, const FoldConfig& cfg, void* stream);
+int launch_dft(const DevPtrs& p, int64_t nframes, int T, int maxB, int sum_tw,
+               int identity_relabel, int nchunks_override, void* stream);
+int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_chunks,
+                int max_words, void* stream);
+int launch_scan(const DevPtrs& p, int64_t nframes, void* stream);
+int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, void* stream);
+int launch_zero_counts(const DevPtrs& p, int64_t nframes, void* stream);
+// Per-frame comparator path.
+int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t frame,
+                      int round, int B, void* stream);
+int launch_plain_vote(const DevPtrs& p, int64_t frame, int64_t N, void* stream);
+int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int maxB, int sum_tw, void* stream);
+
+}  // namespace rsft

@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs, element by element.
+
+Contract (FP32 path vs FP64 oracle):
+* buckets fhat_s (eq. f): max |gpu - oracle| <= 1e-4 * rms of the round;
+* first-stage flags: a flag may differ only where |P - gamma| / gamma <= 1e-3
+  (an FP32 rounding of |fhat|^2 can cross the threshold only there);
+* detections and votes: identical except on cells whose T buckets include
+  such an ambiguous bucket; with the oracle's flags injected, identical bit
+  for bit;
+* estimates of matched detections: magnitude within 1e-3 relative, off-grid
+  frequency within 1e-3 bin.
+"""
+
+import zlib
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import rsft as OR
+
+from helpers import (BUCKET_RTOL, ambiguous, bucket_errors, cells_from_records,
+                     free_cells, make_input, oracle_plan, pack_flags, unpack_flags)
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _seed(name):
+    return zlib.crc32(name.encode())
+
+
+def _plan(**kw):
+    from paper_1610_01050_amd import Plan
+    return Plan(**kw)
+
+
+CASES = {
+    # name: (shape, buckets, rounds, mu, dtype, batch, K, pfa, atten)
+    "c1_256x256_c128": ((256, 256), (16, 16), 3, 0, "c128", 3, 4, 1e-3, 60.0),
+    "c2_1024x1024": ((1024, 1024), (64, 64), 3, 0, "c64", 2, 20, 1e-4, 60.0),
+    "c3_cube_256x128x32": ((256, 128, 32), (32, 16, 8), 3, 0, "c64", 2, 6, 1e-4, 60.0),
+    "one_dim_4096": ((4096,), (64,), 3, 0, "c64", 3, 3, 1e-3, 60.0),
+    "four_dim": ((16, 8, 16, 32), (4, 2, 4, 8), 3, 0, "c64", 2, 3, 1e-3, 60.0),
+    "short_rows_512x64": ((512, 64), (32, 8), 3, 0, "c64", 2, 5, 1e-3, 60.0),
+    "tiny_last_bucket": ((128, 256), (32, 2), 3, 0, "c64", 2, 3, 1e-3, 60.0),
+    "wide_rows_multichunk": ((16, 65536), (8, 128), 3, 0, "c64", 1, 1, 1e-3, 60.0),
+    "single_round": ((256, 512), (16, 32), 1, 1, "c64", 2, 5, 1e-3, 60.0),
+    "five_rounds_mu3": ((256, 256), (16, 16), 5, 3, "c64", 2, 5, 1e-3, 60.0),
+    "rectangular_windows": ((256, 256), (16, 16), 3, 0, "c64", 2, 5, 1e-3, 0.0),
+    "forty_db": ((1024, 256), (32, 16), 3, 0, "c64", 2, 8, 1e-3, 40.0),
+}
+
+
+def _run_case(name, per_frame=False, noise="known"):
+    shape, buckets, T, mu, dtype, batch, K, pfa, atten = CASES[name]
+    print(f"case {name} per_frame={per_frame} noise={noise}", flush=True)
+    npdt = np.complex128 if dtype == "c128" else np.complex64
+    frames = []
+    freqs = []
+    for f in range(batch):
+        x, fr = make_input(shape, K, seed=_seed(name) % 100000 + f, dtype=npdt)
+        frames.append(x)
+        freqs.append(fr)
+    sigma = synth.draw_sigma(np.random.default_rng(_seed(name) % 7919), T, shape)
+    flat = 0.0 if atten == 0.0 else -1.0
+    plan = _plan(shape=shape, buckets=buckets, rounds=T, sigma=sigma, window_atten_db=atten,
+                 flat_atten_db=flat, pfa=pfa, mu=mu, dtype=dtype, max_batch=batch,
+                 noise_mode=noise, max_detections=1 << 18)
+    xd = torch.from_numpy(np.stack(frames)).to("cuda")
+    if per_frame:
+        plan.execute_per_frame(xd)
+    else:
+        plan.execute(xd)
+    recs, counts = plan.detect()
+    gbk = [b.cpu().numpy() for b in plan.buckets()]
+    gfl = [w.cpu().numpy().view(np.uint32) for w in plan.flags()]
+    oplan = oracle_plan(shape, buckets, sigma, atten, flat, pfa, mu)
+    refs = [OR.rsft(x, oplan, noise=noise) for x in frames]
+    return plan, oplan, frames, refs, recs, counts, gbk, gfl
+
+
+def _check_frame(f, oplan, ref, recs, gbk, gfl, check_estimates=True):
+    errs = bucket_errors(gbk, ref["buckets"])
+    assert max(errs) <= BUCKET_RTOL, f"frame {f}: bucket errors {errs}"
+    amb = ambiguous(ref["buckets"], ref["gamma"])
+    gflags = unpack_flags(gfl, oplan.B)
+    diff = gflags != ref["flags"]
+    assert not np.any(diff & ~amb), f"frame {f}: flag mismatch outside the ambiguity band"
+    free = free_cells(amb, oplan).ravel()
+    got = cells_from_records(recs, oplan.shape, f)
+    want = set(int(v) for v in ref["detections"])
+    sym = set(got) ^ want
+    assert all(free[c] for c in sym), f"frame {f}: {len(sym)} detection differences on fixed cells"
+    votes = ref["votes"].ravel()
+    for c, r in got.items():
+        if not free[c]:
+            assert int(r["votes"]) == int(votes[c])
+    if not check_estimates:
+        return
+    common = sorted(c for c in set(got) & want if not free[c])
+    est = {e["cell"]: e for e in OR.estimate(common, ref["buckets"], oplan)}
+    peak_mismatch = 0
+    for c in common:
+        r, e = got[c], est[c]
+        assert abs(float(r["magnitude"]) / e["magnitude"] - 1.0) < 1e-3
+        if bool(r["is_peak"]) != e["is_peak"]:
+            peak_mismatch += 1
+            continue
+        if e["is_peak"]:
+            for d in range(len(oplan.shape)):
+                dd = (float(r["freq"][d]) - e["freq"][d] + 0.5) % 1.0 - 0.5
+                assert abs(dd * oplan.shape[d]) <= 1e-3, f"cell {c} dim {d}: {dd * oplan.shape[d]} bin"
+    assert peak_mismatch <= max(1, len(common) // 100)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fused_path_matches_oracle(name):
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name)
+    for f, ref in enumerate(refs):
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
+        assert counts[f] == len(cells_from_records(recs, oplan.shape, f))
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["c1_256x256_c128", "c3_cube_256x128x32", "one_dim_4096"])
+def test_per_frame_path_matches_oracle(name):
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name, per_frame=True)
+    for f, ref in enumerate(refs):
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["c2_1024x1024", "short_rows_512x64"])
+def test_estimated_noise_floor_matches_oracle(name):
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name, noise="estimated")
+    for f, ref in enumerate(refs):
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["c1_256x256_c128", "c3_cube_256x128x32", "four_dim",
+                                  "five_rounds_mu3", "one_dim_4096"])
+def test_votes_bit_exact_from_oracle_flags(name):
+    """Voting, second stage and ordering are integer work: given the oracle's
+    flags, the detections and their votes must match exactly."""
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name)
+    words = np.concatenate([pack_flags(r["flags"]).ravel() for r in refs]).view(np.int32)
+    plan.vote_flags(torch.from_numpy(words.copy()).to("cuda"))
+    recs2, counts2 = plan.detect()
+    for f, ref in enumerate(refs):
+        got = cells_from_records(recs2, oplan.shape, f)
+        assert sorted(got) == [int(v) for v in ref["detections"]]
+        votes = ref["votes"].ravel()
+        assert all(int(r["votes"]) == int(votes[c]) for c, r in got.items())
+        assert counts2[f] == len(ref["detections"])
+    # records are sorted by (frame, row-major cell)
+    keys = [(int(r["frame"]), int(np.ravel_multi_index(tuple(r["idx"][:len(oplan.shape)]),
+                                                        oplan.shape))) for r in recs2]
+    assert keys == sorted(keys)
+    plan.close()
+
+
+def test_uneven_batch_matches_oracle():
+    """Frames of different shapes, each with its own sigma, in one launch."""
+    shapes = [(128, 256), (256, 128), (512, 512), (128, 128), (1024, 256), (256, 2048)]
+    descs, frames, sigmas = [], [], []
+    for i, sh in enumerate(shapes):
+        sg = synth.draw_sigma(np.random.default_rng(400 + i), 3, sh)
+        bk = tuple(n // 16 for n in sh)
+        descs.append(dict(shape=sh, buckets=bk, rounds=3, sigma=sg, pfa=1e-4))
+        x, _ = make_input(sh, 6, seed=500 + i)
+        frames.append(x)
+        sigmas.append(sg)
+    from paper_1610_01050_amd import Plan
+    plan = Plan.uneven([dict(dsc, max_detections=1 << 16) for dsc in descs])
+    xd = torch.from_numpy(np.concatenate([x.ravel() for x in frames])).to("cuda")
+    plan.execute(xd)
+    recs, counts = plan.detect()
+    gbk = [b.cpu().numpy() for b in plan.buckets()]
+    gfl = [w.cpu().numpy().view(np.uint32) for w in plan.flags()]
+    for f, sh in enumerate(shapes):
+        oplan = oracle_plan(sh, tuple(n // 16 for n in sh), sigmas[f], pfa=1e-4)
+        ref = OR.rsft(frames[f], oplan)
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
+    plan.close()
+
+
+def test_graph_replay_equals_eager():
+    """The captured launch sequence gives the same results on every replay as
+    the eager launches, with eager work in between."""
+    from paper_1610_01050_amd import OPT_GRAPH
+    shape, buckets = (512, 512), (32, 32)
+    xs = [make_input(shape, 8, seed=700 + f)[0] for f in range(4)]
+    xd = torch.from_numpy(np.stack(xs)).to("cuda")
+    sigma = synth.draw_sigma(np.random.default_rng(3), 3, shape)
+    plan = _plan(shape=shape, buckets=buckets, rounds=3, sigma=sigma, pfa=1e-3, max_batch=4)
+    plan.set_option(OPT_GRAPH, 0)
+    plan.execute(xd)
+    ref_recs, _ = plan.detect()
+    ref_bk = plan.buckets()[0].cpu().numpy()
+    for rep in range(3):
+        plan.set_option(OPT_GRAPH, 1)
+        plan.execute(xd)
+        recs, _ = plan.detect()
+        assert np.array_equal(plan.buckets()[0].cpu().numpy(), ref_bk)
+        assert np.array_equal(recs, ref_recs)
+        plan.set_option(OPT_GRAPH, 0)
+        plan.execute(xd)
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_empty_batch_and_nan_frame():
+    shape, buckets = (256, 256), (16, 16)
+    sigma = synth.draw_sigma(np.random.default_rng(8), 3, shape)
+    plan = _plan(shape=shape, buckets=buckets, rounds=3, sigma=sigma, pfa=1e-3, max_batch=2)
+    xs = [make_input(shape, 4, seed=800 + f)[0] for f in range(2)]
+    xs[0][10, 20] = np.nan
+    xd = torch.from_numpy(np.stack(xs)).to("cuda")
+    plan.execute(xd, batch=0)
+    recs, counts = plan.detect()
+    assert len(recs) == 0 and len(counts) == 0
+    plan.execute(xd)
+    recs, counts = plan.detect()
+    bk = [b.cpu().numpy() for b in plan.buckets()]
+    assert np.all(np.isnan(bk[0]))          # the NaN spreads to every bucket
+    assert counts[0] == 0                    # and no flag is set (NaN >= gamma is false)
+    oplan = oracle_plan(shape, buckets, sigma)
+    ref = OR.rsft(xs[1], oplan)
+    _check_frame(1, oplan, ref, recs, bk[1], plan.flags()[1].cpu().numpy().view(np.uint32))
+    plan.close()
+
+
+def test_capacity_overflow_keeps_exact_counts():
+    """A frame over max_detections keeps its first max_detections records in
+    row-major order; the counts stay exact and detect() reports CAPACITY."""
+    from paper_1610_01050_amd import RsftError
+    shape, buckets = (256, 256), (16, 16)
+    sigma = synth.draw_sigma(np.random.default_rng(9), 3, shape)
+    xs = [make_input(shape, 4, seed=900 + f)[0] for f in range(2)]
+    xd = torch.from_numpy(np.stack(xs)).to("cuda")
+    full = _plan(shape=shape, buckets=buckets, rounds=3, sigma=sigma, pfa=1e-2, max_batch=2)
+    full.execute(xd)
+    frecs, fcounts = full.detect()
+    small = _plan(shape=shape, buckets=buckets, rounds=3, sigma=sigma, pfa=1e-2,
+                  max_batch=2, max_detections=8)
+    small.execute(xd)
+    with pytest.raises(RsftError):
+        small.detect()
+    recs, counts = small.detect(allow_truncation=True)
+    assert np.array_equal(counts, fcounts)
+    for f in range(2):
+        assert counts[f] > 8
+        want = frecs[frecs["frame"] == f][:8]
+        assert np.array_equal(recs[recs["frame"] == f], want)
+    oplan = oracle_plan(shape, buckets, sigma, pfa=1e-2)
+    for f in range(2):
+        ref = OR.rsft(xs[f], oplan)
+        amb = ambiguous(ref["buckets"], ref["gamma"])
+        n_free = int(free_cells(amb, oplan).sum())
+        assert abs(int(counts[f]) - len(ref["detections"])) <= n_free
+    full.close()
+    small.close()

@@ -206,3 +206,22 @@ def test_mu_below_T_votes():
     votes = R.votes_by_mapping(out["flags"], plan)
     assert np.array_equal(np.flatnonzero(votes >= 2), out["detections"])
     assert np.array_equal(votes, out["votes"])
+
+
+def test_estimated_noise_floor_unbiased():
+    """The order-statistic noise floor is unbiased for exponential powers
+    (Renyi representation): its mean over noise-only rounds equals
+    sigma_n^2 beta(sigma_s) within 3 standard errors, and it is insensitive to
+    a handful of strong tone buckets."""
+    shape, b = (64, 64), (8, 8)
+    plan = _plan(shape, b, pfa=1e-3, seed=23)
+    est = []
+    for f in range(400):
+        r = synth.noise_only(shape, 91, f, dtype=np.complex128)
+        est.append(R.estimated_noise_floor(R.rsft_round(r, plan, 0)) / plan.beta[0])
+    est = np.array(est)
+    assert abs(est.mean() - 1.0) < 3 * est.std(ddof=1) / math.sqrt(len(est))
+    # exact closed form of the estimator on a known sample
+    p = np.arange(1, 65, dtype=np.float64)
+    H = sum(1.0 / (64 - i) for i in range(32))
+    assert abs(R.estimated_noise_floor(np.sqrt(p)) - 32.0 / H) < 1e-12
