@@ -1,0 +1,295 @@
+#!/usr/bin/env python3
+"""Throughput of the batched fused RSFT hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 128 frames of
+1024x1024 complex64, each with K = 20 off-grid tones (frequencies uniform in
+[0,1)^2, Rayleigh amplitudes at per-sample SNR uniform in [-10, 10] dB) in
+CN(0,1) noise; B = 64x64 buckets, T = 3 permutation rounds, Pfa = 1e-4,
+60 dB Dolph-Chebyshev windows, one sigma set for the batch. Seeded synthetic
+data (no dataset is involved).
+
+One step = one rsft_execute over the batch: fold (window, permutation, flat
+window, aliasing for all rounds), MFMA DFT + first-stage threshold, voting +
+second stage, ordered compaction + off-grid estimates; the detection records
+end in device memory. Inputs are resident in HBM before timing starts; two
+1 GiB input buffers alternate so the 256 MB last-level cache cannot serve
+repeated reads.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from synth import scoring  # noqa: E402
+
+METRIC = "frames/s + HBM GB/s: batched fused RSFT vs per-frame RSFT at equal Pd/Pfa"
+HBM_PEAK_GBS = 8000.0
+CONFIG = 2
+FRAMES = 128
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "fold_c2_hbm_counters.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_01050_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per fold launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def score(recs, counts, metas, shape, frames):
+    hits = tgt = fa = outside = 0
+    D = len(shape)
+    for f in frames:
+        sel = recs[recs["frame"] == f]
+        cells = [int(np.ravel_multi_index(tuple(int(v) for v in r["idx"][:D]), shape)) for r in sel]
+        h, k, a, o = scoring.pd_pfa(cells, metas[f]["freqs"], shape)
+        hits += h
+        tgt += k
+        fa += a
+        outside += o
+    return {"pd": hits / max(tgt, 1), "pfa": fa / max(outside, 1), "frames": len(frames)}
+
+
+def cpu_baseline(frames_np, metas, shape, buckets, sigma, pfa, nsample):
+    """The FP64 oracle (literal Algorithm 1, numpy) on the first `nsample`
+    frames of the batch, one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import rsft as oracle_rsft
+    with threadpool_limits(limits=1):
+        plan = oracle_rsft.OraclePlan(shape, buckets, sigma, 60.0, None, pfa)
+        dets = []
+        t0 = time.perf_counter()
+        for f in range(nsample):
+            out = oracle_rsft.rsft(frames_np[f], plan)
+            dets.append(out["detections"])
+        dt = time.perf_counter() - t0
+    hits = tgt = fa = outside = 0
+    for f in range(nsample):
+        h, k, a, o = scoring.pd_pfa(dets[f], metas[f]["freqs"], shape)
+        hits += h
+        tgt += k
+        fa += a
+        outside += o
+    return {"value": nsample / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nsample} of the {FRAMES} frames of this workload: literal "
+                      f"FP64 Algorithm 1 (numpy, one thread), {dt:.1f} s",
+            "pd": hits / max(tgt, 1), "pfa": fa / max(outside, 1)}, dets
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-comparators", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="run one 1 GiB device copy (for scaling HBM counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(frames shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1610_01050_amd import OPT_GRAPH, OPT_TIMING, Plan, load_library
+    load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = synth.CONFIGS[CONFIG]
+    shape, buckets, T, pfa = cfg["shape"], cfg["buckets"], cfg["rounds"], cfg["pfa"]
+    N = int(np.prod(shape))
+    B = int(np.prod(buckets))
+
+    log(f"generating {FRAMES} frames {shape} ...")
+    t0 = time.perf_counter()
+    frames_np, metas = synth.make_batch(CONFIG, FRAMES)
+    log(f"  done in {time.perf_counter() - t0:.1f} s")
+    xa = torch.from_numpy(frames_np).to(dev)
+    xb = torch.neg(xa)                      # second buffer: same statistics, other bytes
+    bufs = [xa, xb]
+    sigma = synth.shared_sigma(CONFIG)
+    plan = Plan(shape, buckets, rounds=T, sigma=sigma, window_atten_db=cfg["atten_db"],
+                pfa=pfa, dtype="c64", max_batch=FRAMES, max_detections=1 << 16)
+    torch.cuda.synchronize()
+
+    if args.calibration_copy:
+        src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        src.zero_()
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # graph replay (production launch mode)
+    plan.set_option(OPT_TIMING, 0)
+    plan.set_option(OPT_GRAPH, 1)
+    for w in range(args.warmup):
+        plan.execute(bufs[w % 2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan.execute(bufs[k % 2])
+    torch.cuda.synchronize()
+    graph_s = time.perf_counter() - t0
+    log(f"graph mode: {graph_s / args.steps * 1e3:.3f} ms/step")
+
+    # timed region: eager launches with HIP events around every stage on the
+    # stream the kernels run on
+    plan.set_option(OPT_TIMING, 1)
+    for w in range(args.warmup):
+        plan.execute(bufs[w % 2])
+    torch.cuda.synchronize()
+    plan.stage_times(reset=True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan.execute(bufs[k % 2])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages, nstaged = plan.stage_times(reset=True)
+    plan.set_option(OPT_TIMING, 0)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = FRAMES * args.steps / elapsed
+    log(f"eager+events: {ms_per_step:.3f} ms/step, stages {stages}")
+
+    # detections of buffer A
+    plan.execute(xa)
+    recs, counts = plan.detect()
+    fused_score = score(recs, counts, metas, shape, range(FRAMES))
+    log(f"fused: {int(counts.sum())} detections, {fused_score}")
+
+    fold_ms = stages["fold"]
+    fold_bytes = FRAMES * (N * 8 + T * B * 8)        # input once + T x B partial buckets
+    achieved = fold_bytes / (fold_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC, "value": value, "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "128 frames of 1024x1024 complex64, K=20 off-grid tones, "
+                               "SNR U[-10,10] dB Rayleigh, B=64x64, T=3, Pfa=1e-4, 60 dB "
+                               "Dolph-Chebyshev, shared sigma",
+                   "frames": FRAMES, "shape": list(shape), "buckets": list(buckets),
+                   "rounds": T, "pfa": pfa},
+        "hbm_gbs": FRAMES * N * 8 * args.steps / elapsed / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "kernel": "fold",
+                     "algorithmic_bytes_per_launch": fold_bytes,
+                     "avg_launch_ms": fold_ms},
+        "stage_ms": stages,
+        "graph_ms_per_step": graph_s / args.steps * 1e3,
+        "detections": {"total": int(counts.sum()), **fused_score},
+    }
+
+    if not args.skip_comparators:
+        # per-frame plain RSFT: literal Algorithm 1, one launch chain per frame
+        plan.execute_per_frame(xa)
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.execute_per_frame(xa)
+        torch.cuda.synchronize()
+        pf_s = (time.perf_counter() - t0) / reps
+        precs, pcounts = plan.detect()
+        pf_score = score(precs, pcounts, metas, shape, range(FRAMES))
+        same = int(np.array_equal(precs[["frame", "idx"]], recs[["frame", "idx"]]))
+        out["per_frame_rsft"] = {"frames_per_s": FRAMES / pf_s, "ms_per_batch": pf_s * 1e3,
+                                 "speedup_of_fused": value / (FRAMES / pf_s),
+                                 "same_detections": bool(same), **pf_score}
+        log(f"per-frame: {pf_s * 1e3:.2f} ms/batch, {pf_score}")
+
+        # dense windowed 2-D FFT (rocFFT through torch) + exact T=1 NP threshold
+        from paper_1610_01050_amd import chebyshev_window
+        w0 = torch.tensor(chebyshev_window(shape[0], cfg["atten_db"]), dtype=torch.float32, device=dev)
+        w1 = torch.tensor(chebyshev_window(shape[1], cfg["atten_db"]), dtype=torch.float32, device=dev)
+        wnd = torch.outer(w0, w1)
+        thr = float((wnd.double() ** 2).sum().item() * math.log(1.0 / pfa))
+
+        def dense(x):
+            X = torch.fft.fft2(x * wnd)
+            return (X.real ** 2 + X.imag ** 2) >= thr
+
+        det = dense(xa)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            det = dense(xa)
+            nz = torch.nonzero(det.view(FRAMES, -1))
+        torch.cuda.synchronize()
+        dn_s = (time.perf_counter() - t0) / 3
+        nz = nz.cpu().numpy()
+        hits = tgt = fa = outside = 0
+        for f in range(FRAMES):
+            cells = nz[nz[:, 0] == f, 1]
+            h, k, a, o = scoring.pd_pfa(cells, metas[f]["freqs"], shape)
+            hits += h
+            tgt += k
+            fa += a
+            outside += o
+        out["dense_fft"] = {"frames_per_s": FRAMES / dn_s, "ms_per_batch": dn_s * 1e3,
+                            "speedup_of_fused": value / (FRAMES / dn_s),
+                            "pd": hits / max(tgt, 1), "pfa": fa / max(outside, 1)}
+        log(f"dense: {dn_s * 1e3:.2f} ms/batch")
+
+    if not args.skip_cpu and args.cpu_sample > 0:
+        n = min(args.cpu_sample, FRAMES)
+        log(f"cpu baseline: oracle on {n} frames ...")
+        cb, odets = cpu_baseline(frames_np, metas, shape, buckets, sigma, pfa, n)
+        gpu_sample = score(recs, counts, metas, shape, range(n))
+        cb["gpu_pd_same_frames"] = gpu_sample["pd"]
+        cb["gpu_pfa_same_frames"] = gpu_sample["pfa"]
+        agree = 0
+        total = 0
+        D = len(shape)
+        for f in range(n):
+            sel = recs[recs["frame"] == f]
+            g = set(int(np.ravel_multi_index(tuple(int(v) for v in r["idx"][:D]), shape)) for r in sel)
+            o = set(int(v) for v in odets[f])
+            agree += len(g & o)
+            total += len(g | o)
+        cb["detection_jaccard_vs_gpu"] = agree / max(total, 1)
+        out["cpu_baseline"] = cb
+        log(f"cpu: {cb['value']:.2f} frames/s")
+
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -22,7 +22,7 @@ rsft      Algorithm 1 literal, thresholds (eq. tpd), noise law (eq.
           alpha_beta), off-grid estimate of detected cells.
 dense     Algorithm 2 (Bartlett) with T=1 exact exponential threshold and the
           eq. bartlettROC closed form.
-evaluate  Pd / Pfa scoring and the complexity model of Tables I-II.
+evaluate  the complexity model of Tables I-II.
 """
 
 from . import windows, hashing, rsft, dense, evaluate  # noqa: F401

@@ -346,11 +346,6 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   const int wave = tid >> 6;
   constexpr int nwaves = kDftThreads / 64;
 
-  if (s == 0) {
-    if (tid == 0) p.counts[f] = 0u;
-    for (int c = tid; c < d.cchunks; c += kDftThreads)
-      p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = 0u;
-  }
 
   // twiddles of each dimension, concatenated
   int twoff[kMaxDims];
@@ -489,126 +484,247 @@ static int launch_dft_frame(const DevPtrs& p, int64_t frame, int T, int maxB, in
 
 // ---------------------------------------------------------------------------
 // vote: abar_i = sum_s c_s[M(i, sigma_s)] with M_d(i) = [sigma_{s,d} i_d] >>
-// log2 L_d (Def. 3). A cell with at least mu votes has a flag in one of the
-// rounds 0..T-mu, so only preimages R(j, sigma_{s0}^{-1}) of buckets flagged
-// in those rounds are visited (Def. 4): cell i_d = [sigma_inv u_d] for u_d in
-// [j_d L_d, (j_d + 1) L_d). A cell reached from round s0 is skipped when an
-// earlier candidate round also flags it, so each cell is visited once (the
-// preimages of one round are disjoint, Property 4). Work-group = 256 buckets
-// of one candidate round of one frame. A detected cell sets its bit in the
-// frame's bitmap and bumps its frame and compaction-chunk counters. Index
-// products are taken modulo 2^32 and masked, which equals the product modulo
-// N_d (a power of two).
+// log2 L_d (Def. 3), which by Properties 3-4 equals the accumulation of the
+// reverse-mapped flags (Def. 4, eq. a_i); detection iff abar_i >= mu.
+// One work-group per compaction chunk of 2^15 cells; each chunk's bitmap
+// words are written completely and its detection count stored, so no atomics
+// touch global memory. Index products are taken modulo 2^32 and masked,
+// which equals the product modulo N_d (a power of two).
+//
+// vote_rows_kernel (rows of 64..4096 cells, T <= 4): a cell with >= mu votes
+// is flagged in one of the rounds 0..T-mu, so each wave takes one row at a
+// time and visits only the preimages of that row's flagged buckets (Def. 4):
+// within a row the leading indices fix the leading bucket indices, so the
+// candidates are i_last = [sigma_inv u]_N for u in [j L, (j + 1) L) over the
+// flagged j of the row's bucket row. Work is proportional to the flagged
+// buckets times L, the reverse-mapping cost of the paper's complexity table,
+// instead of N T. A cell reached from round s0 is skipped when an earlier
+// candidate round flags it (each cell is counted once). Hits go to a
+// wave-private row bitmap in LDS, written out once per row.
+//
+// vote_kernel (any shape): the dense gather, every cell evaluated.
 // ---------------------------------------------------------------------------
 
 constexpr int kVoteThreads = 256;
+constexpr int kRowWordsMax = 128;   // rows of up to 4096 cells
 
-__device__ __forceinline__ void mark_cell(const DevPtrs& p, const FrameDesc& d, int64_t rel, int64_t f,
-                                          bool hit, unsigned long long flat) {
-  const unsigned long long m = __ballot(hit);
-  if (m == 0ull) return;
-  const int lane = threadIdx.x & 63;
-  if (lane == __ffsll((long long)m) - 1) atomicAdd(&p.counts[f], uint32_t(__popcll(m)));
-  if (hit) {
-    atomicOr(&p.bitmap[d.bitmap_off + rel * d.bitmap_stride + int64_t(flat >> 5)], 1u << (flat & 31ull));
-    atomicAdd(&p.chunk_counts[d.chunk_off + rel * d.chunk_stride + int64_t(flat >> kCompactShift)], 1u);
-  }
-}
-
-__global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, int mu) {
+template <int D>
+__global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, int mu, int frame0) {
   extern __shared__ uint32_t sflags[];
-  __shared__ int list[kVoteThreads];
-  __shared__ int wave_count[kVoteThreads / 64];
-
-  const int chunk = blockIdx.x;
-  const int s0 = blockIdx.y;
-  const int64_t f = blockIdx.z;
+  __shared__ uint32_t wcount[kVoteThreads / 64];
+  __shared__ uint32_t ssig[kMaxRounds * kMaxDims];
+  const int c = blockIdx.x;
+  const int64_t f = frame0 + int64_t(blockIdx.y);
   const FrameDesc& d = desc_of(p, f);
+  if (c >= d.cchunks || d.ndim != D) return;
   const int64_t rel = rel_of(p, f);
-  const int B = d.B;
-  if (chunk * kVoteThreads >= B) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int words = d.words;
-
   const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
   for (int w = tid; w < T * words; w += kVoteThreads) sflags[w] = fl[w];
-  __syncthreads();
-
-  const int j = chunk * kVoteThreads + tid;
-  const bool set = j < B && ((sflags[s0 * words + (j >> 5)] >> (j & 31)) & 1u);
-  const unsigned long long m = __ballot(set);
-  if (lane == 0) wave_count[wave] = __popcll(m);
-  __syncthreads();
-  int off = 0, nb = 0;
-  for (int w = 0; w < kVoteThreads / 64; ++w) {
-    if (w < wave) off += wave_count[w];
-    nb += wave_count[w];
+  if (tid < T * D) ssig[tid] = uint32_t(d.sigma[tid / D][tid % D]);
+  uint32_t nm[D], ls[D], bs[D], ns[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    nm[dd] = uint32_t(d.n[dd] - 1);
+    ls[dd] = uint32_t(d.lshift[dd]);
+    bs[dd] = uint32_t(d.bshift[dd]);
+    ns[dd] = uint32_t(d.nshift[dd]);
   }
-  if (set) list[off + __popcll(m & ((1ull << lane) - 1ull))] = j;
+  const int64_t cell0 = int64_t(c) << kCompactShift;
+  const int64_t rem = d.N - cell0;
+  const int ncell = int(rem < (int64_t(1) << kCompactShift) ? rem : (int64_t(1) << kCompactShift));
+  uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride + (cell0 >> 5);
   __syncthreads();
-  if (nb == 0) return;
 
-  const int Ls = d.Lshift;
-  const int64_t total = int64_t(nb) << Ls;
-  const int64_t nloop = (total + kVoteThreads - 1) / kVoteThreads * kVoteThreads;
-  for (int64_t w = tid; w < nloop; w += kVoteThreads) {
+  uint32_t cnt = 0u;
+  for (int base = wave * 64; base < ncell; base += kVoteThreads) {
+    const int64_t i = cell0 + base + lane;
     bool hit = false;
-    unsigned long long flat = 0ull;
-    if (w < total) {
-      const int jj = list[w >> Ls];
-      const uint32_t t = uint32_t(w & ((int64_t(1) << Ls) - 1));
-      uint32_t cell[kMaxDims];
-      for (int dd = 0; dd < d.ndim; ++dd) {
-        const uint32_t jd = uint32_t(jj >> d.bshift[dd]) & uint32_t(d.b[dd] - 1);
-        const uint32_t td = (t >> d.tshift[dd]) & uint32_t(d.l[dd] - 1);
-        const uint32_t u = (jd << d.lshift[dd]) | td;
-        cell[dd] = (uint32_t(d.sigma_inv[s0][dd]) * u) & uint32_t(d.n[dd] - 1);
-        flat |= (unsigned long long)cell[dd] << d.nshift[dd];
-      }
+    if (base + lane < ncell) {
       int votes = 0;
-      bool skip = false;
       for (int s = 0; s < T; ++s) {
         uint32_t jf = 0u;
-        for (int dd = 0; dd < d.ndim; ++dd) {
-          const uint32_t uu = (uint32_t(d.sigma[s][dd]) * cell[dd]) & uint32_t(d.n[dd] - 1);
-          jf |= (uu >> d.lshift[dd]) << d.bshift[dd];
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+          const uint32_t cd = uint32_t(i >> ns[dd]) & nm[dd];
+          jf |= (((ssig[s * D + dd] * cd) & nm[dd]) >> ls[dd]) << bs[dd];
         }
-        const int bit = int((sflags[s * words + (jf >> 5)] >> (jf & 31u)) & 1u);
-        if (s < s0 && bit) skip = true;
-        votes += bit;
+        votes += int((sflags[s * words + (jf >> 5)] >> (jf & 31u)) & 1u);
       }
-      hit = !skip && votes >= mu;
+      hit = votes >= mu;
     }
-    mark_cell(p, d, rel, f, hit, flat);
+    const unsigned long long m = __ballot(hit);
+    if (lane == 0) {
+      bm[base >> 5] = uint32_t(m & 0xffffffffull);
+      if (base + 32 < ncell) bm[(base >> 5) + 1] = uint32_t(m >> 32);
+      cnt += uint32_t(__popcll(m));
+    }
+  }
+  if (lane == 0) wcount[wave] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t total = 0u;
+    for (int w = 0; w < kVoteThreads / 64; ++w) total += wcount[w];
+    p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = total;
   }
 }
 
-int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_chunks, int max_words,
-                void* stream) {
+// bit j (< 128) of a 128-bit row held as four words
+__device__ __forceinline__ uint32_t row_bit(const uint32_t* w, uint32_t j) {
+  return __builtin_amdgcn_ubfe(w[j >> 5], j & 31u, 1u);
+}
+
+template <int D, int TT>
+__global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int mu, int frame0) {
+  extern __shared__ uint32_t sflags[];
+  __shared__ uint32_t wcount[kVoteThreads / 64];
+  __shared__ uint32_t rowbm[kVoteThreads / 64][kRowWordsMax];
+  __shared__ uint32_t blist[kVoteThreads / 64][128];
+  __shared__ uint32_t rowflags[kVoteThreads / 64][TT * 4];
+  const int c = blockIdx.x;
+  const int64_t f = frame0 + int64_t(blockIdx.y);
+  const FrameDesc& d = desc_of(p, f);
+  if (c >= d.cchunks || d.ndim != D) return;
+  const int64_t rel = rel_of(p, f);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int words = d.words;
+  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
+  for (int w = tid; w < TT * words; w += kVoteThreads) sflags[w] = fl[w];
+  uint32_t nm[D], ls[D], bs[D], ns[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    nm[dd] = uint32_t(d.n[dd] - 1);
+    ls[dd] = uint32_t(d.lshift[dd]);
+    bs[dd] = uint32_t(d.bshift[dd]);
+    ns[dd] = uint32_t(d.nshift[dd]);
+  }
+  uint32_t sig[TT][D], sinv_last[TT];
+#pragma unroll
+  for (int s = 0; s < TT; ++s) {
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) sig[s][dd] = uint32_t(d.sigma[s][dd]);
+    sinv_last[s] = uint32_t(d.sigma_inv[s][D - 1]);
+  }
+  (void)sig;
+  const uint32_t nl = nm[D - 1] + 1u;
+  const uint32_t lsl = ls[D - 1];
+  const uint32_t bl = uint32_t(d.b_last);
+  const int row_words = int(nl >> 5);
+  const int64_t cell0 = int64_t(c) << kCompactShift;
+  const int64_t rem = d.N - cell0;
+  const int ncell = int(rem < (int64_t(1) << kCompactShift) ? rem : (int64_t(1) << kCompactShift));
+  const int nrows = ncell / int(nl);
+  uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride + (cell0 >> 5);
+  uint32_t* rb = rowbm[wave];
+  uint32_t* lst = blist[wave];
+  uint32_t* R = rowflags[wave];
+  __syncthreads();
+
+  uint32_t cnt = 0u;
+  for (int r = wave; r < nrows; r += kVoteThreads / 64) {
+    const int64_t iw = cell0 + int64_t(r) * nl;               // first cell of the row
+    // the row's flags in every round: a 128-bit window at the row's bucket
+    // row, kept in wave-private LDS (lane 4s + q fills word q of round s)
+    if (lane < TT * 4) {
+      const int s = lane >> 2;
+      const int q = lane & 3;
+      uint32_t rowpart = 0u;
+#pragma unroll
+      for (int dd = 0; dd < D - 1; ++dd) {
+        const uint32_t cd = uint32_t(iw >> ns[dd]) & nm[dd];
+        rowpart |= (((uint32_t(d.sigma[s][dd]) * cd) & nm[dd]) >> ls[dd]) << bs[dd];
+      }
+      const int wi = s * words + int(rowpart >> 5);
+      uint32_t v = 0u;
+      if (q == 0) {
+        v = sflags[wi] >> (rowpart & 31u);                     // offset only when B_last < 32
+        if (bl < 32u) v &= (1u << bl) - 1u;
+      } else if (uint32_t(q) * 32u < bl) {
+        v = sflags[wi + q];
+      }
+      R[lane] = v;
+    }
+    for (int q = lane; q < row_words; q += 64) rb[q] = 0u;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int s0 = 0; s0 < TT; ++s0) {
+      if (s0 > TT - mu) continue;
+      // ordered list of the flagged bucket positions of the row in round s0
+      const bool b0 = uint32_t(lane) < bl && row_bit(R + s0 * 4, uint32_t(lane)) != 0u;
+      const bool b1 = bl > 64u && row_bit(R + s0 * 4, uint32_t(lane) + 64u) != 0u;
+      const unsigned long long m0 = __ballot(b0);
+      const unsigned long long m1 = __ballot(b1);
+      const unsigned long long below = (1ull << lane) - 1ull;
+      const int k0 = __popcll(m0);
+      if (b0) lst[__popcll(m0 & below)] = uint32_t(lane);
+      if (b1) lst[k0 + __popcll(m1 & below)] = uint32_t(lane) + 64u;
+      __builtin_amdgcn_wave_barrier();
+      const int ncand = (k0 + __popcll(m1)) << lsl;
+      for (int ci = lane; ci < ncand; ci += 64) {
+        const uint32_t jl = lst[ci >> lsl];
+        const uint32_t u = (jl << lsl) | (uint32_t(ci) & ((1u << lsl) - 1u));
+        const uint32_t il = (sinv_last[s0] * u) & nm[D - 1];
+        int votes = 0;
+        bool skip = false;
+#pragma unroll
+        for (int s = 0; s < TT; ++s) {
+          const uint32_t bit = row_bit(R + s * 4, ((sig[s][D - 1] * il) & nm[D - 1]) >> lsl);
+          if (s < s0 && bit) skip = true;
+          votes += int(bit);
+        }
+        if (!skip && votes >= mu) atomicOr(&rb[il >> 5], 1u << (il & 31u));
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int q = lane; q < row_words; q += 64) {
+      const uint32_t v = rb[q];
+      bm[int64_t(r) * row_words + q] = v;
+      cnt += uint32_t(__popc(v));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // wave total, then work-group total
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_down(cnt, o);
+  if (lane == 0) wcount[wave] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t total = 0u;
+    for (int w = 0; w < kVoteThreads / 64; ++w) total += wcount[w];
+    p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = total;
+  }
+}
+
+template <int D>
+static void launch_vote_d(const DevPtrs& p, dim3 grid, size_t shmem, hipStream_t st, int T, int mu,
+                          int frame0, bool rows) {
+  if (rows) {
+    switch (T) {
+      case 1: hipLaunchKernelGGL((vote_rows_kernel<D, 1>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      case 2: hipLaunchKernelGGL((vote_rows_kernel<D, 2>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      case 3: hipLaunchKernelGGL((vote_rows_kernel<D, 3>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      case 4: hipLaunchKernelGGL((vote_rows_kernel<D, 4>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      default: break;
+    }
+  }
+  hipLaunchKernelGGL(vote_kernel<D>, grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0);
+}
+
+int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks, int max_words,
+                int dims_mask, int rows_ok, int frame0, void* stream) {
   if (nframes <= 0) return hipSuccess;
   const size_t shmem = size_t(T) * size_t(max_words) * sizeof(uint32_t);
-  hipLaunchKernelGGL(vote_kernel, dim3(unsigned(max_chunks), unsigned(T - mu + 1), unsigned(nframes)),
-                     dim3(kVoteThreads), shmem, static_cast<hipStream_t>(stream), p, T, mu);
-  return hipGetLastError();
-}
-
-// counters of a frame are cleared by the dft stage of round 0; this kernel
-// does the same for a re-vote from given flags
-__global__ void zero_counts_kernel(DevPtrs p) {
-  const int64_t f = blockIdx.x;
-  const FrameDesc& d = desc_of(p, f);
-  const int64_t rel = rel_of(p, f);
-  if (threadIdx.x == 0) p.counts[f] = 0u;
-  for (int c = threadIdx.x; c < d.cchunks; c += blockDim.x)
-    p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = 0u;
-}
-
-int launch_zero_counts(const DevPtrs& p, int64_t nframes, void* stream) {
-  if (nframes <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_counts_kernel, dim3(unsigned(nframes)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid{unsigned(max_cchunks), unsigned(nframes), 1u};
+  const bool rows = rows_ok != 0 && T <= 4;
+  if (dims_mask & 1) launch_vote_d<1>(p, grid, shmem, st, T, mu, frame0, rows);
+  if (dims_mask & 2) launch_vote_d<2>(p, grid, shmem, st, T, mu, frame0, rows);
+  if (dims_mask & 4) launch_vote_d<3>(p, grid, shmem, st, T, mu, frame0, rows);
+  if (dims_mask & 8) launch_vote_d<4>(p, grid, shmem, st, T, mu, frame0, rows);
   return hipGetLastError();
 }
 
@@ -632,7 +748,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t n
       p.chunk_offsets[d.chunk_off + rel * d.chunk_stride + c] = run;
       run += p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c];
     }
+    p.counts[f] = uint32_t(run);
   }
+  __syncthreads();
   if (tid == 0) carry = 0;
   __syncthreads();
   for (int64_t start = 0; start < nframes; start += kScanThreads) {
@@ -666,133 +784,27 @@ int launch_scan(const DevPtrs& p, int64_t nframes, void* stream) {
 }
 
 // ---------------------------------------------------------------------------
-// estimate: one work-group per (compaction chunk of 2^15 cells, frame). It
-// reads the chunk's bitmap words in row-major order (clearing them for the
-// next execute), turns set bits into an ordered list in LDS (popcount + block
-// prefix sum), and for each detected cell writes its record at its rank in
-// the frame: votes recounted from the flags, gain-corrected magnitude
-// (median over the estimation rounds of |fhat_s[M(i, sigma_s)]| divided by
-// the flat-window response at the cell's offset inside its bucket), a peak
-// test against the 3^D - 1 circular neighbours (strictly above lower-index
-// neighbours, at least equal to higher-index ones) and per dimension the
-// vertex of a parabola through the log magnitudes at offsets -1, 0, +1,
-// clamped to [-1/2, 1/2]. FP32 bucket values, FP64 arithmetic.
+// compact: one work-group per (compaction chunk of 2^15 cells, frame). It
+// reads the chunk's bitmap words in row-major order and writes each detected
+// cell (flat index) and its frame at the cell's rank in the frame's record
+// range (popcount + block prefix sum), dropping ranks beyond the frame's
+// capacity.
+//
+// estimate: a grid-stride loop over all detections of the batch (balanced
+// whatever the detections' spread), one record per detection: votes recounted
+// from the flags, gain-corrected magnitude (median over the estimation rounds
+// of |fhat_s[M(i, sigma_s)]| times the inverse flat-window response at the
+// cell's offset inside its bucket), a peak test against the 3^D - 1 circular
+// neighbours (strictly above lower-index neighbours, at least equal to
+// higher-index ones) and per dimension the vertex of a parabola through the
+// log magnitudes at offsets -1, 0, +1, clamped to [-1/2, 1/2]. The 3^D
+// neighbourhood is evaluated once into registers (the kernel is specialised
+// on D). FP32 magnitudes, FP64 vertex and frequency.
 // ---------------------------------------------------------------------------
 
 constexpr int kEstThreads = 256;
 
-__device__ double cell_magnitude(const DevPtrs& p, const FrameDesc& d, int64_t rel, int T,
-                                 const uint32_t* cell) {
-  double vals[kMaxRounds];
-  int m = 0;
-  const float2* bk = p.buckets + d.bucket_off + rel * d.bucket_stride;
-  for (int s = 0; s < T; ++s) {
-    if (!((d.est_mask >> s) & 1)) continue;
-    uint32_t jf = 0u;
-    double g = 1.0;
-    for (int dd = 0; dd < d.ndim; ++dd) {
-      const uint32_t u = (uint32_t(d.sigma[s][dd]) * cell[dd]) & uint32_t(d.n[dd] - 1);
-      const uint32_t jd = u >> d.lshift[dd];
-      const uint32_t t = u & uint32_t(d.l[dd] - 1);
-      g *= p.gains[d.gain_off[dd] + t];
-      jf |= jd << d.bshift[dd];
-    }
-    const float2 v = bk[int64_t(s) * d.B + jf];
-    const double mag = sqrt(double(v.x) * double(v.x) + double(v.y) * double(v.y));
-    const double a = mag / g;
-    int q = m;
-    while (q > 0 && vals[q - 1] > a) {
-      vals[q] = vals[q - 1];
-      --q;
-    }
-    vals[q] = a;
-    ++m;
-  }
-  if (m == 0) return 0.0;
-  return (m & 1) ? vals[m / 2] : 0.5 * (vals[m / 2 - 1] + vals[m / 2]);
-}
-
-__device__ __forceinline__ double log_parabola_offset(double am, double a0, double ap) {
-  const double tiny = 1e-300;
-  const double lm = log(am > tiny ? am : tiny);
-  const double l0 = log(a0 > tiny ? a0 : tiny);
-  const double lp = log(ap > tiny ? ap : tiny);
-  const double den = 2.0 * l0 - lm - lp;
-  if (!(den > 0.0)) return 0.0;
-  double v = 0.5 * (lp - lm) / den;
-  v = v < -0.5 ? -0.5 : v;
-  v = v > 0.5 ? 0.5 : v;
-  return v;
-}
-
-__device__ void write_record(const DevPtrs& p, const FrameDesc& d, int64_t rel, int64_t f, int T,
-                             unsigned long long flat, int64_t out) {
-  const int D = d.ndim;
-  uint32_t cell[kMaxDims];
-  for (int dd = 0; dd < D; ++dd) cell[dd] = uint32_t(flat >> d.nshift[dd]) & uint32_t(d.n[dd] - 1);
-  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
-  int votes = 0;
-  for (int s = 0; s < T; ++s) {
-    uint32_t jf = 0u;
-    for (int dd = 0; dd < D; ++dd) {
-      const uint32_t u = (uint32_t(d.sigma[s][dd]) * cell[dd]) & uint32_t(d.n[dd] - 1);
-      jf |= (u >> d.lshift[dd]) << d.bshift[dd];
-    }
-    votes += int((fl[int64_t(s) * d.words + (jf >> 5)] >> (jf & 31u)) & 1u);
-  }
-  const double a0 = cell_magnitude(p, d, rel, T, cell);
-  int npow3 = 1;
-  for (int dd = 0; dd < D; ++dd) npow3 *= 3;
-  bool peak = true;
-  for (int code = 0; code < npow3; ++code) {
-    int c = code;
-    bool centre = true;
-    uint32_t nb[kMaxDims];
-    for (int dd = D - 1; dd >= 0; --dd) {
-      const int o = c % 3 - 1;
-      c /= 3;
-      if (o != 0) centre = false;
-      nb[dd] = uint32_t(int64_t(cell[dd]) + o + d.n[dd]) & uint32_t(d.n[dd] - 1);
-    }
-    if (centre) continue;
-    unsigned long long nflat = 0ull;
-    for (int dd = 0; dd < D; ++dd) nflat |= (unsigned long long)nb[dd] << d.nshift[dd];
-    if (nflat == flat) continue;
-    const double an = cell_magnitude(p, d, rel, T, nb);
-    if (nflat < flat) {
-      if (!(a0 > an)) peak = false;
-    } else {
-      if (!(a0 >= an)) peak = false;
-    }
-  }
-  rsft_detection rec;
-  rec.frame = f;
-  for (int dd = 0; dd < kMaxDims; ++dd) {
-    rec.idx[dd] = 0;
-    rec.freq[dd] = 0.0;
-  }
-  for (int dd = 0; dd < D; ++dd) {
-    uint32_t mcell[kMaxDims], pcell[kMaxDims];
-    for (int e = 0; e < D; ++e) mcell[e] = pcell[e] = cell[e];
-    mcell[dd] = (cell[dd] + uint32_t(d.n[dd]) - 1u) & uint32_t(d.n[dd] - 1);
-    pcell[dd] = (cell[dd] + 1u) & uint32_t(d.n[dd] - 1);
-    const double am = cell_magnitude(p, d, rel, T, mcell);
-    const double ap = cell_magnitude(p, d, rel, T, pcell);
-    const double delta = log_parabola_offset(am, a0, ap);
-    double fr = (double(cell[dd]) + delta) / double(d.n[dd]);
-    if (fr < 0.0) fr += 1.0;
-    if (fr >= 1.0) fr -= 1.0;
-    rec.idx[dd] = cell[dd];
-    rec.freq[dd] = fr;
-  }
-  rec.votes = votes;
-  rec.is_peak = peak ? 1 : 0;
-  rec.magnitude = float(a0);
-  rec.reserved = 0.f;
-  p.records[out] = rec;
-}
-
-__global__ __launch_bounds__(kEstThreads) void estimate_kernel(DevPtrs p, int T) {
+__global__ __launch_bounds__(kEstThreads) void compact_kernel(DevPtrs p) {
   constexpr int kWordsPerPass = kEstThreads;
   __shared__ uint32_t list[kWordsPerPass * 32];
   __shared__ uint32_t wsum[kEstThreads / 64];
@@ -807,22 +819,19 @@ __global__ __launch_bounds__(kEstThreads) void estimate_kernel(DevPtrs p, int T)
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int64_t rank0 = p.chunk_offsets[ck];
-  const int64_t out0 = p.offsets[f];
   const int64_t cap = d.cap;
-  uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride;
+  if (rank0 >= cap) return;
+  const int64_t out0 = p.offsets[f];
+  const uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride;
   const int w0 = c << (kCompactShift - 5);
   const int wend = min(d.bitmap_words, w0 + (1 << (kCompactShift - 5)));
   int64_t running = 0;
   for (int wb = w0; wb < wend; wb += kWordsPerPass) {
     const int w = wb + tid;
-    uint32_t word = 0u;
-    if (w < wend) {
-      word = bm[w];
-      if (word) bm[w] = 0u;
-    }
-    // block exclusive prefix of the popcounts
+    uint32_t word = w < wend ? bm[w] : 0u;
     const int pc = __popc(word);
     int incl = pc;
+#pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int v = __shfl_up(incl, o);
       if (lane >= o) incl += v;
@@ -830,6 +839,7 @@ __global__ __launch_bounds__(kEstThreads) void estimate_kernel(DevPtrs p, int T)
     if (lane == 63) wsum[wave] = uint32_t(incl);
     __syncthreads();
     int base = 0, total = 0;
+#pragma unroll
     for (int q = 0; q < kEstThreads / 64; ++q) {
       if (q < wave) base += int(wsum[q]);
       total += int(wsum[q]);
@@ -844,9 +854,8 @@ __global__ __launch_bounds__(kEstThreads) void estimate_kernel(DevPtrs p, int T)
     for (int q = tid; q < total; q += kEstThreads) {
       const int64_t rank = rank0 + running + q;
       if (rank < cap) {
-        const unsigned long long flat =
-            ((unsigned long long)c << kCompactShift) | (unsigned long long)list[q];
-        write_record(p, d, rel, f, T, flat, out0 + rank);
+        p.det_cell[out0 + rank] = ((unsigned long long)c << kCompactShift) | (unsigned long long)list[q];
+        p.det_frame[out0 + rank] = int32_t(f);
       }
     }
     running += total;
@@ -854,10 +863,218 @@ __global__ __launch_bounds__(kEstThreads) void estimate_kernel(DevPtrs p, int T)
   }
 }
 
-int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, void* stream) {
+// Per-frame constants of the estimate stage, held in registers.
+template <int D>
+struct EstParams {
+  uint32_t nm[D], lm[D], ls[D], bs[D], ns[D];
+  const float* ig[D];              // inverse flat-window gains per dimension
+  int n_est;
+  uint32_t sig_est[kMaxEstRounds][D];
+  const float2* bk_est[kMaxEstRounds];
+  const uint32_t* fl;              // flags [T][words]
+  const int32_t* sig;              // sigma [kMaxRounds][kMaxDims] of the descriptor
+  int words;
+};
+
+template <int D>
+__device__ __forceinline__ void load_params(const DevPtrs& p, const FrameDesc& d, int64_t rel,
+                                            EstParams<D>& e) {
+  const float2* bk = p.buckets + d.bucket_off + rel * d.bucket_stride;
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    e.nm[dd] = uint32_t(d.n[dd] - 1);
+    e.lm[dd] = uint32_t(d.l[dd] - 1);
+    e.ls[dd] = uint32_t(d.lshift[dd]);
+    e.bs[dd] = uint32_t(d.bshift[dd]);
+    e.ns[dd] = uint32_t(d.nshift[dd]);
+    e.ig[dd] = p.inv_gains + d.gain_off[dd];
+  }
+  e.n_est = d.n_est;
+#pragma unroll
+  for (int q = 0; q < kMaxEstRounds; ++q) {
+    const int s = q < e.n_est ? d.est_rounds[q] : 0;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) e.sig_est[q][dd] = uint32_t(d.sigma[s][dd]);
+    e.bk_est[q] = bk + int64_t(s) * d.B;
+  }
+  e.fl = p.flags + d.flag_off + rel * d.flag_stride;
+  e.sig = &d.sigma[0][0];
+  e.words = d.words;
+}
+
+template <int D>
+__device__ __forceinline__ float cell_magnitude(const EstParams<D>& e, const uint32_t (&cell)[D]) {
+  float v[kMaxEstRounds];
+  const int m = e.n_est;
+#pragma unroll
+  for (int q = 0; q < kMaxEstRounds; ++q) {
+    v[q] = 0.f;
+    if (q < m) {
+      uint32_t jf = 0u;
+      float ig = 1.f;
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd) {
+        const uint32_t u = (e.sig_est[q][dd] * cell[dd]) & e.nm[dd];
+        ig *= e.ig[dd][u & e.lm[dd]];
+        jf |= (u >> e.ls[dd]) << e.bs[dd];
+      }
+      const float2 b = e.bk_est[q][jf];
+      v[q] = sqrtf(b.x * b.x + b.y * b.y) * ig;
+    }
+  }
+  // sort the m <= kMaxEstRounds values (odd-even transposition, fixed indices)
+#pragma unroll
+  for (int pass = 0; pass < kMaxEstRounds; ++pass) {
+#pragma unroll
+    for (int q = pass & 1; q + 1 < kMaxEstRounds; q += 2) {
+      if (q + 1 < m && v[q] > v[q + 1]) {
+        const float t = v[q];
+        v[q] = v[q + 1];
+        v[q + 1] = t;
+      }
+    }
+  }
+  float med = v[0];
+#pragma unroll
+  for (int q = 1; q < kMaxEstRounds; ++q) {
+    if (q == m / 2) med = (m & 1) ? v[q] : 0.5f * (v[q - 1] + v[q]);
+  }
+  return med;
+}
+
+// Vertex of the parabola through (-1, log am), (0, log a0), (1, log ap),
+// clamped to [-1/2, 1/2]; 0 when the points are not concave. The logarithms
+// of the FP32 magnitudes are taken in FP32 (base 2: the ratio is the same in
+// any base), the vertex in FP64.
+__device__ __forceinline__ double log_parabola_offset(float am, float a0, float ap) {
+  const float tiny = 1e-30f;
+  const double lm = double(__builtin_amdgcn_logf(am > tiny ? am : tiny));
+  const double l0 = double(__builtin_amdgcn_logf(a0 > tiny ? a0 : tiny));
+  const double lp = double(__builtin_amdgcn_logf(ap > tiny ? ap : tiny));
+  const double den = 2.0 * l0 - lm - lp;
+  if (!(den > 0.0)) return 0.0;
+  double v = 0.5 * (lp - lm) / den;
+  v = v < -0.5 ? -0.5 : v;
+  v = v > 0.5 ? 0.5 : v;
+  return v;
+}
+
+template <int D>
+__device__ void write_record(const EstParams<D>& e, int T, int64_t f, unsigned long long flat,
+                             rsft_detection* out) {
+  constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
+  uint32_t cell[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) cell[dd] = uint32_t(flat >> e.ns[dd]) & e.nm[dd];
+  int votes = 0;
+  for (int s = 0; s < T; ++s) {
+    uint32_t jf = 0u;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) {
+      const uint32_t u = (uint32_t(e.sig[s * kMaxDims + dd]) * cell[dd]) & e.nm[dd];
+      jf |= (u >> e.ls[dd]) << e.bs[dd];
+    }
+    votes += int((e.fl[int64_t(s) * e.words + (jf >> 5)] >> (jf & 31u)) & 1u);
+  }
+  // magnitudes of the 3^D neighbourhood; code = sum_d (o_d + 1) 3^(D-1-d)
+  float A[kNb];
+  constexpr int kCentre = (kNb - 1) / 2;
+#pragma unroll
+  for (int code = 0; code < kNb; ++code) {
+    uint32_t nb[D];
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      nb[dd] = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
+    }
+    A[code] = cell_magnitude<D>(e, nb);
+  }
+  const float a0 = A[kCentre];
+  bool peak = true;
+#pragma unroll
+  for (int code = 0; code < kNb; ++code) {
+    if (code == kCentre) continue;
+    uint32_t nb[D];
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      nb[dd] = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
+    }
+    unsigned long long nflat = 0ull;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) nflat |= (unsigned long long)nb[dd] << e.ns[dd];
+    if (nflat == flat) continue;
+    if (nflat < flat) {
+      if (!(a0 > A[code])) peak = false;
+    } else {
+      if (!(a0 >= A[code])) peak = false;
+    }
+  }
+  rsft_detection rec;
+  rec.frame = f;
+#pragma unroll
+  for (int dd = 0; dd < kMaxDims; ++dd) {
+    rec.idx[dd] = 0;
+    rec.freq[dd] = 0.0;
+  }
+  int stride = 1;
+#pragma unroll
+  for (int dd = D - 1; dd >= 0; --dd) {
+    const double delta = log_parabola_offset(A[kCentre - stride], a0, A[kCentre + stride]);
+    double fr = (double(cell[dd]) + delta) / double(e.nm[dd] + 1u);
+    if (fr < 0.0) fr += 1.0;
+    if (fr >= 1.0) fr -= 1.0;
+    rec.idx[dd] = cell[dd];
+    rec.freq[dd] = fr;
+    stride *= 3;
+  }
+  rec.votes = votes;
+  rec.is_peak = peak ? 1 : 0;
+  rec.magnitude = a0;
+  rec.reserved = 0.f;
+  *out = rec;
+}
+
+template <int D>
+__global__ __launch_bounds__(kEstThreads) void estimate_kernel(DevPtrs p, int T, int64_t nframes) {
+  const int64_t total = p.offsets[nframes];
+  const int64_t stride = int64_t(gridDim.x) * kEstThreads;
+  if (p.uniform) {
+    const FrameDesc& d0 = p.descs[0];
+    if (d0.ndim != D) return;
+    for (int64_t k = int64_t(blockIdx.x) * kEstThreads + threadIdx.x; k < total; k += stride) {
+      const int64_t f = p.det_frame[k];
+      EstParams<D> e;
+      load_params<D>(p, d0, f, e);
+      write_record<D>(e, T, f, p.det_cell[k], p.records + k);
+    }
+  } else {
+    for (int64_t k = int64_t(blockIdx.x) * kEstThreads + threadIdx.x; k < total; k += stride) {
+      const int64_t f = p.det_frame[k];
+      const FrameDesc& d = p.descs[f];
+      if (d.ndim != D) continue;
+      EstParams<D> e;
+      load_params<D>(p, d, 0, e);
+      write_record<D>(e, T, f, p.det_cell[k], p.records + k);
+    }
+  }
+}
+
+int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
+                    void* stream) {
   if (nframes <= 0) return hipSuccess;
-  hipLaunchKernelGGL(estimate_kernel, dim3(unsigned(max_cchunks), unsigned(nframes)), dim3(kEstThreads), 0,
-                     static_cast<hipStream_t>(stream), p, T);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(compact_kernel, dim3(unsigned(max_cchunks), unsigned(nframes)), dim3(kEstThreads), 0,
+                     st, p);
+  const dim3 grid(2048u);
+  if (dims_mask & 1) hipLaunchKernelGGL(estimate_kernel<1>, grid, dim3(kEstThreads), 0, st, p, T, nframes);
+  if (dims_mask & 2) hipLaunchKernelGGL(estimate_kernel<2>, grid, dim3(kEstThreads), 0, st, p, T, nframes);
+  if (dims_mask & 4) hipLaunchKernelGGL(estimate_kernel<3>, grid, dim3(kEstThreads), 0, st, p, T, nframes);
+  if (dims_mask & 8) hipLaunchKernelGGL(estimate_kernel<4>, grid, dim3(kEstThreads), 0, st, p, T, nframes);
   return hipGetLastError();
 }
 
@@ -867,7 +1084,7 @@ int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, v
 // applies both windows and aliases (Def. 2): one wave per bucket b sums
 // z[b + B l] = wbar[n] w[[sigma n]] r[[sigma n]] over the L terms, n_d =
 // b_d + B_d l_d. Buckets are written in the paper's indexing (no relabel).
-// plain_vote evaluates abar_i = sum_s c_s[M(i, sigma_s)] for every cell.
+// Its votes are taken with the vote stage launched for that frame alone.
 // ---------------------------------------------------------------------------
 
 constexpr int kPlainThreads = 256;
@@ -932,35 +1149,6 @@ int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t fr
   else
     hipLaunchKernelGGL(plain_fold_kernel<false>, dim3(blocks), dim3(kPlainThreads), 0, st, p, input,
                        frame, round);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(kPlainThreads) void plain_vote_kernel(DevPtrs p, int64_t f) {
-  const FrameDesc& d = desc_of(p, f);
-  const int64_t rel = rel_of(p, f);
-  const int64_t i = int64_t(blockIdx.x) * kPlainThreads + threadIdx.x;
-  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
-  bool hit = false;
-  if (i < d.N) {
-    int votes = 0;
-    for (int s = 0; s < d.T; ++s) {
-      uint32_t jf = 0u;
-      for (int dd = 0; dd < d.ndim; ++dd) {
-        const uint32_t cell = uint32_t(i >> d.nshift[dd]) & uint32_t(d.n[dd] - 1);
-        const uint32_t u = (uint32_t(d.sigma[s][dd]) * cell) & uint32_t(d.n[dd] - 1);
-        jf |= (u >> d.lshift[dd]) << d.bshift[dd];
-      }
-      votes += int((fl[int64_t(s) * d.words + (jf >> 5)] >> (jf & 31u)) & 1u);
-    }
-    hit = votes >= d.mu;
-  }
-  mark_cell(p, d, rel, f, hit, (unsigned long long)i);
-}
-
-int launch_plain_vote(const DevPtrs& p, int64_t frame, int64_t N, void* stream) {
-  const unsigned blocks = unsigned((N + kPlainThreads - 1) / kPlainThreads);
-  hipLaunchKernelGGL(plain_vote_kernel, dim3(blocks), dim3(kPlainThreads), 0,
-                     static_cast<hipStream_t>(stream), p, frame);
   return hipGetLastError();
 }
 

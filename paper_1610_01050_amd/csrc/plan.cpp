@@ -68,13 +68,13 @@ struct rsft_plan_s {
   std::vector<rsft::FrameDesc> descs;
   std::vector<rsft_plan_info_t> info;
   rsft::FoldConfig fold{256, 4};
-  int maxB = 0, max_words = 0, max_cchunks = 0, max_vote_chunks = 0, sum_tw_max = 0;
+  int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, rows_ok = 1;
   int64_t tiles_per_frame = 0;   // uniform plans
   int64_t ntiles_uneven = 0;     // uneven plans
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles;
   DeviceBuffer d_part, d_buckets, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
-      d_offsets, d_records;
+      d_offsets, d_records, d_det_cell, d_det_frame;
   rsft::DevPtrs ptrs{};
   // state of the last execute
   int64_t last_batch = -1;
@@ -161,14 +161,15 @@ void release(DeviceBuffer& buf) {
 struct HostTables {
   std::vector<float2> wrow, wcol, tw, flat;
   std::vector<int32_t> rowlist;
-  std::vector<double> gains;
+  std::vector<float> inv_gains;
   std::vector<float> win;
 };
 
 // Rounds feeding magnitude estimates: a round is clean when no dimension d
 // and k in {1, 2} has |[sigma_{s,d} k]_{N_d}| (circular) < L_d + 2, i.e. the
-// main-lobe bins of one tone never share a bucket; all clean rounds are used,
-// else the one whose worst distance is largest (first on ties).
+// main-lobe bins of one tone never share a bucket; the first (up to
+// kMaxEstRounds) clean rounds are used, else the one whose worst distance is
+// largest (first on ties).
 int estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma) {
   std::vector<int64_t> score(static_cast<size_t>(p.rounds));
   int mask = 0;
@@ -183,7 +184,7 @@ int estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma) {
       }
     }
     score[size_t(s)] = worst;
-    if (worst >= 0) mask |= 1 << s;
+    if (worst >= 0 && __builtin_popcount(unsigned(mask)) < rsft::kMaxEstRounds) mask |= 1 << s;
   }
   if (mask) return mask;
   int best = 0;
@@ -245,6 +246,9 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
       d.tau[s][k] = int32_t(inv % p.b[k]);
     }
   d.est_mask = estimation_mask(p, sigma);
+  d.n_est = 0;
+  for (int s = 0; s < T; ++s)
+    if ((d.est_mask >> s) & 1) d.est_rounds[d.n_est++] = s;
 
   // windows (Sec. III-C.1, Sec. IV-B) per dimension, FP64
   const double flat_db = p.flat_atten_db < 0.0 ? p.window_atten_db : p.flat_atten_db;
@@ -360,9 +364,8 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
       const double ang = -2.0 * M_PI * double(m) / double(p.b[k]);
       ht.tw.push_back(make_float2(float(std::cos(ang)), float(std::sin(ang))));
     }
-    d.gain_off[k] = int64_t(ht.gains.size());
-    const auto g = rsft::flat_gain(wbar[size_t(k)], p.n[k] / p.b[k]);
-    ht.gains.insert(ht.gains.end(), g.begin(), g.end());
+    d.gain_off[k] = int64_t(ht.inv_gains.size());
+    for (double g : rsft::flat_gain(wbar[size_t(k)], p.n[k] / p.b[k])) ht.inv_gains.push_back(float(1.0 / g));
     d.win_off[k] = int64_t(ht.win.size());
     for (int64_t m = 0; m < p.n[k]; ++m) ht.win.push_back(float(w[size_t(k)][size_t(m)]));
     d.flat_off[k] = int64_t(ht.flat.size());
@@ -402,7 +405,8 @@ void free_plan(rsft_plan_s* pl) {
   DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
                           &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_part,
                           &pl->d_buckets, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
-                          &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records};
+                          &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
+                          &pl->d_det_cell, &pl->d_det_frame};
   for (auto* b : bufs) release(*b);
   delete pl;
 }
@@ -465,7 +469,8 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     pl->maxB = std::max(pl->maxB, d.B);
     pl->max_words = std::max(pl->max_words, d.words);
     pl->max_cchunks = std::max(pl->max_cchunks, d.cchunks);
-    pl->max_vote_chunks = std::max(pl->max_vote_chunks, (d.B + 255) / 256);
+    pl->dims_mask |= 1 << (d.ndim - 1);
+    if (d.n_last < 64 || d.n_last > 4096) pl->rows_ok = 0;
     int sum_tw = 0;
     for (int k = 0; k < d.ndim; ++k) sum_tw += d.b[k];
     pl->sum_tw_max = std::max(pl->sum_tw_max, sum_tw);
@@ -502,7 +507,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = upload(pl->d_wcol, ht.wcol)) != RSFT_OK) return st;
   if ((st = upload(pl->d_rowlist, ht.rowlist)) != RSFT_OK) return st;
   if ((st = upload(pl->d_tw, ht.tw)) != RSFT_OK) return st;
-  if ((st = upload(pl->d_gains, ht.gains)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_gains, ht.inv_gains)) != RSFT_OK) return st;
   if ((st = upload(pl->d_win, ht.win)) != RSFT_OK) return st;
   if ((st = upload(pl->d_flat, ht.flat)) != RSFT_OK) return st;
   if ((st = upload(pl->d_tiles, tiles)) != RSFT_OK) return st;
@@ -516,6 +521,8 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = alloc(pl->d_counts, size_t(pl->max_frames) * sizeof(uint32_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_offsets, size_t(pl->max_frames + 1) * sizeof(int64_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_records, size_t(rec_total) * sizeof(rsft_detection))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_det_cell, size_t(rec_total) * sizeof(unsigned long long))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_det_frame, size_t(rec_total) * sizeof(int32_t))) != RSFT_OK) return st;
   HIP_TRY(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
 
   auto& q = pl->ptrs;
@@ -525,7 +532,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.wcol = static_cast<const float2*>(pl->d_wcol.ptr);
   q.rowlist = static_cast<const int32_t*>(pl->d_rowlist.ptr);
   q.tw = static_cast<const float2*>(pl->d_tw.ptr);
-  q.gains = static_cast<const double*>(pl->d_gains.ptr);
+  q.inv_gains = static_cast<const float*>(pl->d_gains.ptr);
   q.win = static_cast<const float*>(pl->d_win.ptr);
   q.flat = static_cast<const float2*>(pl->d_flat.ptr);
   q.part = static_cast<float2*>(pl->d_part.ptr);
@@ -537,6 +544,8 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.counts = static_cast<uint32_t*>(pl->d_counts.ptr);
   q.offsets = static_cast<int64_t*>(pl->d_offsets.ptr);
   q.records = static_cast<rsft_detection*>(pl->d_records.ptr);
+  q.det_cell = static_cast<unsigned long long*>(pl->d_det_cell.ptr);
+  q.det_frame = static_cast<int32_t*>(pl->d_det_frame.ptr);
   q.tiles = static_cast<const int32_t*>(pl->d_tiles.ptr);
   return RSFT_OK;
 }
@@ -568,10 +577,10 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->maxB, pl->sum_tw_max, 0, 0, st));
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_vote_chunks, pl->max_words, st));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, st));
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   LAUNCH_TRY(rsft::launch_scan(q, batch, st));
-  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, st));
+  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, st));
   if (ev) HIP_TRY(hipEventRecord(ev[4], st));
   return RSFT_OK;
 }
@@ -688,11 +697,11 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
     const auto& d = pl->descs[size_t(pl->uniform ? 0 : f)];
     for (int r = 0; r < pl->T; ++r) LAUNCH_TRY(rsft::launch_plain_fold(q, d_input, pl->dtype, f, r, d.B, s));
     LAUNCH_TRY(rsft::launch_plain_dft(q, f, pl->T, pl->maxB, pl->sum_tw_max, s));
-    LAUNCH_TRY(rsft::launch_plain_vote(q, f, d.N, s));
+    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, int(f), s));
   }
   if (batch > 0) {
     LAUNCH_TRY(rsft::launch_scan(q, batch, s));
-    LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, s));
+    LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, s));
   }
   return RSFT_OK;
 }
@@ -707,10 +716,9 @@ rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* strea
   for (int64_t f = 0; f < batch; ++f) words += size_t(pl->descs[size_t(pl->uniform ? 0 : f)].flag_stride);
   HIP_TRY(hipMemcpyAsync(pl->d_flags.ptr, d_flags, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   const auto& q = pl->ptrs;
-  LAUNCH_TRY(rsft::launch_zero_counts(q, batch, s));
-  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_vote_chunks, pl->max_words, s));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, s));
   LAUNCH_TRY(rsft::launch_scan(q, batch, s));
-  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, s));
+  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, s));
   return RSFT_OK;
 }
 

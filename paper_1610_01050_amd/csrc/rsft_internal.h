@@ -14,6 +14,7 @@ constexpr int kMaxLastBuckets = 4096;     // B_{D-1} (fold stage residue slots p
 constexpr int kMaxDetectionsPerFrame = 1 << 24;
 constexpr int kDefaultDetections = 16384;
 constexpr int kCompactShift = 15;         // cells per compaction chunk = 2^15
+constexpr int kMaxEstRounds = 5;          // rounds feeding a magnitude estimate
 constexpr int kFoldRoundGroup = 4;        // rounds folded per pass over the input
 
 // Everything a kernel needs to know about one frame descriptor. Lives in
@@ -36,6 +37,8 @@ struct FrameDesc {
   int32_t words;              // flag words per round = ceil(B / 32)
   int32_t cap;                // detection capacity of a frame
   int32_t est_mask;           // rounds used for magnitude estimates
+  int32_t n_est;              // their number (<= kMaxEstRounds)
+  int32_t est_rounds[kMaxEstRounds];
   int32_t sigma[kMaxRounds][kMaxDims];
   int32_t sigma_inv[kMaxRounds][kMaxDims];
   int32_t tau[kMaxRounds][kMaxDims];      // sigma_inv mod B_d
@@ -47,7 +50,7 @@ struct FrameDesc {
   int64_t wcol_off;       // float2 [T][n_last]
   int64_t rowlist_off;    // int32  [rows_total], grouped by residue class
   int64_t tw_off[kMaxDims];    // float2 [B_d]: exp(-2 pi i m / B_d)
-  int64_t gain_off[kMaxDims];  // double [L_d]: flat-window response / N_d
+  int64_t gain_off[kMaxDims];  // float [L_d]: N_d / flat-window response
   int64_t win_off[kMaxDims];   // float  [N_d]: pre-permutation window (per-frame path)
   int64_t flat_off[kMaxDims];  // float2 [N_d]: flat window (per-frame path)
   // workspace offsets of the descriptor's first frame, and per-frame strides
@@ -70,7 +73,7 @@ struct DevPtrs {
   const float2* wcol;
   const int32_t* rowlist;
   const float2* tw;
-  const double* gains;
+  const float* inv_gains;
   const float* win;
   const float2* flat;
   float2* part;
@@ -81,6 +84,8 @@ struct DevPtrs {
   int64_t* chunk_offsets;      // rank of a chunk's first detection within its frame
   uint32_t* counts;            // [frames]
   int64_t* offsets;            // [frames + 1]
+  unsigned long long* det_cell;  // detected cells in record order
+  int32_t* det_frame;            // their frames
   rsft_detection* records;
   const int32_t* tiles;        // uneven plans: [ntiles][3] (frame, class, chunk)
 };
@@ -97,15 +102,14 @@ int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
                 int T, const FoldConfig& cfg, void* stream);
 int launch_dft(const DevPtrs& p, int64_t nframes, int T, int maxB, int sum_tw,
                int identity_relabel, int nchunks_override, void* stream);
-int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_chunks,
-                int max_words, void* stream);
+int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
+                int max_words, int dims_mask, int rows_ok, int frame0, void* stream);
 int launch_scan(const DevPtrs& p, int64_t nframes, void* stream);
-int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, void* stream);
-int launch_zero_counts(const DevPtrs& p, int64_t nframes, void* stream);
+int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
+                    void* stream);
 // Per-frame comparator path.
 int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t frame,
                       int round, int B, void* stream);
-int launch_plain_vote(const DevPtrs& p, int64_t frame, int64_t N, void* stream);
 int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int maxB, int sum_tw, void* stream);
 
 }  // namespace rsft

@@ -102,18 +102,25 @@ def _check_frame(f, oplan, ref, recs, gbk, gfl, check_estimates=True):
         return
     common = sorted(c for c in set(got) & want if not free[c])
     est = {e["cell"]: e for e in OR.estimate(common, ref["buckets"], oplan)}
-    peak_mismatch = 0
+    gains = OR.flat_window_gain(oplan)
     for c in common:
         r, e = got[c], est[c]
         assert abs(float(r["magnitude"]) / e["magnitude"] - 1.0) < 1e-3
         if bool(r["is_peak"]) != e["is_peak"]:
-            peak_mismatch += 1
+            # the peak decision may flip only on a near-tie with a neighbour
+            # (FP32 buckets carry ~1e-5 relative error)
+            cell = np.unravel_index(c, oplan.shape)
+            a0 = e["magnitude"]
+            gap = min(abs(a0 - OR.cell_magnitude(
+                tuple((cell[d] + o[d] - 1) % oplan.shape[d] for d in range(len(cell))),
+                ref["buckets"], oplan, gains)) / a0
+                for o in np.ndindex(*([3] * len(cell))) if any(v != 1 for v in o))
+            assert gap <= 2e-3, f"cell {c}: peak flag differs with nearest neighbour gap {gap}"
             continue
         if e["is_peak"]:
             for d in range(len(oplan.shape)):
                 dd = (float(r["freq"][d]) - e["freq"][d] + 0.5) % 1.0 - 0.5
                 assert abs(dd * oplan.shape[d]) <= 1e-3, f"cell {c} dim {d}: {dd * oplan.shape[d]} bin"
-    assert peak_mismatch <= max(1, len(common) // 100)
 
 
 @pytest.mark.parametrize("name", list(CASES))

@@ -11,6 +11,7 @@ from scipy import stats
 import synth
 from oracle import dense as Dn
 from oracle import evaluate as E
+from synth import scoring as S
 from oracle import rsft as R
 from oracle import windows as W
 
@@ -179,6 +180,6 @@ def test_pd_pfa_scoring():
     freqs = np.array([[10 / 64, 20 / 64], [40.4 / 64, 5.2 / 64]])
     det = [np.ravel_multi_index((11, 21), shape),     # inside guard of tone 0
            np.ravel_multi_index((30, 30), shape)]     # false alarm
-    hits, K, fa, outside = E.pd_pfa(det, freqs, shape, guard=3)
+    hits, K, fa, outside = S.pd_pfa(det, freqs, shape, guard=3)
     assert (hits, K, fa) == (1, 2, 1)
     assert outside == 64 * 64 - 2 * 49
