@@ -144,6 +144,9 @@ def main():
     plan = Plan(shape, buckets, rounds=T, sigma=sigma, window_atten_db=cfg["atten_db"],
                 pfa=pfa, dtype="c64", max_batch=FRAMES, max_detections=1 << 16)
     torch.cuda.synchronize()
+    tuned_ms = plan.autotune(xa, repeats=5)          # fold launch shape, untimed
+    fold_cfg = plan.info()["fold"]
+    log(f"autotuned fold: {fold_cfg} ({tuned_ms:.4f} ms)")
 
     if args.calibration_copy:
         src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)   # 1 GiB
@@ -212,6 +215,7 @@ def main():
                      "algorithmic_bytes_per_launch": fold_bytes,
                      "avg_launch_ms": fold_ms},
         "stage_ms": stages,
+        "fold_launch": fold_cfg,
         "graph_ms_per_step": graph_s / args.steps * 1e3,
         "detections": {"total": int(counts.sum()), **fused_score},
     }

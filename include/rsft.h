@@ -160,6 +160,11 @@ typedef struct {
                                 K >= this many tones, whatever their SNR */
   int32_t estimation_rounds; /* bit s set: round s feeds magnitude estimates */
   int32_t reserved;
+  /* plan-wide launch shape of the fold stage (see rsft_autotune) */
+  int32_t fold_threads;      /* work-group size */
+  int32_t fold_vec;          /* complex samples per thread per row */
+  int32_t fold_nontemporal;  /* 1: non-temporal input loads */
+  int32_t reserved2;
 } rsft_plan_info_t;
 
 typedef struct rsft_plan_s* rsft_plan_t;
@@ -192,6 +197,19 @@ rsft_status rsft_plan(const rsft_params* frames, int64_t nframes, rsft_plan_t* o
  */
 rsft_status rsft_execute(rsft_plan_t plan, const void* d_input, int64_t batch,
                          void* stream);
+
+/*
+ * Choose the launch shape of the fold stage (the HBM-bound stage) by timing:
+ * work-group size (256 / 512 threads), samples per thread (4 / 2) and
+ * ordinary vs non-temporal input loads are each run `repeats` times
+ * (<= 0: 5) on d_input (same contract as rsft_execute) with
+ * hipEvents on `stream`; the fastest becomes the plan's shape (reported by
+ * rsft_plan_info) and *best_ms (may be NULL) its average duration.
+ * Synchronizes the stream; the plan's detection results are unaffected.
+ * Errors: as rsft_execute.
+ */
+rsft_status rsft_autotune(rsft_plan_t plan, const void* d_input, int64_t batch, void* stream,
+                          int32_t repeats, double* best_ms);
 
 /*
  * The same detections computed the plain way, as a comparator: for each
@@ -252,9 +270,15 @@ enum {
   RSFT_OPT_GRAPH = 0,  /* 1: replay the launch sequence as a captured hipGraph
                           (cached per input pointer and batch); 0: launch
                           kernels one by one. Default 1. */
-  RSFT_OPT_TIMING = 1  /* 1: record hipEvents around each stage in eager mode
+  RSFT_OPT_TIMING = 1, /* 1: record hipEvents around each stage in eager mode
                           and accumulate their durations (forces GRAPH=0
                           while set). Default 0. */
+  /* launch shape of the fold stage (what rsft_autotune chooses):
+     work-group size 256 | 512; samples per thread 2 | 4; non-temporal
+     input loads 0 | 1 */
+  RSFT_OPT_FOLD_THREADS = 2,
+  RSFT_OPT_FOLD_VEC = 3,
+  RSFT_OPT_FOLD_NONTEMPORAL = 4
 };
 rsft_status rsft_set_option(rsft_plan_t plan, int32_t option, int64_t value);
 

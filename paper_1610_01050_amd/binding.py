@@ -30,11 +30,12 @@ ERROR_CAPACITY = 7
 C64, C128 = 0, 1
 NOISE_KNOWN, NOISE_ESTIMATED = 0, 1
 OPT_GRAPH, OPT_TIMING = 0, 1
+OPT_FOLD_THREADS, OPT_FOLD_VEC, OPT_FOLD_NONTEMPORAL = 2, 3, 4
 STAGES = ("fold", "dft", "vote", "estimate")
 
 # Every symbol include/rsft.h declares.
 SYMBOLS = (
-    "rsft_plan", "rsft_execute", "rsft_execute_per_frame", "rsft_detect",
+    "rsft_plan", "rsft_execute", "rsft_autotune", "rsft_execute_per_frame", "rsft_detect",
     "rsft_detection_count", "rsft_get_buckets", "rsft_get_flags",
     "rsft_vote_flags", "rsft_plan_info", "rsft_set_option", "rsft_stage_times",
     "rsft_destroy", "rsft_status_string", "rsft_last_error",
@@ -86,6 +87,8 @@ class PlanInfo(ctypes.Structure):
         ("p1", ctypes.c_double), ("eta_m", ctypes.c_double),
         ("max_sparsity", ctypes.c_double),
         ("estimation_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("fold_threads", ctypes.c_int32), ("fold_vec", ctypes.c_int32),
+        ("fold_nontemporal", ctypes.c_int32), ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -114,6 +117,7 @@ def load_library(path=None):
     lib.rsft_plan.argtypes = [ctypes.POINTER(Params), i64, ctypes.POINTER(vp)]
     lib.rsft_execute.argtypes = [vp, vp, i64, vp]
     lib.rsft_execute_per_frame.argtypes = [vp, vp, i64, vp]
+    lib.rsft_autotune.argtypes = [vp, vp, i64, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     lib.rsft_detect.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.rsft_detection_count.argtypes = [vp, vp, ctypes.POINTER(i64)]
     lib.rsft_get_buckets.argtypes = [vp, vp, vp]
@@ -301,6 +305,18 @@ class Plan:
                                                  int(batch), _stream_handle(stream)))
         self.last_batch = int(batch)
 
+    def autotune(self, x, batch=None, repeats=5, stream=None):
+        """Time the fold stage's launch shapes on `x` and keep the fastest;
+        returns its average duration in ms."""
+        if batch is None:
+            batch = x.shape[0] if self.uniform else len(self.descs)
+        self._check_input(x, batch)
+        best = ctypes.c_double()
+        _check(self._lib, self._lib.rsft_autotune(self._h, ctypes.c_void_p(x.data_ptr()), int(batch),
+                                                  _stream_handle(stream), int(repeats),
+                                                  ctypes.byref(best)))
+        return best.value
+
     def execute_per_frame(self, x, batch=None, stream=None):
         if batch is None:
             batch = x.shape[0] if self.uniform else len(self.descs)
@@ -386,6 +402,8 @@ class Plan:
             "gamma": np.array([out.gamma[s] for s in range(T)]),
             "p1": out.p1, "eta_m": out.eta_m, "max_sparsity": out.max_sparsity,
             "estimation_rounds": [s for s in range(T) if (out.estimation_rounds >> s) & 1],
+            "fold": {"threads": out.fold_threads, "vec": out.fold_vec,
+                     "nontemporal": out.fold_nontemporal},
         }
 
     def set_option(self, option, value):

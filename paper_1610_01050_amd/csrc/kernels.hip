@@ -55,49 +55,66 @@ __device__ __forceinline__ int64_t rel_of(const DevPtrs& p, int64_t f) {
 // row groups that take every G-th row of the class.
 // ---------------------------------------------------------------------------
 
-template <bool C128, int V>
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <bool C128, bool NT, int V>
 __device__ __forceinline__ void load_vec(const void* base, int64_t idx, float2 (&x)[V]) {
   if constexpr (!C128) {
-    const float4* p4 = reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(base) + idx);
+    const v4f* p4 = reinterpret_cast<const v4f*>(reinterpret_cast<const float2*>(base) + idx);
 #pragma unroll
     for (int q = 0; q < V / 2; ++q) {
-      const float4 v = p4[q];
+      const v4f v = NT ? __builtin_nontemporal_load(p4 + q) : p4[q];
       x[2 * q] = make_float2(v.x, v.y);
       x[2 * q + 1] = make_float2(v.z, v.w);
     }
   } else {
-    const double2* p2 = reinterpret_cast<const double2*>(base) + idx;
+    const v2d* p2 = reinterpret_cast<const v2d*>(base) + idx;
 #pragma unroll
     for (int q = 0; q < V; ++q) {
-      const double2 v = p2[q];
+      const v2d v = NT ? __builtin_nontemporal_load(p2 + q) : p2[q];
       x[q] = make_float2(float(v.x), float(v.y));
     }
   }
 }
 
-template <int TG, int V, int THREADS, bool C128>
-__global__ __launch_bounds__(THREADS) void fold_kernel(DevPtrs p, const void* __restrict__ input,
-                                                       int64_t tiles_per_frame, int round0, int T) {
-  constexpr int P = THREADS * V;
-  __shared__ float2 red[TG * P];
+// Pointers of the fold stage. The tables are read-only and never alias the
+// partial-bucket output, which lets the compiler read them with scalar loads.
+struct FoldArgs {
+  const FrameDesc* __restrict__ descs;
+  int uniform;
+  const float2* __restrict__ wrow;
+  const float2* __restrict__ wcol;
+  const int32_t* __restrict__ rowlist;
+  const int32_t* __restrict__ tiles;
+  float2* __restrict__ part;
+};
 
+template <int TG, int V, int THREADS, bool C128, bool NT>
+__device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restrict__ input, int tile,
+                                          int tiles_per_frame, int round0, int T, float2* red) {
+  constexpr int P = THREADS * V;
   const int tid = threadIdx.x;
-  int64_t f;
-  int cls, chunk;
+  // the tile's (frame, class, chunk), kept in scalar registers so that the
+  // descriptor, row list and row weights are read with scalar loads
+  int f, cls, chunk;
   if (p.uniform) {
-    const FrameDesc& d0 = p.descs[0];
-    f = int64_t(blockIdx.x) / tiles_per_frame;
-    const int64_t rem = int64_t(blockIdx.x) - f * tiles_per_frame;
-    cls = int(rem / d0.nchunks);
-    chunk = int(rem - int64_t(cls) * d0.nchunks);
+    const int nch = p.descs[0].nchunks;
+    f = tile / tiles_per_frame;
+    const int rem = tile - f * tiles_per_frame;
+    cls = rem / nch;
+    chunk = rem - cls * nch;
   } else {
-    const int32_t* t = p.tiles + 3 * int64_t(blockIdx.x);
+    const int32_t* t = p.tiles + 3 * int64_t(tile);
     f = t[0];
     cls = t[1];
     chunk = t[2];
   }
-  const FrameDesc& d = desc_of(p, f);
-  const int64_t rel = rel_of(p, f);
+  f = __builtin_amdgcn_readfirstlane(f);
+  cls = __builtin_amdgcn_readfirstlane(cls);
+  chunk = __builtin_amdgcn_readfirstlane(chunk);
+  const FrameDesc& d = p.descs[p.uniform ? 0 : f];
+  const int64_t rel = p.uniform ? f : 0;
   const int nl = d.n_last, bl = d.b_last, R = d.rows_per_class, rows_total = d.rows_total;
   const float2* __restrict__ wrow = p.wrow + d.wrow_off;
   const float2* __restrict__ wcol = p.wcol + d.wcol_off;
@@ -124,9 +141,9 @@ __global__ __launch_bounds__(THREADS) void fold_kernel(DevPtrs p, const void* __
         for (int v = 0; v < V; ++v) cr[s][v] = ci[s][v] = 0.f;
 #pragma unroll 4
       for (int i = 0; i < R; ++i) {
-        const int row = rl[i];
+        const int row = __builtin_amdgcn_readfirstlane(rl[i]);
         float2 x[V];
-        load_vec<C128, V>(in, int64_t(row) * nl + col, x);
+        load_vec<C128, NT, V>(in, int64_t(row) * nl + col, x);
 #pragma unroll
         for (int s = 0; s < TG; ++s) {
           const float2 w = wrow[int64_t(round0 + s) * rows_total + row];
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(THREADS) void fold_kernel(DevPtrs p, const void* __
     for (int i = g; i < R; i += G) {
       const int row = rl[i];
       float2 x[V];
-      load_vec<C128, V>(in, int64_t(row) * nl + col, x);
+      load_vec<C128, NT, V>(in, int64_t(row) * nl + col, x);
 #pragma unroll
       for (int s = 0; s < TG; ++s) {
         const float2 w = wrow[int64_t(round0 + s) * rows_total + row];
@@ -189,10 +206,9 @@ __global__ __launch_bounds__(THREADS) void fold_kernel(DevPtrs p, const void* __
 
   // slot q holds residue q mod B_{D-1}; sum the P / B_{D-1} slots of each
   // residue in a fixed order
-  const int tg = (T - round0) < TG ? (T - round0) : TG;
   const int nslots = P / bl;
   float2* part = p.part + d.part_off + rel * d.part_stride;
-  for (int o = tid; o < tg * bl; o += THREADS) {
+  for (int o = tid; o < TG * bl; o += THREADS) {
     const int s = o / bl;
     const int rho = o - s * bl;
     float sr = 0.f, si = 0.f;
@@ -205,27 +221,51 @@ __global__ __launch_bounds__(THREADS) void fold_kernel(DevPtrs p, const void* __
   }
 }
 
-template <int TG, int V, int THREADS>
-static hipError_t launch_fold_t(const DevPtrs& p, const void* input, int dtype, int64_t tpf,
+// One work-group per tile; tiles of uneven batches are listed largest first
+// so that the hardware dispatcher balances the tail.
+template <int TG, int V, int THREADS, bool C128, bool NT>
+__global__ __launch_bounds__(THREADS) void fold_kernel(FoldArgs p, const void* __restrict__ input,
+                                                       int tiles_per_frame, int round0, int T) {
+  __shared__ float2 red[TG * THREADS * V];
+  fold_tile<TG, V, THREADS, C128, NT>(p, input, int(blockIdx.x), tiles_per_frame, round0, T, red);
+}
+
+template <int TG, int V, int THREADS, bool NT>
+static hipError_t launch_fold_t(const DevPtrs& q, const void* input, int dtype, int64_t tpf,
                                 int64_t ntiles, int round0, int T, hipStream_t st) {
+  const FoldArgs p{q.descs, q.uniform, q.wrow, q.wcol, q.rowlist, q.tiles, q.part};
   if (dtype == RSFT_C128)
-    hipLaunchKernelGGL((fold_kernel<TG, V, THREADS, true>), dim3(unsigned(ntiles)), dim3(THREADS), 0,
-                       st, p, input, tpf, round0, T);
+    hipLaunchKernelGGL((fold_kernel<TG, V, THREADS, true, NT>), dim3(unsigned(ntiles)), dim3(THREADS), 0,
+                       st, p, input, int(tpf), round0, T);
   else
-    hipLaunchKernelGGL((fold_kernel<TG, V, THREADS, false>), dim3(unsigned(ntiles)), dim3(THREADS), 0,
-                       st, p, input, tpf, round0, T);
+    hipLaunchKernelGGL((fold_kernel<TG, V, THREADS, false, NT>), dim3(unsigned(ntiles)), dim3(THREADS), 0,
+                       st, p, input, int(tpf), round0, T);
   return hipGetLastError();
 }
 
-template <int V, int THREADS>
+template <int V, int THREADS, bool NT>
 static hipError_t launch_fold_v(const DevPtrs& p, const void* input, int dtype, int64_t tpf,
                                 int64_t ntiles, int round0, int rounds, int T, hipStream_t st) {
   switch (rounds) {
-    case 1: return launch_fold_t<1, V, THREADS>(p, input, dtype, tpf, ntiles, round0, T, st);
-    case 2: return launch_fold_t<2, V, THREADS>(p, input, dtype, tpf, ntiles, round0, T, st);
-    case 3: return launch_fold_t<3, V, THREADS>(p, input, dtype, tpf, ntiles, round0, T, st);
-    default: return launch_fold_t<4, V, THREADS>(p, input, dtype, tpf, ntiles, round0, T, st);
+    case 1: return launch_fold_t<1, V, THREADS, NT>(p, input, dtype, tpf, ntiles, round0, T, st);
+    case 2: return launch_fold_t<2, V, THREADS, NT>(p, input, dtype, tpf, ntiles, round0, T, st);
+    case 3: return launch_fold_t<3, V, THREADS, NT>(p, input, dtype, tpf, ntiles, round0, T, st);
+    default: return launch_fold_t<4, V, THREADS, NT>(p, input, dtype, tpf, ntiles, round0, T, st);
   }
+}
+
+template <bool NT>
+static int launch_fold_nt(const DevPtrs& p, const void* input, int dtype, int64_t tpf, int64_t ntiles,
+                          int round0, int rounds, int T, const FoldConfig& cfg, hipStream_t st) {
+  if (cfg.vec == 4 && cfg.threads == 256)
+    return launch_fold_v<4, 256, NT>(p, input, dtype, tpf, ntiles, round0, rounds, T, st);
+  if (cfg.vec == 4 && cfg.threads == 512)
+    return launch_fold_v<4, 512, NT>(p, input, dtype, tpf, ntiles, round0, rounds, T, st);
+  if (cfg.vec == 2 && cfg.threads == 256)
+    return launch_fold_v<2, 256, NT>(p, input, dtype, tpf, ntiles, round0, rounds, T, st);
+  if (cfg.vec == 2 && cfg.threads == 512)
+    return launch_fold_v<2, 512, NT>(p, input, dtype, tpf, ntiles, round0, rounds, T, st);
+  return hipErrorInvalidValue;
 }
 
 int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
@@ -234,22 +274,9 @@ int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
   (void)nframes;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ntiles <= 0) return hipSuccess;
-  if (cfg.vec == 4) {
-    switch (cfg.threads) {
-      case 256: return launch_fold_v<4, 256>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
-      case 512: return launch_fold_v<4, 512>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
-      case 1024: return launch_fold_v<4, 1024>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  if (cfg.vec == 2) {
-    switch (cfg.threads) {
-      case 256: return launch_fold_v<2, 256>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
-      case 512: return launch_fold_v<2, 512>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, st);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  return hipErrorInvalidValue;
+  return cfg.nontemporal
+             ? launch_fold_nt<true>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, cfg, st)
+             : launch_fold_nt<false>(p, input, dtype, tiles_per_frame, ntiles, round0, rounds, T, cfg, st);
 }
 
 // ---------------------------------------------------------------------------

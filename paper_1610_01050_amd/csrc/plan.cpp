@@ -67,7 +67,9 @@ struct rsft_plan_s {
   int T = 0, mu = 0, dtype = 0;
   std::vector<rsft::FrameDesc> descs;
   std::vector<rsft_plan_info_t> info;
-  rsft::FoldConfig fold{256, 4};
+  rsft::FoldConfig fold{256, 4, 0};
+  int num_cus = 256;
+  int64_t min_nl = 0;
   int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, rows_ok = 1;
   int64_t tiles_per_frame = 0;   // uniform plans
   int64_t ntiles_uneven = 0;     // uneven plans
@@ -194,7 +196,8 @@ int estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma) {
 }
 
 rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan_info_t& info,
-                             HostTables& ht, int fold_p) {
+                             HostTables& ht) {
+  const int64_t fold_p = rsft::kFoldMaxP;   // chunks must suit every fold shape the tuner may pick
   std::memset(&d, 0, sizeof(d));
   std::memset(&info, 0, sizeof(info));
   const int D = p.ndim, T = p.rounds;
@@ -426,16 +429,19 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   // must hold at least that many
   int64_t min_nl = INT64_MAX;
   for (int64_t i = 0; i < nframes; ++i) min_nl = std::min<int64_t>(min_nl, frames[i].n[frames[i].ndim - 1]);
-  pl->fold = rsft::FoldConfig{256, min_nl >= 4 ? 4 : 2};
-  while (int64_t(pl->fold.threads) * pl->fold.vec < max_bl) pl->fold.threads *= 2;
-  if (pl->fold.threads > 512) return fail(RSFT_ERROR_UNSUPPORTED, "last-dimension B too large");
-  const int fold_p = pl->fold.threads * pl->fold.vec;
+  pl->min_nl = min_nl;
+  (void)hipDeviceGetAttribute(&pl->num_cus, hipDeviceAttributeMultiprocessorCount, pl->device);
+  if (pl->num_cus <= 0) pl->num_cus = 256;
+  // default fold shape: 256 threads x 4 samples, ordinary loads;
+  // rsft_autotune may replace it
+  pl->fold = rsft::FoldConfig{256, min_nl >= 4 ? 4 : 2, 0};
+  if (int64_t(pl->fold.threads) * pl->fold.vec < max_bl) return fail(RSFT_ERROR_UNSUPPORTED, "last-dimension B too large");
 
   HostTables ht;
   pl->descs.resize(size_t(nframes));
   pl->info.resize(size_t(nframes));
   for (int64_t i = 0; i < nframes; ++i) {
-    rsft_status st = build_descriptor(frames[i], pl->descs[size_t(i)], pl->info[size_t(i)], ht, fold_p);
+    rsft_status st = build_descriptor(frames[i], pl->descs[size_t(i)], pl->info[size_t(i)], ht);
     if (st != RSFT_OK) return st;
   }
 
@@ -563,16 +569,34 @@ rsft_status check_batch(rsft_plan_s* pl, const void* d_input, int64_t batch) {
   return RSFT_OK;
 }
 
+// Stage 1 (window, permutation, flat window, aliasing), all round groups.
+rsft_status fold_stage(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStream_t st,
+                       const rsft::FoldConfig& cfg) {
+  const auto& q = pl->ptrs;
+  const int64_t ntiles = pl->uniform ? batch * pl->tiles_per_frame : pl->ntiles_uneven;
+  if (ntiles >= (int64_t(1) << 31)) return fail(RSFT_ERROR_UNSUPPORTED, "more than 2^31 fold tiles");
+  for (int r0 = 0; r0 < pl->T; r0 += rsft::kFoldRoundGroup) {
+    const int rounds = std::min(rsft::kFoldRoundGroup, pl->T - r0);
+    LAUNCH_TRY(rsft::launch_fold(q, d_input, pl->dtype, batch, pl->tiles_per_frame, ntiles, r0, rounds,
+                                 pl->T, cfg, st));
+  }
+  return RSFT_OK;
+}
+
+void drop_graphs(rsft_plan_s* pl) {
+  for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+  pl->graphs.clear();
+  pl->graph_order.clear();
+}
+
 // The hot path, stage by stage; `ev` (optional) brackets the stages.
 rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStream_t st,
                     hipEvent_t* ev) {
   const auto& q = pl->ptrs;
   if (ev) HIP_TRY(hipEventRecord(ev[0], st));
-  const int64_t ntiles = pl->uniform ? batch * pl->tiles_per_frame : pl->ntiles_uneven;
-  for (int r0 = 0; r0 < pl->T; r0 += rsft::kFoldRoundGroup) {
-    const int rounds = std::min(rsft::kFoldRoundGroup, pl->T - r0);
-    LAUNCH_TRY(rsft::launch_fold(q, d_input, pl->dtype, batch, pl->tiles_per_frame, ntiles, r0, rounds,
-                                 pl->T, pl->fold, st));
+  {
+    const rsft_status fs = fold_stage(pl, d_input, batch, st, pl->fold);
+    if (fs != RSFT_OK) return fs;
   }
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->maxB, pl->sum_tw_max, 0, 0, st));
@@ -686,6 +710,52 @@ rsft_status rsft_execute(rsft_plan_t pl, const void* d_input, int64_t batch, voi
   return RSFT_OK;
 }
 
+rsft_status rsft_autotune(rsft_plan_t pl, const void* d_input, int64_t batch, void* stream,
+                          int32_t repeats, double* best_ms) {
+  if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
+  rsft_status st = check_batch(pl, d_input, batch);
+  if (st != RSFT_OK) return st;
+  if (batch == 0) return RSFT_OK;
+  if (repeats <= 0) repeats = 5;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  struct Events {  // released on every return path
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  HIP_TRY(hipEventCreate(&ev.e[0]));
+  HIP_TRY(hipEventCreate(&ev.e[1]));
+  hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
+  rsft::FoldConfig best = pl->fold;
+  float best_t = 1e30f;
+  for (int threads : {256, 512})
+    for (int vec : {4, 2})
+      for (int nt : {0, 1}) {
+        if (vec == 4 && pl->min_nl < 4) continue;
+        if (st != RSFT_OK) break;
+        const rsft::FoldConfig cfg{threads, vec, nt};
+        if ((st = fold_stage(pl, d_input, batch, s, cfg)) != RSFT_OK) break;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < repeats && st == RSFT_OK; ++r) st = fold_stage(pl, d_input, batch, s, cfg);
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= float(repeats);
+        if (st == RSFT_OK && ms < best_t) {
+          best_t = ms;
+          best = cfg;
+        }
+      }
+  if (st != RSFT_OK) return st;
+  pl->fold = best;
+  drop_graphs(pl);   // captured graphs hold the previous launch shape
+  if (best_ms) *best_ms = double(best_t);
+  return RSFT_OK;
+}
+
 rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t batch, void* stream) {
   if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
   rsft_status st = check_batch(pl, d_input, batch);
@@ -789,6 +859,9 @@ rsft_status rsft_plan_info(rsft_plan_t pl, int64_t frame, rsft_plan_info_t* out)
   if (!pl || !out) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
   if (frame < 0 || frame >= pl->ndesc) return fail(RSFT_ERROR_INVALID_ARGUMENT, "frame out of range");
   *out = pl->info[size_t(frame)];
+  out->fold_threads = pl->fold.threads;
+  out->fold_vec = pl->fold.vec;
+  out->fold_nontemporal = pl->fold.nontemporal;
   return RSFT_OK;
 }
 
@@ -797,6 +870,21 @@ rsft_status rsft_set_option(rsft_plan_t pl, int32_t option, int64_t value) {
   switch (option) {
     case RSFT_OPT_GRAPH: pl->use_graph = value != 0; return RSFT_OK;
     case RSFT_OPT_TIMING: pl->timing = value != 0; return RSFT_OK;
+    case RSFT_OPT_FOLD_THREADS:
+      if (value != 256 && value != 512) return fail(RSFT_ERROR_INVALID_ARGUMENT, "fold threads: 256 or 512");
+      pl->fold.threads = int(value);
+      drop_graphs(pl);
+      return RSFT_OK;
+    case RSFT_OPT_FOLD_VEC:
+      if (value != 2 && value != 4) return fail(RSFT_ERROR_INVALID_ARGUMENT, "fold vec: 2 or 4");
+      if (value == 4 && pl->min_nl < 4) return fail(RSFT_ERROR_UNSUPPORTED, "rows shorter than 4 samples");
+      pl->fold.vec = int(value);
+      drop_graphs(pl);
+      return RSFT_OK;
+    case RSFT_OPT_FOLD_NONTEMPORAL:
+      pl->fold.nontemporal = value != 0 ? 1 : 0;
+      drop_graphs(pl);
+      return RSFT_OK;
     default: return fail(RSFT_ERROR_INVALID_ARGUMENT, "unknown option");
   }
 }

@@ -92,9 +92,11 @@ struct DevPtrs {
 
 // Launch configuration of the fold stage, chosen per plan.
 struct FoldConfig {
-  int threads;   // work-group size
-  int vec;       // complex elements per thread per row
+  int threads;      // work-group size (256 or 512)
+  int vec;          // complex elements per thread per row (2 or 4)
+  int nontemporal;  // 1: streaming (non-temporal) loads of the input
 };
+constexpr int kFoldMaxP = 2048;   // largest threads * vec a plan may be tuned to
 
 // Launchers (kernels.hip). All enqueue on `stream` and return hipError_t.
 int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,

@@ -271,3 +271,22 @@ def test_capacity_overflow_keeps_exact_counts():
         assert abs(int(counts[f]) - len(ref["detections"])) <= n_free
     full.close()
     small.close()
+
+
+def test_autotuned_fold_keeps_parity():
+    """Whatever launch shape the tuner picks, the results stay within the
+    parity contract."""
+    name = "c2_1024x1024"
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name)
+    xd = torch.from_numpy(np.stack(frames)).to("cuda")
+    ms = plan.autotune(xd, repeats=2)
+    assert ms > 0
+    cfg = plan.info()["fold"]
+    assert cfg["threads"] in (256, 512) and cfg["vec"] in (2, 4)
+    plan.execute(xd)
+    recs, counts = plan.detect()
+    gbk = [b.cpu().numpy() for b in plan.buckets()]
+    gfl = [w.cpu().numpy().view(np.uint32) for w in plan.flags()]
+    for f, ref in enumerate(refs):
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f], check_estimates=False)
+    plan.close()

@@ -124,3 +124,35 @@ def test_product_path_has_no_cpu_fallback(rsft, monkeypatch, tmp_path):
     monkeypatch.setattr(rsft, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         rsft.load_library()
+
+
+def test_struct_layouts_match_header(rsft, tmp_path):
+    """The ctypes structures have the sizes and field offsets the C compiler
+    gives the header's structs."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    fields = {
+        "rsft_params": [f for f, _ in rsft.Params._fields_],
+        "rsft_detection": [f for f, _ in rsft.Detection._fields_],
+        "rsft_plan_info_t": [f for f, _ in rsft.PlanInfo._fields_],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rsft.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'  printf("%zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'  printf("%zu\\n", offsetof({st}, {f}));')
+    lines.append("  return 0; }")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = []
+    for cls in (rsft.Params, rsft.Detection, rsft.PlanInfo):
+        want.append(ctypes.sizeof(cls))
+        want.extend(getattr(cls, f).offset for f, _ in cls._fields_)
+    assert got == want
