@@ -52,9 +52,16 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per fold launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+def fold_kernel_key(rounds, fold_cfg):
+    """Template signature of the fold kernel variant a launch shape selects."""
+    nt = "true" if fold_cfg["nontemporal"] else "false"
+    return f"fold_kernel<{min(rounds, 4)}, {fold_cfg['vec']}, {fold_cfg['threads']}, false, {nt}>"
+
+
+def measured_traffic(rounds, fold_cfg):
+    """HBM bytes per fold launch of the chosen variant, from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source;
+    else None."""
     try:
         with open(COUNTERS_FILE) as fh:
             c = json.load(fh)
@@ -62,7 +69,73 @@ def measured_traffic():
         return None
     if c.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return c.get("hbm_bytes_per_launch")
+    v = c.get("variants", {}).get(fold_kernel_key(rounds, fold_cfg))
+    return None if v is None else v["hbm_bytes_per_launch"]
+
+
+def _counter_rows(directory):
+    """(kernel name, counter, value) of every dispatch in rocprofv3's CSV
+    counter-collection output under `directory`."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {directory}")
+    return rows
+
+
+def summarize_counters(fetch_dir, write_dir, command_fetch, command_write):
+    """Turn two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) into HBM bytes per fold launch. Both counters are scaled by what
+    they read for the elementwise negation that makes the second input buffer,
+    a kernel that reads and writes exactly 1 GiB."""
+    calib_bytes = FRAMES * int(np.prod(synth.CONFIGS[CONFIG]["shape"])) * 8
+    out = {"kernel_source_sha256_16": kernel_source_hash(),
+           "commands": {"FETCH_SIZE": command_fetch, "WRITE_SIZE": command_write},
+           "calibration": {"kernel": "elementwise negation (torch.neg) of the 1 GiB input batch",
+                           "bytes_read": calib_bytes, "bytes_written": calib_bytes},
+           "variants": {}}
+    per = {}
+    for counter, directory in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        vals = {}
+        for name, cn, v in _counter_rows(directory):
+            if cn != counter:
+                continue
+            vals.setdefault(name, []).append(v)
+        calib = [np.mean(v) for n, v in vals.items() if "neg" in n]
+        if not calib:
+            raise SystemExit(f"{counter}: no negation kernel in {directory}")
+        scale = calib_bytes / (calib[0] * 1024.0)
+        out["calibration"][counter + "_kib"] = calib[0]
+        out["calibration"][counter + "_scale"] = scale
+        for name, v in vals.items():
+            if "fold_kernel<" not in name:
+                continue
+            key = name[name.index("fold_kernel<"):name.index(">", name.index("fold_kernel<")) + 1]
+            per.setdefault(key, {})[counter] = (float(np.mean(v)), len(v), scale)
+    N = int(np.prod(synth.CONFIGS[CONFIG]["shape"]))
+    B = int(np.prod(synth.CONFIGS[CONFIG]["buckets"]))
+    T = synth.CONFIGS[CONFIG]["rounds"]
+    algorithmic = FRAMES * (N * 8 + T * B * 8)
+    for key, c in sorted(per.items()):
+        if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+            continue
+        fetch = c["FETCH_SIZE"][0] * 1024.0 * c["FETCH_SIZE"][2]
+        write = c["WRITE_SIZE"][0] * 1024.0 * c["WRITE_SIZE"][2]
+        out["variants"][key] = {"fetch_kib": c["FETCH_SIZE"][0], "write_kib": c["WRITE_SIZE"][0],
+                                "dispatches": [c["FETCH_SIZE"][1], c["WRITE_SIZE"][1]],
+                                "hbm_fetch_bytes": fetch, "hbm_write_bytes": write,
+                                "hbm_bytes_per_launch": fetch + write,
+                                "algorithmic_bytes_per_launch": algorithmic,
+                                "traffic_over_algorithmic": (fetch + write) / algorithmic}
+    with open(COUNTERS_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out, indent=1))
 
 
 def score(recs, counts, metas, shape, frames):
@@ -113,9 +186,15 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-comparators", action="store_true")
-    ap.add_argument("--calibration-copy", action="store_true",
-                    help="run one 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the fold HBM-traffic summary from two rocprofv3 --pmc "
+                         "CSV output folders (FETCH_SIZE, WRITE_SIZE) and exit; no GPU")
+    ap.add_argument("--counter-commands", nargs=2, default=["", ""],
+                    help="the two rocprofv3 commands, recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, *args.counter_commands)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -138,7 +217,8 @@ def main():
     frames_np, metas = synth.make_batch(CONFIG, FRAMES)
     log(f"  done in {time.perf_counter() - t0:.1f} s")
     xa = torch.from_numpy(frames_np).to(dev)
-    xb = torch.neg(xa)                      # second buffer: same statistics, other bytes
+    xb = torch.neg(xa)   # second buffer: same statistics, other bytes; this kernel reads
+                         # and writes exactly 1 GiB and calibrates the HBM counters
     bufs = [xa, xb]
     sigma = synth.shared_sigma(CONFIG)
     plan = Plan(shape, buckets, rounds=T, sigma=sigma, window_atten_db=cfg["atten_db"],
@@ -147,15 +227,6 @@ def main():
     tuned_ms = plan.autotune(xa, repeats=5)          # fold launch shape, untimed
     fold_cfg = plan.info()["fold"]
     log(f"autotuned fold: {fold_cfg} ({tuned_ms:.4f} ms)")
-
-    if args.calibration_copy:
-        src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)   # 1 GiB
-        dst = torch.empty_like(src)
-        src.zero_()
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     # graph replay (production launch mode)
     plan.set_option(OPT_TIMING, 0)
@@ -168,7 +239,17 @@ def main():
         plan.execute(bufs[k % 2])
     torch.cuda.synchronize()
     graph_s = time.perf_counter() - t0
-    log(f"graph mode: {graph_s / args.steps * 1e3:.3f} ms/step")
+    # per-replay durations from events around each replay, on the launch stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
+        plan.execute(bufs[k % 2])
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    replay_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    graph_pct = {"p10": float(np.percentile(replay_ms, 10)), "median": float(np.median(replay_ms)),
+                 "p90": float(np.percentile(replay_ms, 90))}
+    log(f"graph mode: {graph_s / args.steps * 1e3:.3f} ms/step, per replay {graph_pct}")
 
     # timed region: eager launches with HIP events around every stage on the
     # stream the kernels run on
@@ -197,7 +278,7 @@ def main():
     fold_ms = stages["fold"]
     fold_bytes = FRAMES * (N * 8 + T * B * 8)        # input once + T x B partial buckets
     achieved = fold_bytes / (fold_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(T, fold_cfg)
     out = {
         "metric": METRIC, "value": value, "unit": "frames/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -217,6 +298,7 @@ def main():
         "stage_ms": stages,
         "fold_launch": fold_cfg,
         "graph_ms_per_step": graph_s / args.steps * 1e3,
+        "graph_replay_ms": graph_pct,
         "detections": {"total": int(counts.sum()), **fused_score},
     }
 
