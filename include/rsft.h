@@ -129,7 +129,7 @@ typedef struct {
  *            row-major index), else 0.
  * magnitude  gain-corrected magnitude: median over the estimation rounds of
  *            |fhat_s[M(i, sigma_s)]| divided by the flat-window response,
- *            an estimate of |DFT(W r)| at the cell (FP32 inputs, FP64 math).
+ *            an estimate of |DFT(W r)| at the cell (FP32).
  * freq[d]    off-grid frequency estimate in cycles/sample, in [0, 1):
  *            (idx[d] + offset)/N_d, offset = vertex of a parabola through the
  *            log magnitudes of the cell and its two neighbours along d,
