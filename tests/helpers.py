@@ -73,3 +73,47 @@ def make_input(shape, K, seed, dtype=np.complex64, snr_db=(-5.0, 15.0), noise_va
 def oracle_plan(shape, buckets, sigma, atten=60.0, flat=-1.0, pfa=1e-3, mu=0, noise_var=1.0):
     return oracle_rsft.OraclePlan(shape, buckets, sigma, atten, flat, pfa,
                                   None if mu == 0 else mu, noise_var)
+
+
+def check_frame(f, oplan, ref, recs, gbk, gfl, check_estimates=True):
+    """Parity of one frame: buckets, flags, detections, votes and (for
+    detections whose votes are fixed) estimates, against the oracle's
+    result `ref` for that frame."""
+    errs = bucket_errors(gbk, ref["buckets"])
+    assert max(errs) <= BUCKET_RTOL, f"frame {f}: bucket errors {errs}"
+    amb = ambiguous(ref["buckets"], ref["gamma"])
+    gflags = unpack_flags(gfl, oplan.B)
+    diff = gflags != ref["flags"]
+    assert not np.any(diff & ~amb), f"frame {f}: flag mismatch outside the ambiguity band"
+    free = free_cells(amb, oplan).ravel()
+    got = cells_from_records(recs, oplan.shape, f)
+    want = set(int(v) for v in ref["detections"])
+    sym = set(got) ^ want
+    assert all(free[c] for c in sym), f"frame {f}: {len(sym)} detection differences on fixed cells"
+    votes = ref["votes"].ravel()
+    for c, r in got.items():
+        if not free[c]:
+            assert int(r["votes"]) == int(votes[c])
+    if not check_estimates:
+        return
+    common = sorted(c for c in set(got) & want if not free[c])
+    est = {e["cell"]: e for e in oracle_rsft.estimate(common, ref["buckets"], oplan)}
+    gains = oracle_rsft.flat_window_gain(oplan)
+    for c in common:
+        r, e = got[c], est[c]
+        assert abs(float(r["magnitude"]) / e["magnitude"] - 1.0) < 1e-3
+        if bool(r["is_peak"]) != e["is_peak"]:
+            # the peak decision may flip only on a near-tie with a neighbour
+            # (FP32 buckets carry ~1e-5 relative error)
+            cell = np.unravel_index(c, oplan.shape)
+            a0 = e["magnitude"]
+            gap = min(abs(a0 - oracle_rsft.cell_magnitude(
+                tuple((cell[d] + o[d] - 1) % oplan.shape[d] for d in range(len(cell))),
+                ref["buckets"], oplan, gains)) / a0
+                for o in np.ndindex(*([3] * len(cell))) if any(v != 1 for v in o))
+            assert gap <= 2e-3, f"cell {c}: peak flag differs with nearest neighbour gap {gap}"
+            continue
+        if e["is_peak"]:
+            for d in range(len(oplan.shape)):
+                dd = (float(r["freq"][d]) - e["freq"][d] + 0.5) % 1.0 - 0.5
+                assert abs(dd * oplan.shape[d]) <= 1e-3, f"cell {c} dim {d}: {dd * oplan.shape[d]} bin"

@@ -20,8 +20,9 @@ import pytest
 import synth
 from oracle import rsft as OR
 
-from helpers import (BUCKET_RTOL, ambiguous, bucket_errors, cells_from_records,
-                     free_cells, make_input, oracle_plan, pack_flags, unpack_flags)
+from helpers import (ambiguous, cells_from_records, free_cells, make_input, oracle_plan,
+                     pack_flags, unpack_flags)
+from helpers import check_frame as _check_frame
 
 torch = pytest.importorskip("torch")
 
@@ -80,47 +81,6 @@ def _run_case(name, per_frame=False, noise="known"):
     oplan = oracle_plan(shape, buckets, sigma, atten, flat, pfa, mu)
     refs = [OR.rsft(x, oplan, noise=noise) for x in frames]
     return plan, oplan, frames, refs, recs, counts, gbk, gfl
-
-
-def _check_frame(f, oplan, ref, recs, gbk, gfl, check_estimates=True):
-    errs = bucket_errors(gbk, ref["buckets"])
-    assert max(errs) <= BUCKET_RTOL, f"frame {f}: bucket errors {errs}"
-    amb = ambiguous(ref["buckets"], ref["gamma"])
-    gflags = unpack_flags(gfl, oplan.B)
-    diff = gflags != ref["flags"]
-    assert not np.any(diff & ~amb), f"frame {f}: flag mismatch outside the ambiguity band"
-    free = free_cells(amb, oplan).ravel()
-    got = cells_from_records(recs, oplan.shape, f)
-    want = set(int(v) for v in ref["detections"])
-    sym = set(got) ^ want
-    assert all(free[c] for c in sym), f"frame {f}: {len(sym)} detection differences on fixed cells"
-    votes = ref["votes"].ravel()
-    for c, r in got.items():
-        if not free[c]:
-            assert int(r["votes"]) == int(votes[c])
-    if not check_estimates:
-        return
-    common = sorted(c for c in set(got) & want if not free[c])
-    est = {e["cell"]: e for e in OR.estimate(common, ref["buckets"], oplan)}
-    gains = OR.flat_window_gain(oplan)
-    for c in common:
-        r, e = got[c], est[c]
-        assert abs(float(r["magnitude"]) / e["magnitude"] - 1.0) < 1e-3
-        if bool(r["is_peak"]) != e["is_peak"]:
-            # the peak decision may flip only on a near-tie with a neighbour
-            # (FP32 buckets carry ~1e-5 relative error)
-            cell = np.unravel_index(c, oplan.shape)
-            a0 = e["magnitude"]
-            gap = min(abs(a0 - OR.cell_magnitude(
-                tuple((cell[d] + o[d] - 1) % oplan.shape[d] for d in range(len(cell))),
-                ref["buckets"], oplan, gains)) / a0
-                for o in np.ndindex(*([3] * len(cell))) if any(v != 1 for v in o))
-            assert gap <= 2e-3, f"cell {c}: peak flag differs with nearest neighbour gap {gap}"
-            continue
-        if e["is_peak"]:
-            for d in range(len(oplan.shape)):
-                dd = (float(r["freq"][d]) - e["freq"][d] + 0.5) % 1.0 - 0.5
-                assert abs(dd * oplan.shape[d]) <= 1e-3, f"cell {c} dim {d}: {dd * oplan.shape[d]} bin"
 
 
 @pytest.mark.parametrize("name", list(CASES))
