@@ -637,7 +637,6 @@ __global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int 
     for (int dd = 0; dd < D; ++dd) sig[s][dd] = uint32_t(d.sigma[s][dd]);
     sinv_last[s] = uint32_t(d.sigma_inv[s][D - 1]);
   }
-  (void)sig;
   const uint32_t nl = nm[D - 1] + 1u;
   const uint32_t lsl = ls[D - 1];
   const uint32_t bl = uint32_t(d.b_last);
@@ -662,9 +661,14 @@ __global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int 
       const int q = lane & 3;
       uint32_t rowpart = 0u;
 #pragma unroll
-      for (int dd = 0; dd < D - 1; ++dd) {
-        const uint32_t cd = uint32_t(iw >> ns[dd]) & nm[dd];
-        rowpart |= (((uint32_t(d.sigma[s][dd]) * cd) & nm[dd]) >> ls[dd]) << bs[dd];
+      for (int ss = 0; ss < TT; ++ss) {   // uniform per round, then picked per lane
+        uint32_t rp = 0u;
+#pragma unroll
+        for (int dd = 0; dd < D - 1; ++dd) {
+          const uint32_t cd = uint32_t(iw >> ns[dd]) & nm[dd];
+          rp |= (((sig[ss][dd] * cd) & nm[dd]) >> ls[dd]) << bs[dd];
+        }
+        if (ss == s) rowpart = rp;
       }
       const int wi = s * words + int(rowpart >> 5);
       uint32_t v = 0u;
@@ -756,104 +760,458 @@ int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunk
 }
 
 // ---------------------------------------------------------------------------
-// scan: offsets[f] = sum_{g<f} min(count_g, cap_g), offsets[nframes] = total;
-// chunk_offsets = rank of each compaction chunk's first detection in its
-// frame (running sum of the chunk counters, in row-major cell order).
+// scan: one work-group per frame turns the frame's chunk counters into
+// chunk_offsets (rank of each compaction chunk's first detection in its
+// frame, a running sum in row-major cell order) and counts[f]. The last
+// work-group to finish (a device-scope counter, released and acquired with
+// fences) computes offsets[f] = sum_{g<f} min(count_g, cap_g),
+// offsets[nframes] = total, and resets the counter for the next launch.
 // ---------------------------------------------------------------------------
 
-constexpr int kScanThreads = 1024;
+constexpr int kScanThreads = 256;
+
+// inclusive scan of v over the work-group; returns it and the block total
+__device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wtot, int64_t& total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int64_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wtot[wave] = incl;
+  __syncthreads();
+  int64_t pre = 0;
+  total = 0;
+#pragma unroll
+  for (int q = 0; q < kScanThreads / 64; ++q) {
+    if (q < wave) pre += wtot[q];
+    total += wtot[q];
+  }
+  __syncthreads();
+  return pre + incl;
+}
 
 __global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t nframes) {
-  __shared__ int64_t buf[kScanThreads];
-  __shared__ int64_t carry;
+  __shared__ int64_t wtot[kScanThreads / 64];
+  __shared__ int is_last;
   const int tid = threadIdx.x;
-  for (int64_t f = tid; f < nframes; f += kScanThreads) {
-    const FrameDesc& d = desc_of(p, f);
-    const int64_t rel = rel_of(p, f);
-    int64_t run = 0;
-    for (int c = 0; c < d.cchunks; ++c) {
-      p.chunk_offsets[d.chunk_off + rel * d.chunk_stride + c] = run;
-      run += p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c];
-    }
-    p.counts[f] = uint32_t(run);
+  const int64_t f = blockIdx.x;
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  const int64_t base = d.chunk_off + rel * d.chunk_stride;
+  int64_t run = 0;
+  for (int c0 = 0; c0 < d.cchunks; c0 += kScanThreads) {
+    const int c = c0 + tid;
+    const int64_t v = c < d.cchunks ? int64_t(p.chunk_counts[base + c]) : 0;
+    int64_t total;
+    const int64_t incl = block_inclusive_scan(v, wtot, total);
+    if (c < d.cchunks) p.chunk_offsets[base + c] = run + incl - v;
+    run += total;
+  }
+  if (tid == 0) {
+    p.counts[f] = run;
+    __threadfence();
+    const unsigned prev = atomicAdd(p.scan_done, 1u);
+    is_last = prev == unsigned(nframes - 1) ? 1 : 0;
   }
   __syncthreads();
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int64_t start = 0; start < nframes; start += kScanThreads) {
-    const int64_t f = start + tid;
+  if (!is_last) return;
+  __threadfence();
+  int64_t carry = 0;
+  for (int64_t g0 = 0; g0 < nframes; g0 += kScanThreads) {
+    const int64_t g = g0 + tid;
     int64_t v = 0;
-    if (f < nframes) {
-      const int64_t c = p.counts[f];
-      const int64_t cap = desc_of(p, f).cap;
-      v = c < cap ? c : cap;
+    if (g < nframes) {
+      const int64_t cnt = __atomic_load_n(p.counts + g, __ATOMIC_RELAXED);
+      const int64_t cap = desc_of(p, g).cap;
+      v = cnt < cap ? cnt : cap;
     }
-    buf[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      const int64_t add = tid >= off ? buf[tid - off] : 0;
-      __syncthreads();
-      buf[tid] += add;
-      __syncthreads();
-    }
-    if (f < nframes) p.offsets[f + 1] = carry + buf[tid];
-    __syncthreads();
-    if (tid == kScanThreads - 1) carry += buf[tid];
-    __syncthreads();
+    int64_t total;
+    const int64_t incl = block_inclusive_scan(v, wtot, total);
+    if (g < nframes) p.offsets[g + 1] = carry + incl;
+    carry += total;
   }
-  if (tid == 0) p.offsets[0] = 0;
+  if (tid == 0) {
+    p.offsets[0] = 0;
+    atomicExch(p.scan_done, 0u);
+  }
 }
 
 int launch_scan(const DevPtrs& p, int64_t nframes, void* stream) {
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, static_cast<hipStream_t>(stream), p,
-                     nframes);
+  if (nframes <= 0) return hipSuccess;
+  if (nframes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_kernel, dim3(unsigned(nframes)), dim3(kScanThreads), 0,
+                     static_cast<hipStream_t>(stream), p, nframes);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// compact: one work-group per (compaction chunk of 2^15 cells, frame). It
-// reads the chunk's bitmap words in row-major order and writes each detected
-// cell (flat index) and its frame at the cell's rank in the frame's record
-// range (popcount + block prefix sum), dropping ranks beyond the frame's
-// capacity.
+// compact + estimate: one work-group per (frame, compaction chunk of 2^15
+// cells). It reads the chunk's bitmap words in row-major order, lists the
+// detected cells in LDS (popcount + block prefix sum) and gives each cell its
+// rank in the frame's record range; then every listed cell gets its record:
+// votes recounted from the flags, gain-corrected magnitude (median over the
+// estimation rounds of |fhat_s[M(i, sigma_s)]| times the inverse flat-window
+// response at the cell's offset inside its bucket), a peak test against the
+// 3^D - 1 circular neighbours (strictly above lower-index neighbours, at
+// least equal to higher-index ones) and per dimension the vertex of a
+// parabola through the log magnitudes at offsets -1, 0, +1, clamped to
+// [-1/2, 1/2]. Ranks beyond the frame's capacity are dropped.
 //
-// estimate: a grid-stride loop over all detections of the batch (balanced
-// whatever the detections' spread), one record per detection: votes recounted
-// from the flags, gain-corrected magnitude (median over the estimation rounds
-// of |fhat_s[M(i, sigma_s)]| times the inverse flat-window response at the
-// cell's offset inside its bucket), a peak test against the 3^D - 1 circular
-// neighbours (strictly above lower-index neighbours, at least equal to
-// higher-index ones) and per dimension the vertex of a parabola through the
-// log magnitudes at offsets -1, 0, +1, clamped to [-1/2, 1/2]. The 3^D
-// neighbourhood is evaluated once into registers (the kernel is specialised
-// on D). FP32 magnitudes, FP64 vertex and frequency.
+// Magnitudes are handled squared: the median, the peak comparisons and the
+// vertex (a ratio of differences of logarithms) are unchanged by squaring,
+// except the mean of the two middle values for an even number of rounds,
+// which is taken on the square roots. FP32 magnitudes, FP64 vertex and
+// frequency.
+//
+// With at least 16 frames, block b serves frames congruent to b mod 8: work-
+// groups are dealt to the eight XCDs round-robin, so each XCD's L2 holds the
+// buckets and flags of only its own frames.
 // ---------------------------------------------------------------------------
 
 constexpr int kEstThreads = 256;
+constexpr int kListMax = kEstThreads * 32;   // cells listed at once (one pass of 32-bit words)
 
-__global__ __launch_bounds__(kEstThreads) void compact_kernel(DevPtrs p) {
-  constexpr int kWordsPerPass = kEstThreads;
-  __shared__ uint32_t list[kWordsPerPass * 32];
+// Per-frame constants of the estimate, uniform across the work-group.
+template <int D, int M>
+struct EstFrame {
+  uint32_t nm[D], lm[D], ls[D], bs[D], ns[D];
+  const float* ig[D];              // inverse flat-window gains per dimension
+  uint32_t sig_est[M][D];
+  const float2* bk_est[M];
+  const uint32_t* fl;              // flags [T][words]
+  const int32_t* sig;              // sigma [kMaxRounds][kMaxDims] of the descriptor
+  int words;
+};
+
+template <int D, int M>
+__device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d, int64_t rel,
+                                           EstFrame<D, M>& e) {
+  const float2* bk = p.buckets + d.bucket_off + rel * d.bucket_stride;
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    e.nm[dd] = uint32_t(d.n[dd] - 1);
+    e.lm[dd] = uint32_t(d.l[dd] - 1);
+    e.ls[dd] = uint32_t(d.lshift[dd]);
+    e.bs[dd] = uint32_t(d.bshift[dd]);
+    e.ns[dd] = uint32_t(d.nshift[dd]);
+    e.ig[dd] = p.inv_gains + d.gain_off[dd];
+  }
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const int s = d.est_rounds[q];
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) e.sig_est[q][dd] = uint32_t(d.sigma[s][dd]);
+    e.bk_est[q] = bk + int64_t(s) * d.B;
+  }
+  e.fl = p.flags + d.flag_off + rel * d.flag_stride;
+  e.sig = &d.sigma[0][0];
+  e.words = d.words;
+}
+
+// Median of M values (an odd-even transposition network on fixed indices);
+// for even M the mean of the middle two is taken on their square roots (the
+// values are squared magnitudes).
+template <int M>
+__device__ __forceinline__ float median_of(float (&v)[M]) {
+#pragma unroll
+  for (int pass = 0; pass < M; ++pass) {
+#pragma unroll
+    for (int q = pass & 1; q + 1 < M; q += 2) {
+      const float lo = fminf(v[q], v[q + 1]);
+      const float hi = fmaxf(v[q], v[q + 1]);
+      v[q] = lo;
+      v[q + 1] = hi;
+    }
+  }
+  if constexpr (M & 1) {
+    return v[M / 2];
+  } else {
+    const float a = 0.5f * (sqrtf(v[M / 2 - 1]) + sqrtf(v[M / 2]));
+    return a * a;
+  }
+}
+
+// Vertex of the parabola through (-1, log am), (0, log a0), (1, log ap) from
+// the squared magnitudes (the factor 2 of the logarithms cancels), clamped to
+// [-1/2, 1/2]; 0 when the points are not concave. Base-2 logarithms of the
+// FP32 powers, vertex in FP64.
+__device__ __forceinline__ double log_parabola_offset(float pm, float p0, float pp) {
+  const float tiny = 1e-37f;
+  const double lm = double(__builtin_amdgcn_logf(pm > tiny ? pm : tiny));
+  const double l0 = double(__builtin_amdgcn_logf(p0 > tiny ? p0 : tiny));
+  const double lp = double(__builtin_amdgcn_logf(pp > tiny ? pp : tiny));
+  const double den = 2.0 * l0 - lm - lp;
+  if (!(den > 0.0)) return 0.0;
+  double v = 0.5 * (lp - lm) / den;
+  v = v < -0.5 ? -0.5 : v;
+  v = v > 0.5 ? 0.5 : v;
+  return v;
+}
+
+// Squared gain-corrected magnitude of neighbour `code` (digit d of code in
+// base 3 is o_d + 1): the median over the estimation rounds, from the
+// per-round squared inverse gains g and bucket offsets jb of the offsets.
+template <int D, int M>
+__device__ __forceinline__ float neighbour_power(const EstFrame<D, M>& e, const float (&g)[M][D][3],
+                                                 const uint32_t (&jb)[M][D][3], int code) {
+  float v[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    uint32_t jf = 0u;
+    float gg = 1.f;
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3;
+      c /= 3;
+      jf |= jb[q][dd][o];
+      gg *= g[q][dd][o];
+    }
+    const float2 b = e.bk_est[q][jf];
+    v[q] = (b.x * b.x + b.y * b.y) * gg;
+  }
+  return median_of<M>(v);
+}
+
+// The same for D >= 3, from the permuted index u0[q][d] = [sigma c]_N of the
+// cell itself (no array indexed at run time).
+template <int D, int M>
+__device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, const uint32_t (&u0)[M][D],
+                                                     int code) {
+  float v[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    uint32_t jf = 0u;
+    float gg = 1.f;
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      const uint32_t u = (u0[q][dd] + e.sig_est[q][dd] * uint32_t(o)) & e.nm[dd];
+      const float ig = e.ig[dd][u & e.lm[dd]];
+      gg *= ig * ig;
+      jf |= (u >> e.ls[dd]) << e.bs[dd];
+    }
+    const float2 b = e.bk_est[q][jf];
+    v[q] = (b.x * b.x + b.y * b.y) * gg;
+  }
+  return median_of<M>(v);
+}
+
+// One record. D <= 2: the 3^D neighbourhood lives in registers (loops
+// unrolled); D >= 3: its 27 or 81 values are kept in this thread's LDS
+// column `pcol` (stride kEstThreads) and visited by ordinary loops.
+template <int D, int M>
+__device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int64_t f,
+                                             unsigned long long flat, rsft_detection* out,
+                                             float* pcol) {
+  constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
+  constexpr bool kRegs = D <= 2;
+  constexpr int kCentre = (kNb - 1) / 2;
+  uint32_t cell[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) cell[dd] = uint32_t(flat >> e.ns[dd]) & e.nm[dd];
+  int votes = 0;
+  for (int s = 0; s < T; ++s) {
+    uint32_t jf = 0u;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) {
+      const uint32_t u = (uint32_t(e.sig[s * kMaxDims + dd]) * cell[dd]) & e.nm[dd];
+      jf |= (u >> e.ls[dd]) << e.bs[dd];
+    }
+    votes += int((e.fl[int64_t(s) * e.words + (jf >> 5)] >> (jf & 31u)) & 1u);
+  }
+  float preg[kRegs ? kNb : 1];
+  if constexpr (kRegs) {
+    // Per round and dimension the three offsets o_d = -1, 0, 1 share one
+    // permuted index, [sigma (c + o)]_N = [sigma c + sigma o]_N, so their
+    // squared inverse gains and bucket offsets are formed once.
+    float g[M][D][3];
+    uint32_t jb[M][D][3];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd) {
+        const uint32_t sg = e.sig_est[q][dd];
+        const uint32_t u0 = sg * cell[dd];
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          const uint32_t u = (u0 + sg * uint32_t(o - 1)) & e.nm[dd];
+          const float ig = e.ig[dd][u & e.lm[dd]];
+          g[q][dd][o] = ig * ig;
+          jb[q][dd][o] = (u >> e.ls[dd]) << e.bs[dd];
+        }
+      }
+    }
+#pragma unroll
+    for (int code = 0; code < kNb; ++code) preg[code] = neighbour_power<D, M>(e, g, jb, code);
+  } else {
+    uint32_t u0[M][D];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd) u0[q][dd] = e.sig_est[q][dd] * cell[dd];
+    }
+#pragma unroll 1
+    for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_dyn<D, M>(e, u0, code);
+  }
+  auto P = [&](int code) -> float {
+    if constexpr (kRegs) return preg[code];
+    else return pcol[code * kEstThreads];
+  };
+  const float p0 = P(kCentre);
+  bool peak = true;
+  auto visit = [&](int code) {
+    if (code == kCentre) return;
+    unsigned long long nflat = 0ull;
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      const uint32_t nb = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
+      nflat |= (unsigned long long)nb << e.ns[dd];
+    }
+    if (nflat == flat) return;       // a dimension of length <= 2 wraps onto the cell
+    const float pc = P(code);
+    if (nflat < flat) {
+      if (!(p0 > pc)) peak = false;
+    } else {
+      if (!(p0 >= pc)) peak = false;
+    }
+  };
+  if constexpr (kRegs) {
+#pragma unroll
+    for (int code = 0; code < kNb; ++code) visit(code);
+  } else {
+#pragma unroll 1
+    for (int code = 0; code < kNb; ++code) visit(code);
+  }
+  rsft_detection rec;
+  rec.frame = f;
+#pragma unroll
+  for (int dd = 0; dd < kMaxDims; ++dd) {
+    rec.idx[dd] = 0;
+    rec.freq[dd] = 0.0;
+  }
+  int stride = 1;
+#pragma unroll
+  for (int dd = D - 1; dd >= 0; --dd) {
+    const double delta = log_parabola_offset(P(kCentre - stride), p0, P(kCentre + stride));
+    double fr = (double(cell[dd]) + delta) / double(e.nm[dd] + 1u);
+    if (fr < 0.0) fr += 1.0;
+    if (fr >= 1.0) fr -= 1.0;
+    rec.idx[dd] = cell[dd];
+    rec.freq[dd] = fr;
+    stride *= 3;
+  }
+  rec.votes = votes;
+  rec.is_peak = peak ? 1 : 0;
+  rec.magnitude = sqrtf(p0);
+  rec.reserved = 0.f;
+  *out = rec;
+}
+
+template <int D, int M>
+__device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc& d, int64_t f,
+                                              int64_t rel, int T, const uint32_t* list, int n,
+                                              unsigned long long cell0, rsft_detection* out,
+                                              int64_t room, float* pcol) {
+  EstFrame<D, M> e;
+  load_frame<D, M>(p, d, rel, e);
+  const int lim = int(n < room ? n : room);
+  for (int q = int(threadIdx.x); q < lim; q += kEstThreads)
+    write_record<D, M>(e, T, f, cell0 | (unsigned long long)list[q], out + q, pcol);
+}
+
+template <int D, int M>
+__global__ __launch_bounds__(kEstThreads) void compact_estimate_kernel(DevPtrs p, int T,
+                                                                       int64_t nframes,
+                                                                       int max_cchunks,
+                                                                       int xcd_groups) {
+  constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
+  __shared__ uint32_t list[kListMax];
   __shared__ uint32_t wsum[kEstThreads / 64];
-  const int c = blockIdx.x;
-  const int64_t f = blockIdx.y;
+  __shared__ float pbuf[D >= 3 ? kNb * kEstThreads : 1];
+  int64_t f;
+  int c;
+  const int64_t b = blockIdx.x;
+  if (xcd_groups) {
+    const int64_t k = b >> 3;
+    f = (k / max_cchunks) * 8 + (b & 7);
+    c = int(k % max_cchunks);
+  } else {
+    f = b / max_cchunks;
+    c = int(b % max_cchunks);
+  }
+  if (f >= nframes) return;
   const FrameDesc& d = desc_of(p, f);
-  if (c >= d.cchunks) return;
+  if (c >= d.cchunks || d.ndim != D || d.n_est != M) return;
   const int64_t rel = rel_of(p, f);
   const int64_t ck = d.chunk_off + rel * d.chunk_stride + c;
   if (p.chunk_counts[ck] == 0u) return;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
   const int64_t rank0 = p.chunk_offsets[ck];
   const int64_t cap = d.cap;
   if (rank0 >= cap) return;
-  const int64_t out0 = p.offsets[f];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  rsft_detection* out = p.records + p.offsets[f] + rank0;
   const uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride;
   const int w0 = c << (kCompactShift - 5);
   const int wend = min(d.bitmap_words, w0 + (1 << (kCompactShift - 5)));
+  const unsigned long long cell0 = (unsigned long long)c << kCompactShift;
+  const int64_t room0 = cap - rank0;
+  float* pcol = pbuf + threadIdx.x;
+  const uint32_t chunk_count = p.chunk_counts[ck];
+  if (chunk_count <= uint32_t(kListMax)) {
+    // one pass: thread t lists the set bits of words w0 + 4t .. w0 + 4t + 3
+    constexpr int kWpt = (1 << (kCompactShift - 5)) / kEstThreads;
+    uint32_t wv[kWpt];
+    int pc = 0;
+#pragma unroll
+    for (int q = 0; q < kWpt; ++q) {
+      const int w = w0 + tid * kWpt + q;
+      wv[q] = w < wend ? bm[w] : 0u;
+      pc += __popc(wv[q]);
+    }
+    int incl = pc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = uint32_t(incl);
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < kEstThreads / 64; ++q) {
+      if (q < wave) base += int(wsum[q]);
+      total += int(wsum[q]);
+    }
+    int k = base + incl - pc;
+#pragma unroll
+    for (int q = 0; q < kWpt; ++q) {
+      uint32_t word = wv[q];
+      const uint32_t wrel = uint32_t(tid * kWpt + q) << 5;
+      while (word) {
+        const int bit = __ffs(word) - 1;
+        word &= word - 1u;
+        if (k < kListMax) list[k] = wrel | uint32_t(bit);
+        ++k;
+      }
+    }
+    __syncthreads();
+    estimate_list<D, M>(p, d, f, rel, T, list, min(total, kListMax), cell0, out, room0, pcol);
+    return;
+  }
+  // dense chunk: passes of kEstThreads words
   int64_t running = 0;
-  for (int wb = w0; wb < wend; wb += kWordsPerPass) {
+  for (int wb = w0; wb < wend; wb += kEstThreads) {
     const int w = wb + tid;
     uint32_t word = w < wend ? bm[w] : 0u;
     const int pc = __popc(word);
@@ -878,230 +1236,36 @@ __global__ __launch_bounds__(kEstThreads) void compact_kernel(DevPtrs p) {
       list[k++] = (uint32_t(w - w0) << 5) | uint32_t(bit);
     }
     __syncthreads();
-    for (int q = tid; q < total; q += kEstThreads) {
-      const int64_t rank = rank0 + running + q;
-      if (rank < cap) {
-        p.det_cell[out0 + rank] = ((unsigned long long)c << kCompactShift) | (unsigned long long)list[q];
-        p.det_frame[out0 + rank] = int32_t(f);
-      }
-    }
+    estimate_list<D, M>(p, d, f, rel, T, list, total, cell0, out + running, room0 - running, pcol);
     running += total;
+    if (running >= room0) return;   // uniform: the frame's capacity is used up
     __syncthreads();
   }
 }
 
-// Per-frame constants of the estimate stage, held in registers.
 template <int D>
-struct EstParams {
-  uint32_t nm[D], lm[D], ls[D], bs[D], ns[D];
-  const float* ig[D];              // inverse flat-window gains per dimension
-  int n_est;
-  uint32_t sig_est[kMaxEstRounds][D];
-  const float2* bk_est[kMaxEstRounds];
-  const uint32_t* fl;              // flags [T][words]
-  const int32_t* sig;              // sigma [kMaxRounds][kMaxDims] of the descriptor
-  int words;
-};
-
-template <int D>
-__device__ __forceinline__ void load_params(const DevPtrs& p, const FrameDesc& d, int64_t rel,
-                                            EstParams<D>& e) {
-  const float2* bk = p.buckets + d.bucket_off + rel * d.bucket_stride;
-#pragma unroll
-  for (int dd = 0; dd < D; ++dd) {
-    e.nm[dd] = uint32_t(d.n[dd] - 1);
-    e.lm[dd] = uint32_t(d.l[dd] - 1);
-    e.ls[dd] = uint32_t(d.lshift[dd]);
-    e.bs[dd] = uint32_t(d.bshift[dd]);
-    e.ns[dd] = uint32_t(d.nshift[dd]);
-    e.ig[dd] = p.inv_gains + d.gain_off[dd];
-  }
-  e.n_est = d.n_est;
-#pragma unroll
-  for (int q = 0; q < kMaxEstRounds; ++q) {
-    const int s = q < e.n_est ? d.est_rounds[q] : 0;
-#pragma unroll
-    for (int dd = 0; dd < D; ++dd) e.sig_est[q][dd] = uint32_t(d.sigma[s][dd]);
-    e.bk_est[q] = bk + int64_t(s) * d.B;
-  }
-  e.fl = p.flags + d.flag_off + rel * d.flag_stride;
-  e.sig = &d.sigma[0][0];
-  e.words = d.words;
-}
-
-template <int D>
-__device__ __forceinline__ float cell_magnitude(const EstParams<D>& e, const uint32_t (&cell)[D]) {
-  float v[kMaxEstRounds];
-  const int m = e.n_est;
-#pragma unroll
-  for (int q = 0; q < kMaxEstRounds; ++q) {
-    v[q] = 0.f;
-    if (q < m) {
-      uint32_t jf = 0u;
-      float ig = 1.f;
-#pragma unroll
-      for (int dd = 0; dd < D; ++dd) {
-        const uint32_t u = (e.sig_est[q][dd] * cell[dd]) & e.nm[dd];
-        ig *= e.ig[dd][u & e.lm[dd]];
-        jf |= (u >> e.ls[dd]) << e.bs[dd];
-      }
-      const float2 b = e.bk_est[q][jf];
-      v[q] = sqrtf(b.x * b.x + b.y * b.y) * ig;
-    }
-  }
-  // sort the m <= kMaxEstRounds values (odd-even transposition, fixed indices)
-#pragma unroll
-  for (int pass = 0; pass < kMaxEstRounds; ++pass) {
-#pragma unroll
-    for (int q = pass & 1; q + 1 < kMaxEstRounds; q += 2) {
-      if (q + 1 < m && v[q] > v[q + 1]) {
-        const float t = v[q];
-        v[q] = v[q + 1];
-        v[q + 1] = t;
-      }
-    }
-  }
-  float med = v[0];
-#pragma unroll
-  for (int q = 1; q < kMaxEstRounds; ++q) {
-    if (q == m / 2) med = (m & 1) ? v[q] : 0.5f * (v[q - 1] + v[q]);
-  }
-  return med;
-}
-
-// Vertex of the parabola through (-1, log am), (0, log a0), (1, log ap),
-// clamped to [-1/2, 1/2]; 0 when the points are not concave. The logarithms
-// of the FP32 magnitudes are taken in FP32 (base 2: the ratio is the same in
-// any base), the vertex in FP64.
-__device__ __forceinline__ double log_parabola_offset(float am, float a0, float ap) {
-  const float tiny = 1e-30f;
-  const double lm = double(__builtin_amdgcn_logf(am > tiny ? am : tiny));
-  const double l0 = double(__builtin_amdgcn_logf(a0 > tiny ? a0 : tiny));
-  const double lp = double(__builtin_amdgcn_logf(ap > tiny ? ap : tiny));
-  const double den = 2.0 * l0 - lm - lp;
-  if (!(den > 0.0)) return 0.0;
-  double v = 0.5 * (lp - lm) / den;
-  v = v < -0.5 ? -0.5 : v;
-  v = v > 0.5 ? 0.5 : v;
-  return v;
-}
-
-template <int D>
-__device__ void write_record(const EstParams<D>& e, int T, int64_t f, unsigned long long flat,
-                             rsft_detection* out) {
-  constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
-  uint32_t cell[D];
-#pragma unroll
-  for (int dd = 0; dd < D; ++dd) cell[dd] = uint32_t(flat >> e.ns[dd]) & e.nm[dd];
-  int votes = 0;
-  for (int s = 0; s < T; ++s) {
-    uint32_t jf = 0u;
-#pragma unroll
-    for (int dd = 0; dd < D; ++dd) {
-      const uint32_t u = (uint32_t(e.sig[s * kMaxDims + dd]) * cell[dd]) & e.nm[dd];
-      jf |= (u >> e.ls[dd]) << e.bs[dd];
-    }
-    votes += int((e.fl[int64_t(s) * e.words + (jf >> 5)] >> (jf & 31u)) & 1u);
-  }
-  // magnitudes of the 3^D neighbourhood; code = sum_d (o_d + 1) 3^(D-1-d)
-  float A[kNb];
-  constexpr int kCentre = (kNb - 1) / 2;
-#pragma unroll
-  for (int code = 0; code < kNb; ++code) {
-    uint32_t nb[D];
-    int c = code;
-#pragma unroll
-    for (int dd = D - 1; dd >= 0; --dd) {
-      const int o = c % 3 - 1;
-      c /= 3;
-      nb[dd] = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
-    }
-    A[code] = cell_magnitude<D>(e, nb);
-  }
-  const float a0 = A[kCentre];
-  bool peak = true;
-#pragma unroll
-  for (int code = 0; code < kNb; ++code) {
-    if (code == kCentre) continue;
-    uint32_t nb[D];
-    int c = code;
-#pragma unroll
-    for (int dd = D - 1; dd >= 0; --dd) {
-      const int o = c % 3 - 1;
-      c /= 3;
-      nb[dd] = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
-    }
-    unsigned long long nflat = 0ull;
-#pragma unroll
-    for (int dd = 0; dd < D; ++dd) nflat |= (unsigned long long)nb[dd] << e.ns[dd];
-    if (nflat == flat) continue;
-    if (nflat < flat) {
-      if (!(a0 > A[code])) peak = false;
-    } else {
-      if (!(a0 >= A[code])) peak = false;
-    }
-  }
-  rsft_detection rec;
-  rec.frame = f;
-#pragma unroll
-  for (int dd = 0; dd < kMaxDims; ++dd) {
-    rec.idx[dd] = 0;
-    rec.freq[dd] = 0.0;
-  }
-  int stride = 1;
-#pragma unroll
-  for (int dd = D - 1; dd >= 0; --dd) {
-    const double delta = log_parabola_offset(A[kCentre - stride], a0, A[kCentre + stride]);
-    double fr = (double(cell[dd]) + delta) / double(e.nm[dd] + 1u);
-    if (fr < 0.0) fr += 1.0;
-    if (fr >= 1.0) fr -= 1.0;
-    rec.idx[dd] = cell[dd];
-    rec.freq[dd] = fr;
-    stride *= 3;
-  }
-  rec.votes = votes;
-  rec.is_peak = peak ? 1 : 0;
-  rec.magnitude = a0;
-  rec.reserved = 0.f;
-  *out = rec;
-}
-
-template <int D>
-__global__ __launch_bounds__(kEstThreads) void estimate_kernel(DevPtrs p, int T, int64_t nframes) {
-  const int64_t total = p.offsets[nframes];
-  const int64_t stride = int64_t(gridDim.x) * kEstThreads;
-  if (p.uniform) {
-    const FrameDesc& d0 = p.descs[0];
-    if (d0.ndim != D) return;
-    for (int64_t k = int64_t(blockIdx.x) * kEstThreads + threadIdx.x; k < total; k += stride) {
-      const int64_t f = p.det_frame[k];
-      EstParams<D> e;
-      load_params<D>(p, d0, f, e);
-      write_record<D>(e, T, f, p.det_cell[k], p.records + k);
-    }
-  } else {
-    for (int64_t k = int64_t(blockIdx.x) * kEstThreads + threadIdx.x; k < total; k += stride) {
-      const int64_t f = p.det_frame[k];
-      const FrameDesc& d = p.descs[f];
-      if (d.ndim != D) continue;
-      EstParams<D> e;
-      load_params<D>(p, d, 0, e);
-      write_record<D>(e, T, f, p.det_cell[k], p.records + k);
-    }
-  }
+static void launch_estimate_d(const DevPtrs& p, dim3 grid, hipStream_t st, int T, int64_t nframes,
+                              int max_cchunks, int xcd, int est_mask) {
+  if (est_mask & 2) hipLaunchKernelGGL((compact_estimate_kernel<D, 1>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask & 4) hipLaunchKernelGGL((compact_estimate_kernel<D, 2>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask & 8) hipLaunchKernelGGL((compact_estimate_kernel<D, 3>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask & 16) hipLaunchKernelGGL((compact_estimate_kernel<D, 4>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask & 32) hipLaunchKernelGGL((compact_estimate_kernel<D, 5>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
 }
 
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
-                    void* stream) {
+                    int est_mask, void* stream) {
   if (nframes <= 0) return hipSuccess;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(compact_kernel, dim3(unsigned(max_cchunks), unsigned(nframes)), dim3(kEstThreads), 0,
-                     st, p);
-  const dim3 grid(2048u);
-  if (dims_mask & 1) hipLaunchKernelGGL(estimate_kernel<1>, grid, dim3(kEstThreads), 0, st, p, T, nframes);
-  if (dims_mask & 2) hipLaunchKernelGGL(estimate_kernel<2>, grid, dim3(kEstThreads), 0, st, p, T, nframes);
-  if (dims_mask & 4) hipLaunchKernelGGL(estimate_kernel<3>, grid, dim3(kEstThreads), 0, st, p, T, nframes);
-  if (dims_mask & 8) hipLaunchKernelGGL(estimate_kernel<4>, grid, dim3(kEstThreads), 0, st, p, T, nframes);
+  const int xcd = nframes >= 16 ? 1 : 0;
+  const int64_t rows = xcd ? ((nframes + 7) / 8) * 8 : nframes;
+  const int64_t blocks = rows * int64_t(max_cchunks);
+  if (blocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+  const dim3 grid{unsigned(blocks), 1u, 1u};
+  if (dims_mask & 1) launch_estimate_d<1>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 2) launch_estimate_d<2>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 4) launch_estimate_d<3>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 8) launch_estimate_d<4>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
   return hipGetLastError();
 }
 

@@ -70,13 +70,13 @@ struct rsft_plan_s {
   rsft::FoldConfig fold{256, 4, 0};
   int num_cus = 256;
   int64_t min_nl = 0;
-  int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, rows_ok = 1;
+  int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, rows_ok = 1, est_nmask = 0;
   int64_t tiles_per_frame = 0;   // uniform plans
   int64_t ntiles_uneven = 0;     // uneven plans
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles;
   DeviceBuffer d_part, d_buckets, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
-      d_offsets, d_records, d_det_cell, d_det_frame;
+      d_offsets, d_records, d_scan_done;
   rsft::DevPtrs ptrs{};
   // state of the last execute
   int64_t last_batch = -1;
@@ -409,7 +409,7 @@ void free_plan(rsft_plan_s* pl) {
                           &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_part,
                           &pl->d_buckets, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
-                          &pl->d_det_cell, &pl->d_det_frame};
+                          &pl->d_scan_done};
   for (auto* b : bufs) release(*b);
   delete pl;
 }
@@ -476,6 +476,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     pl->max_words = std::max(pl->max_words, d.words);
     pl->max_cchunks = std::max(pl->max_cchunks, d.cchunks);
     pl->dims_mask |= 1 << (d.ndim - 1);
+    pl->est_nmask |= 1 << d.n_est;
     if (d.n_last < 64 || d.n_last > 4096) pl->rows_ok = 0;
     int sum_tw = 0;
     for (int k = 0; k < d.ndim; ++k) sum_tw += d.b[k];
@@ -524,11 +525,11 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   HIP_TRY(hipMemset(pl->d_bitmap.ptr, 0, pl->d_bitmap.bytes));  // kept clear by the compaction
   if ((st = alloc(pl->d_chunk_counts, size_t(chunk_off) * sizeof(uint32_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_chunk_offsets, size_t(chunk_off) * sizeof(int64_t))) != RSFT_OK) return st;
-  if ((st = alloc(pl->d_counts, size_t(pl->max_frames) * sizeof(uint32_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_counts, size_t(pl->max_frames) * sizeof(int64_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_offsets, size_t(pl->max_frames + 1) * sizeof(int64_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_records, size_t(rec_total) * sizeof(rsft_detection))) != RSFT_OK) return st;
-  if ((st = alloc(pl->d_det_cell, size_t(rec_total) * sizeof(unsigned long long))) != RSFT_OK) return st;
-  if ((st = alloc(pl->d_det_frame, size_t(rec_total) * sizeof(int32_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_scan_done, sizeof(uint32_t))) != RSFT_OK) return st;
+  HIP_TRY(hipMemset(pl->d_scan_done.ptr, 0, sizeof(uint32_t)));   // the scan keeps it 0 between launches
   HIP_TRY(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
 
   auto& q = pl->ptrs;
@@ -547,11 +548,10 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.bitmap = static_cast<uint32_t*>(pl->d_bitmap.ptr);
   q.chunk_counts = static_cast<uint32_t*>(pl->d_chunk_counts.ptr);
   q.chunk_offsets = static_cast<int64_t*>(pl->d_chunk_offsets.ptr);
-  q.counts = static_cast<uint32_t*>(pl->d_counts.ptr);
+  q.counts = static_cast<int64_t*>(pl->d_counts.ptr);
   q.offsets = static_cast<int64_t*>(pl->d_offsets.ptr);
   q.records = static_cast<rsft_detection*>(pl->d_records.ptr);
-  q.det_cell = static_cast<unsigned long long*>(pl->d_det_cell.ptr);
-  q.det_frame = static_cast<int32_t*>(pl->d_det_frame.ptr);
+  q.scan_done = static_cast<uint32_t*>(pl->d_scan_done.ptr);
   q.tiles = static_cast<const int32_t*>(pl->d_tiles.ptr);
   return RSFT_OK;
 }
@@ -604,7 +604,7 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
   LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, st));
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   LAUNCH_TRY(rsft::launch_scan(q, batch, st));
-  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, st));
+  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask, st));
   if (ev) HIP_TRY(hipEventRecord(ev[4], st));
   return RSFT_OK;
 }
@@ -771,7 +771,7 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
   }
   if (batch > 0) {
     LAUNCH_TRY(rsft::launch_scan(q, batch, s));
-    LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, s));
+    LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask, s));
   }
   return RSFT_OK;
 }
@@ -788,7 +788,7 @@ rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* strea
   const auto& q = pl->ptrs;
   LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, s));
   LAUNCH_TRY(rsft::launch_scan(q, batch, s));
-  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, s));
+  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask, s));
   return RSFT_OK;
 }
 
@@ -800,8 +800,8 @@ rsft_status rsft_detection_count(rsft_plan_t pl, void* stream, int64_t* total) {
   if (batch == 0) return RSFT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipStreamSynchronize(s));
-  std::vector<uint32_t> counts(static_cast<size_t>(batch));
-  HIP_TRY(hipMemcpy(counts.data(), pl->d_counts.ptr, counts.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  std::vector<int64_t> counts(static_cast<size_t>(batch));
+  HIP_TRY(hipMemcpy(counts.data(), pl->d_counts.ptr, counts.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
   for (auto c : counts) *total += c;
   return RSFT_OK;
 }
@@ -816,14 +816,14 @@ rsft_status rsft_detect(rsft_plan_t pl, void* stream, rsft_detection* h_out, int
   if (batch == 0) return RSFT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipStreamSynchronize(s));
-  std::vector<uint32_t> counts(static_cast<size_t>(batch));
+  std::vector<int64_t> counts(static_cast<size_t>(batch));
   std::vector<int64_t> offsets(static_cast<size_t>(batch + 1));
-  HIP_TRY(hipMemcpy(counts.data(), pl->d_counts.ptr, counts.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(counts.data(), pl->d_counts.ptr, counts.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(offsets.data(), pl->d_offsets.ptr, offsets.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
   bool truncated = false;
   for (int64_t f = 0; f < batch; ++f) {
     if (h_counts) h_counts[f] = counts[size_t(f)];
-    if (counts[size_t(f)] > uint32_t(pl->descs[size_t(pl->uniform ? 0 : f)].cap)) truncated = true;
+    if (counts[size_t(f)] > pl->descs[size_t(pl->uniform ? 0 : f)].cap) truncated = true;
   }
   const int64_t stored = offsets[size_t(batch)];
   const int64_t ncopy = std::min(stored, capacity);

@@ -82,10 +82,9 @@ struct DevPtrs {
   uint32_t* bitmap;            // detected cells, cleared again by the compaction
   uint32_t* chunk_counts;      // detections per compaction chunk
   int64_t* chunk_offsets;      // rank of a chunk's first detection within its frame
-  uint32_t* counts;            // [frames]
-  int64_t* offsets;            // [frames + 1]
-  unsigned long long* det_cell;  // detected cells in record order
-  int32_t* det_frame;            // their frames
+  int64_t* counts;             // [frames] exact detections per frame
+  int64_t* offsets;            // [frames + 1] first record of each frame
+  uint32_t* scan_done;         // frames finished by the scan (0 between launches)
   rsft_detection* records;
   const int32_t* tiles;        // uneven plans: [ntiles][3] (frame, class, chunk)
 };
@@ -107,8 +106,9 @@ int launch_dft(const DevPtrs& p, int64_t nframes, int T, int maxB, int sum_tw,
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
                 int max_words, int dims_mask, int rows_ok, int frame0, void* stream);
 int launch_scan(const DevPtrs& p, int64_t nframes, void* stream);
+// est_mask: bit m set when some frame uses m estimation rounds (1..5)
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
-                    void* stream);
+                    int est_mask, void* stream);
 // Per-frame comparator path.
 int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t frame,
                       int round, int B, void* stream);
