@@ -293,73 +293,109 @@ int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
 // the paper's indexing, and sets flag bits |fhat|^2 >= gamma_s with ballots.
 // ---------------------------------------------------------------------------
 
-constexpr int kDftThreads = 256;
-constexpr int kMaxKTiles = 8;  // n <= 128 per dimension
+constexpr int kDftThreads = 1024;
+constexpr int kDftWaves = kDftThreads / 64;
+constexpr int kDftItems = 4;   // output tiles per wave between barriers
 
-__device__ __forceinline__ void mode_product(float* __restrict__ re, float* __restrict__ im,
-                                             const float2* __restrict__ tw, int n, int inner_shift,
-                                             int nlines, int grp) {
+// LDS position of bucket index idx: one pad float after every row of the
+// last dimension (row length 2^nl_shift), so that 16 lines read at the same
+// position along that dimension fall into different banks.
+__device__ __forceinline__ int lds_at(int idx, int nl_shift) { return idx + (idx >> nl_shift); }
+
+// One 16-line x 16-output tile of Y = D_n X along a dimension: lines
+// grp*16 .. grp*16+15, outputs k = kt*16 .. kt*16+15.
+__device__ __forceinline__ void dft_tile(const float* __restrict__ re, const float* __restrict__ im,
+                                         const float2* __restrict__ tw, int n, int inner_shift,
+                                         int nlines, int nl_shift, int grp, int kt, floatx4& accR,
+                                         floatx4& accI) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15;
   const int krow = lane >> 4;
   const int line = grp * 16 + col;
   const bool lvalid = line < nlines;
   const int inner = 1 << inner_shift;
-  const int o = line >> inner_shift;
-  const int ii = line & (inner - 1);
-  const int base = o * n * inner + ii;
-  const int nkt = (n + 15) >> 4;
-  floatx4 accR[kMaxKTiles], accI[kMaxKTiles];
-#pragma unroll
-  for (int kt = 0; kt < kMaxKTiles; ++kt) {
-    accR[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    accI[kt] = floatx4{0.f, 0.f, 0.f, 0.f};
-  }
+  const int base = (line >> inner_shift) * n * inner + (line & (inner - 1));
+  const int k = kt * 16 + col;
+  accR = floatx4{0.f, 0.f, 0.f, 0.f};
+  accI = floatx4{0.f, 0.f, 0.f, 0.f};
   for (int b0 = 0; b0 < n; b0 += 4) {
     const int b = b0 + krow;
-    float xr = 0.f, xi = 0.f;
+    float xr = 0.f, xi = 0.f, dr = 0.f, di = 0.f;
     if (lvalid && b < n) {
-      xr = re[base + b * inner];
-      xi = im[base + b * inner];
+      const int at = lds_at(base + b * inner, nl_shift);
+      xr = re[at];
+      xi = im[at];
     }
-#pragma unroll
-    for (int kt = 0; kt < kMaxKTiles; ++kt) {
-      if (kt < nkt) {
-        const int k = kt * 16 + col;
-        float dr = 0.f, di = 0.f;
-        if (k < n && b < n) {
-          const float2 t = tw[(k * b) & (n - 1)];
-          dr = t.x;
-          di = t.y;
-        }
-        accR[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xr, accR[kt], 0, 0, 0);
-        accR[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-di, xi, accR[kt], 0, 0, 0);
-        accI[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xi, accI[kt], 0, 0, 0);
-        accI[kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(di, xr, accI[kt], 0, 0, 0);
-      }
+    if (k < n && b < n) {
+      const float2 t = tw[(k * b) & (n - 1)];
+      dr = t.x;
+      di = t.y;
     }
-  }
-#pragma unroll
-  for (int kt = 0; kt < kMaxKTiles; ++kt) {
-    if (kt < nkt) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = kt * 16 + krow * 4 + r;
-        if (k < n && lvalid) {
-          re[base + k * inner] = accR[kt][r];
-          im[base + k * inner] = accI[kt][r];
-        }
-      }
-    }
+    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xr, accR, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-di, xi, accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xi, accI, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(di, xr, accI, 0, 0, 0);
   }
 }
 
-__global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int maxB, int frame0,
-                                                          int identity, int nchunks_override) {
+// The DFT along one dimension of length n for all B / n lines, in place.
+// Work items are (line group, output tile) pairs in group-major order; a
+// round of kDftWaves * R items holds whole groups (the tiles per group,
+// ceil(n/16) <= 8, divide 16), every item of a round is computed before any
+// of its outputs is written, and rounds touch disjoint lines.
+__device__ __forceinline__ void mode_product(float* __restrict__ re, float* __restrict__ im,
+                                             const float2* __restrict__ tw, int n, int inner_shift,
+                                             int nlines, int nl_shift) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;
+  const int krow = lane >> 4;
+  const int nkt = (n + 15) >> 4;
+  const int items = ((nlines + 15) >> 4) * nkt;
+  const int per_wave = (items + kDftWaves - 1) / kDftWaves;
+  const int R = per_wave < kDftItems ? per_wave : kDftItems;
+  const int inner = 1 << inner_shift;
+  for (int r0 = 0; r0 < items; r0 += R * kDftWaves) {
+    floatx4 accR[kDftItems], accI[kDftItems];
+#pragma unroll
+    for (int q = 0; q < kDftItems; ++q) {
+      const int item = r0 + q * kDftWaves + wave;
+      if (q < R && item < items)
+        dft_tile(re, im, tw, n, inner_shift, nlines, nl_shift, item / nkt, item % nkt, accR[q], accI[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kDftItems; ++q) {
+      const int item = r0 + q * kDftWaves + wave;
+      if (q < R && item < items) {
+        const int grp = item / nkt;
+        const int kt = item % nkt;
+        const int line = grp * 16 + col;
+        if (line < nlines) {
+          const int base = (line >> inner_shift) * n * inner + (line & (inner - 1));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = kt * 16 + krow * 4 + r;
+            if (k < n) {
+              const int at = lds_at(base + k * inner, nl_shift);
+              re[at] = accR[q][r];
+              im[at] = accI[q][r];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int plane, int pad,
+                                                          int frame0, int identity,
+                                                          int nchunks_override) {
   extern __shared__ float smem[];
   float* re = smem;
-  float* im = smem + maxB;
-  float2* tws = reinterpret_cast<float2*>(smem + 2 * maxB);
+  float* im = smem + plane;
+  float2* tws = reinterpret_cast<float2*>(smem + 2 * plane);
   __shared__ uint32_t sel_prefix, sel_rank;
   __shared__ uint32_t hist[256];
 
@@ -368,10 +404,11 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   const FrameDesc& d = desc_of(p, f);
   const int64_t rel = rel_of(p, f);
   const int B = d.B;
+  // log2 of the last dimension's B (pads on), or no pads
+  const int nls = pad ? __builtin_ctz(uint32_t(d.b_last)) : 31;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  constexpr int nwaves = kDftThreads / 64;
 
 
   // twiddles of each dimension, concatenated
@@ -394,18 +431,14 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
       sr += v.x;
       si += v.y;
     }
-    re[idx] = sr;
-    im[idx] = si;
+    re[lds_at(idx, nls)] = sr;
+    im[lds_at(idx, nls)] = si;
   }
   __syncthreads();
 
   for (int dd = 0; dd < d.ndim; ++dd) {
     const int n = d.b[dd];
-    const int nlines = B / n;
-    const int groups = (nlines + 15) >> 4;
-    for (int grp = wave; grp < groups; grp += nwaves)
-      mode_product(re, im, tws + twoff[dd], n, d.bshift[dd], nlines, grp);
-    __syncthreads();
+    mode_product(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
   }
 
   float2* bout = p.buckets + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
@@ -425,7 +458,7 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   if (d.noise_mode == RSFT_NOISE_ESTIMATED) {
     // pass 1: buckets out, powers into the re plane (relabel is a bijection)
     for (int j = tid; j < B; j += kDftThreads) {
-      const int kf = relabel(j);
+      const int kf = lds_at(relabel(j), nls);
       const float xr = re[kf], xi = im[kf];
       bout[j] = make_float2(xr, xi);
       re[kf] = xr * xr + xi * xi;
@@ -438,7 +471,7 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
       for (int q = tid; q < 256; q += kDftThreads) hist[q] = 0u;
       __syncthreads();
       for (int idx = tid; idx < B; idx += kDftThreads) {
-        const uint32_t u = __float_as_uint(re[idx]);
+        const uint32_t u = __float_as_uint(re[lds_at(idx, nls)]);
         if ((u & pmask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
       }
       __syncthreads();
@@ -464,7 +497,7 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
     for (int j0 = wave * 64; j0 < B; j0 += kDftThreads) {
       const int j = j0 + lane;
       bool flag = false;
-      if (j < B) flag = double(re[relabel(j)]) >= gamma;
+      if (j < B) flag = double(re[lds_at(relabel(j), nls)]) >= gamma;
       const unsigned long long m = __ballot(flag);
       if (lane == 0) {
         const int w = j0 >> 5;
@@ -477,7 +510,7 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
       const int j = j0 + lane;
       bool flag = false;
       if (j < B) {
-        const int kf = relabel(j);
+        const int kf = lds_at(relabel(j), nls);
         const float xr = re[kf], xi = im[kf];
         bout[j] = make_float2(xr, xi);
         flag = double(xr * xr + xi * xi) >= gamma;
@@ -492,20 +525,20 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   }
 }
 
-int launch_dft(const DevPtrs& p, int64_t nframes, int T, int maxB, int sum_tw, int identity,
+int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw, int identity,
                int nchunks_override, void* stream) {
   if (nframes <= 0) return hipSuccess;
-  const size_t shmem = size_t(2 * maxB) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
+  const size_t shmem = size_t(2 * plane) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
   hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), unsigned(nframes)), dim3(kDftThreads), shmem,
-                     static_cast<hipStream_t>(stream), p, T, maxB, 0, identity, nchunks_override);
+                     static_cast<hipStream_t>(stream), p, T, plane, pad, 0, identity, nchunks_override);
   return hipGetLastError();
 }
 
-static int launch_dft_frame(const DevPtrs& p, int64_t frame, int T, int maxB, int sum_tw,
+static int launch_dft_frame(const DevPtrs& p, int64_t frame, int T, int plane, int pad, int sum_tw,
                             hipStream_t st) {
-  const size_t shmem = size_t(2 * maxB) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
-  hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), 1u), dim3(kDftThreads), shmem, st, p, T, maxB,
-                     int(frame), 1, 1);
+  const size_t shmem = size_t(2 * plane) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
+  hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), 1u), dim3(kDftThreads), shmem, st, p, T, plane,
+                     pad, int(frame), 1, 1);
   return hipGetLastError();
 }
 
@@ -872,7 +905,7 @@ int launch_scan(const DevPtrs& p, int64_t nframes, void* stream) {
 // ---------------------------------------------------------------------------
 
 constexpr int kEstThreads = 256;
-constexpr int kListMax = kEstThreads * 32;   // cells listed at once (one pass of 32-bit words)
+constexpr int kListMax = 2048;   // cells listed at once: a chunk's, else one pass's
 
 // Per-frame constants of the estimate, uniform across the work-group.
 template <int D, int M>
@@ -1116,16 +1149,28 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
   *out = rec;
 }
 
+// Records of list[0 .. min(n, room)) in batches of kEstThreads: each thread
+// builds one record in LDS, then the work-group copies the batch out with
+// contiguous 8-byte stores (a record is 88 bytes, 8-byte aligned).
 template <int D, int M>
 __device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc& d, int64_t f,
                                               int64_t rel, int T, const uint32_t* list, int n,
                                               unsigned long long cell0, rsft_detection* out,
-                                              int64_t room, float* pcol) {
+                                              int64_t room, float* pcol, rsft_detection* stage) {
   EstFrame<D, M> e;
   load_frame<D, M>(p, d, rel, e);
   const int lim = int(n < room ? n : room);
-  for (int q = int(threadIdx.x); q < lim; q += kEstThreads)
-    write_record<D, M>(e, T, f, cell0 | (unsigned long long)list[q], out + q, pcol);
+  constexpr int kWords = int(sizeof(rsft_detection) / 8);
+  for (int q0 = 0; q0 < lim; q0 += kEstThreads) {
+    const int q = q0 + int(threadIdx.x);
+    if (q < lim) write_record<D, M>(e, T, f, cell0 | (unsigned long long)list[q], stage + threadIdx.x, pcol);
+    __syncthreads();
+    const int nw = (lim - q0 < kEstThreads ? lim - q0 : kEstThreads) * kWords;
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(stage);
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(out + q0);
+    for (int w = int(threadIdx.x); w < nw; w += kEstThreads) dst[w] = src[w];
+    __syncthreads();
+  }
 }
 
 template <int D, int M>
@@ -1136,6 +1181,7 @@ __global__ __launch_bounds__(kEstThreads) void compact_estimate_kernel(DevPtrs p
   constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
   __shared__ uint32_t list[kListMax];
   __shared__ uint32_t wsum[kEstThreads / 64];
+  __shared__ rsft_detection stage[kEstThreads];
   __shared__ float pbuf[D >= 3 ? kNb * kEstThreads : 1];
   int64_t f;
   int c;
@@ -1206,14 +1252,15 @@ __global__ __launch_bounds__(kEstThreads) void compact_estimate_kernel(DevPtrs p
       }
     }
     __syncthreads();
-    estimate_list<D, M>(p, d, f, rel, T, list, min(total, kListMax), cell0, out, room0, pcol);
+    estimate_list<D, M>(p, d, f, rel, T, list, min(total, kListMax), cell0, out, room0, pcol, stage);
     return;
   }
-  // dense chunk: passes of kEstThreads words
+  // dense chunk: passes of kListMax / 32 words (at most kListMax cells each)
+  constexpr int kPassWords = kListMax / 32;
   int64_t running = 0;
-  for (int wb = w0; wb < wend; wb += kEstThreads) {
+  for (int wb = w0; wb < wend; wb += kPassWords) {
     const int w = wb + tid;
-    uint32_t word = w < wend ? bm[w] : 0u;
+    uint32_t word = (tid < kPassWords && w < wend) ? bm[w] : 0u;
     const int pc = __popc(word);
     int incl = pc;
 #pragma unroll
@@ -1236,7 +1283,8 @@ __global__ __launch_bounds__(kEstThreads) void compact_estimate_kernel(DevPtrs p
       list[k++] = (uint32_t(w - w0) << 5) | uint32_t(bit);
     }
     __syncthreads();
-    estimate_list<D, M>(p, d, f, rel, T, list, total, cell0, out + running, room0 - running, pcol);
+    estimate_list<D, M>(p, d, f, rel, T, list, total, cell0, out + running, room0 - running, pcol,
+                        stage);
     running += total;
     if (running >= room0) return;   // uniform: the frame's capacity is used up
     __syncthreads();
@@ -1343,8 +1391,9 @@ int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t fr
   return hipGetLastError();
 }
 
-int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int maxB, int sum_tw, void* stream) {
-  return launch_dft_frame(p, frame, T, maxB, sum_tw, static_cast<hipStream_t>(stream));
+int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int plane, int pad, int sum_tw,
+                     void* stream) {
+  return launch_dft_frame(p, frame, T, plane, pad, sum_tw, static_cast<hipStream_t>(stream));
 }
 
 }  // namespace rsft

@@ -71,6 +71,8 @@ struct rsft_plan_s {
   int num_cus = 256;
   int64_t min_nl = 0;
   int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, rows_ok = 1, est_nmask = 0;
+  int dft_plane = 0;   // floats per LDS plane of the DFT: B plus one pad per last-dimension row
+  int dft_pad = 0;     // 1 when those pads are used
   int64_t tiles_per_frame = 0;   // uniform plans
   int64_t ntiles_uneven = 0;     // uneven plans
   // device arrays
@@ -473,6 +475,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     chunk_off += mult * d.chunk_stride;
     rec_total += mult * d.cap;
     pl->maxB = std::max(pl->maxB, d.B);
+    pl->dft_plane = std::max(pl->dft_plane, d.B + d.B / d.b_last);
     pl->max_words = std::max(pl->max_words, d.words);
     pl->max_cchunks = std::max(pl->max_cchunks, d.cchunks);
     pl->dims_mask |= 1 << (d.ndim - 1);
@@ -482,8 +485,19 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     for (int k = 0; k < d.ndim; ++k) sum_tw += d.b[k];
     pl->sum_tw_max = std::max(pl->sum_tw_max, sum_tw);
   }
-  if (size_t(2 * pl->maxB) * 4 + size_t(pl->sum_tw_max) * 8 > 160 * 1024)
+  // the DFT stage keeps two planes of B floats plus the twiddles in LDS;
+  // padding of the last dimension's rows (against bank conflicts) is used
+  // when it fits
+  const size_t lds_limit = 160 * 1024;
+  const size_t tw_bytes = size_t(pl->sum_tw_max) * 8;
+  if (size_t(2 * pl->dft_plane) * 4 + tw_bytes <= lds_limit) {
+    pl->dft_pad = 1;
+  } else if (size_t(2 * pl->maxB) * 4 + tw_bytes <= lds_limit) {
+    pl->dft_pad = 0;
+    pl->dft_plane = pl->maxB;
+  } else {
     return fail(RSFT_ERROR_UNSUPPORTED, "buckets per frame exceed the DFT stage's LDS");
+  }
 
   // fold tiles
   std::vector<int32_t> tiles;
@@ -599,7 +613,7 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
     if (fs != RSFT_OK) return fs;
   }
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-  LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->maxB, pl->sum_tw_max, 0, 0, st));
+  LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0, st));
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, st));
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
@@ -766,7 +780,7 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
   for (int64_t f = 0; f < batch; ++f) {
     const auto& d = pl->descs[size_t(pl->uniform ? 0 : f)];
     for (int r = 0; r < pl->T; ++r) LAUNCH_TRY(rsft::launch_plain_fold(q, d_input, pl->dtype, f, r, d.B, s));
-    LAUNCH_TRY(rsft::launch_plain_dft(q, f, pl->T, pl->maxB, pl->sum_tw_max, s));
+    LAUNCH_TRY(rsft::launch_plain_dft(q, f, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, s));
     LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, int(f), s));
   }
   if (batch > 0) {

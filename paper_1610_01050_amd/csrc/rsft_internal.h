@@ -101,7 +101,7 @@ constexpr int kFoldMaxP = 2048;   // largest threads * vec a plan may be tuned t
 int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
                 int64_t tiles_per_frame, int64_t ntiles, int round0, int rounds,
                 int T, const FoldConfig& cfg, void* stream);
-int launch_dft(const DevPtrs& p, int64_t nframes, int T, int maxB, int sum_tw,
+int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw,
                int identity_relabel, int nchunks_override, void* stream);
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
                 int max_words, int dims_mask, int rows_ok, int frame0, void* stream);
@@ -112,6 +112,7 @@ int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, i
 // Per-frame comparator path.
 int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t frame,
                       int round, int B, void* stream);
-int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int maxB, int sum_tw, void* stream);
+int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int plane, int pad, int sum_tw,
+                     void* stream);
 
 }  // namespace rsft

@@ -233,6 +233,36 @@ def test_capacity_overflow_keeps_exact_counts():
     small.close()
 
 
+def test_dense_chunk_every_cell_detected():
+    """Noise 20 dB above the design variance flags every bucket, so all
+    32768 cells of the frame's single compaction chunk are detected: the
+    compaction's multi-pass path (more detections than one listing holds),
+    with every record compared to the oracle, plus a capacity cut inside a
+    later pass."""
+    shape, buckets = (128, 256), (16, 16)
+    sigma = synth.draw_sigma(np.random.default_rng(17), 3, shape)
+    x = (synth.noise_only(shape, 31, 0, dtype=np.complex128) * 10.0).astype(np.complex64)
+    xd = torch.from_numpy(x[None]).to("cuda")
+    plan = _plan(shape=shape, buckets=buckets, rounds=3, sigma=sigma, pfa=1e-3, max_batch=1,
+                 max_detections=1 << 16)
+    plan.execute(xd)
+    recs, counts = plan.detect()
+    gbk = [b.cpu().numpy() for b in plan.buckets()]
+    gfl = [w.cpu().numpy().view(np.uint32) for w in plan.flags()]
+    oplan = oracle_plan(shape, buckets, sigma, pfa=1e-3)
+    ref = OR.rsft(x, oplan)
+    assert len(ref["detections"]) > 20000
+    _check_frame(0, oplan, ref, recs, gbk[0], gfl[0])
+    cut = _plan(shape=shape, buckets=buckets, rounds=3, sigma=sigma, pfa=1e-3, max_batch=1,
+                max_detections=5000)
+    cut.execute(xd)
+    crecs, ccounts = cut.detect(allow_truncation=True)
+    assert np.array_equal(ccounts, counts)
+    assert np.array_equal(crecs, recs[:5000])
+    plan.close()
+    cut.close()
+
+
 def test_autotuned_fold_keeps_parity():
     """Whatever launch shape the tuner picks, the results stay within the
     parity contract."""
