@@ -23,6 +23,8 @@ rsft      Algorithm 1 literal, thresholds (eq. tpd), noise law (eq.
 dense     Algorithm 2 (Bartlett) with T=1 exact exponential threshold and the
           eq. bartlettROC closed form.
 evaluate  the complexity model of Tables I-II.
+refine    the bucketized forward model of off-grid tones (eq. f with a
+          continuous frequency) and its gradients, for refinement.
 """
 
-from . import windows, hashing, rsft, dense, evaluate  # noqa: F401
+from . import windows, hashing, rsft, dense, evaluate, refine  # noqa: F401

@@ -1,0 +1,94 @@
+"""Pins of the refinement oracle (bucketized forward model of off-grid tones
+and its gradients) against the mathematics: FP64 central differences of the
+loss, the minimum at the true parameters, the closed-form bucket of an
+on-grid tone, and an exact Newton step for the amplitudes (which fixes the
+gradient convention and its factor 2)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import hashing as H
+from oracle import refine as RF
+from oracle import rsft as R
+
+
+def _plan(shape, b, T=3, atten=60.0, flat=None, seed=0):
+    sigma = synth.draw_sigma(np.random.default_rng(seed), T, shape)
+    return R.OraclePlan(shape, b, sigma, atten, flat, 1e-3)
+
+
+def _tones(rng, shape, K):
+    freqs = rng.random((K, len(shape)))
+    amps = (rng.standard_normal(K) + 1j * rng.standard_normal(K)) * 2.0
+    return freqs, amps
+
+
+@pytest.mark.parametrize("shape,b", [((64, 32), (8, 4)), ((128,), (16,)), ((16, 8, 8), (4, 2, 2))])
+def test_gradients_match_central_differences(shape, b):
+    """dL/df and dL/db against FP64 central differences with h = 1e-6."""
+    rng = np.random.default_rng(sum(shape))
+    plan = _plan(shape, b, seed=len(shape))
+    freqs, amps = _tones(rng, shape, 2)
+    truth_f = freqs + rng.uniform(-0.3, 0.3, freqs.shape) / np.array(shape)
+    observed = RF.model(truth_f, amps * 1.1, plan)
+    gf, ga = RF.loss_gradients(freqs, amps, plan, observed)
+    h = 1e-6
+    for t in range(len(freqs)):
+        for d in range(len(shape)):
+            fp, fm = freqs.copy(), freqs.copy()
+            fp[t, d] += h
+            fm[t, d] -= h
+            cd = (RF.loss(fp, amps, plan, observed) - RF.loss(fm, amps, plan, observed)) / (2 * h)
+            assert abs(cd - gf[t, d]) <= 1e-5 * max(abs(gf[t, d]), 1.0) + 1e-6 * np.max(np.abs(gf))
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            ap, am = amps.copy(), amps.copy()
+            ap[t] += h * unit
+            am[t] -= h * unit
+            cd = (RF.loss(freqs, ap, plan, observed) - RF.loss(freqs, am, plan, observed)) / (2 * h)
+            want = ga[t].real if part == "re" else ga[t].imag
+            assert abs(cd - want) <= 1e-6 * max(abs(want), 1.0) + 1e-7 * np.max(np.abs(ga))
+
+
+def test_minimum_at_truth():
+    shape, b = (64, 64), (8, 8)
+    rng = np.random.default_rng(4)
+    plan = _plan(shape, b, seed=3)
+    freqs, amps = _tones(rng, shape, 3)
+    observed = RF.model(freqs, amps, plan)
+    assert RF.loss(freqs, amps, plan, observed) < 1e-16 * np.sum(np.abs(observed) ** 2)
+    gf, ga = RF.loss_gradients(freqs, amps, plan, observed)
+    assert np.max(np.abs(gf)) < 1e-6 and np.max(np.abs(ga)) < 1e-6
+
+
+def test_ongrid_tone_model_closed_form():
+    """Rectangular windows, on-grid tone at cell i: every round's model is
+    b * N in bucket M(i, sigma_s) and 0 elsewhere."""
+    shape, b = (32, 64), (4, 8)
+    plan = _plan(shape, b, atten=0.0, flat=0.0, seed=7)
+    cell = (5, 41)
+    freqs = np.array([[cell[0] / shape[0], cell[1] / shape[1]]])
+    amp = np.array([0.3 - 1.2j])
+    m = RF.model(freqs, amp, plan)
+    N = shape[0] * shape[1]
+    for s in range(plan.T):
+        j = tuple(H.mapping(cell[d], plan.sigma[s, d], shape[d], b[d]) for d in range(2))
+        want = np.zeros(b, dtype=np.complex128)
+        want[j] = amp[0] * N
+        assert np.max(np.abs(m[s] - want)) < 1e-9 * N
+
+
+def test_amplitude_newton_step_is_exact():
+    """The loss is quadratic in one tone's amplitude with Hessian 2 ||basis||^2
+    (per real coordinate), so b - grad / (2 ||basis||^2) lands on the least-
+    squares amplitude; with noise-free data that is the true amplitude."""
+    shape, b = (64, 32), (8, 8)
+    rng = np.random.default_rng(11)
+    plan = _plan(shape, b, seed=5)
+    freqs, amps = _tones(rng, shape, 1)
+    observed = RF.model(freqs, amps, plan)
+    start = amps + (0.7 - 0.4j)
+    _, ga = RF.loss_gradients(freqs, start, plan, observed)
+    basis = RF.round_buckets(RF.tone_signal(shape, freqs[0]), plan)
+    step = start - ga / (2.0 * np.sum(np.abs(basis) ** 2))
+    assert abs(step[0] - amps[0]) < 1e-9 * abs(amps[0])
