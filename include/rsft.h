@@ -262,6 +262,60 @@ rsft_status rsft_get_flags(rsft_plan_t plan, uint32_t* d_out, void* stream);
  */
 rsft_status rsft_vote_flags(rsft_plan_t plan, const uint32_t* d_flags, void* stream);
 
+/*
+ * Bucketized forward model of K complex tones per frame, for off-grid
+ * refinement. The round-s buckets of eq. f are linear in the signal, and for
+ * a tone b exp(j 2 pi f . m) with continuous frequency f (cycles/sample per
+ * dimension; the tone v(omega) of eq. f_k) they factor per dimension:
+ *   model_s[k] = sum_t b_t prod_d G_{s,d}(f_{t,d})[k_d],
+ *   G_{s,d}(f)[k] = sum_n wbar_d[n] w_d[m] exp(j 2 pi f m) exp(-2 pi i k n / B_d),
+ *   m = [sigma_{s,d} n]_{N_d}
+ * (window W, permutation P_{sigma,0} of Def. 1, flat window, aliasing of
+ * Def. 2 and the B-point DFT, with this plan's windows and sigma). The phase
+ * f m is reduced modulo 1 exactly (64-bit fixed point); sums are FP32.
+ *
+ * All descriptors of the plan must have the same D. batch: as rsft_execute
+ * (uniform plan: 1..max_batch; uneven plan: its frame count). tones K >= 1
+ * (pad with zero amplitudes when frames have fewer).
+ *   d_freqs  device double [batch][K][D], cycles/sample (any real value;
+ *            only frac(f) matters)
+ *   d_amps   device complex64 [batch][K]
+ *   d_model  device complex64, the layout of rsft_get_buckets
+ *   d_workspace  device buffer of rsft_model_workspace_size bytes; the
+ *            forward call stores the per-dimension factors there and the
+ *            backward call reads them (same plan, batch, K and frequencies)
+ * Errors: INVALID_ARGUMENT (NULL, bad batch or K), UNSUPPORTED (mixed D),
+ * DEVICE. Async on `stream`.
+ */
+rsft_status rsft_model_workspace_size(rsft_plan_t plan, int64_t batch, int32_t tones,
+                                      int64_t* bytes);
+rsft_status rsft_model_forward(rsft_plan_t plan, const double* d_freqs, const void* d_amps,
+                               int64_t batch, int32_t tones, void* d_model, void* d_workspace,
+                               void* stream);
+
+/*
+ * Gradients of a real loss through the model, given the output gradient
+ * d_grad_model = dL/dRe(model) + j dL/dIm(model) (layout of d_model):
+ *   d_grad_amps[f][t]     = sum_{s,k} grad_s[k] conj(prod_d G_{s,d}(f_t)[k_d])
+ *                           (= dL/dRe b_t + j dL/dIm b_t), complex64
+ *   d_grad_freqs[f][t][d] = Re(b_t sum_{s,k} conj(grad_s[k]) dG_{s,d}/df [k_d]
+ *                              prod_{e != d} G_{s,e}[k_e]) = dL/df_{t,d}, double
+ * and, when d_step_freqs / d_step_amps are not NULL (both or neither), each
+ * tone's Gauss-Newton step for the least-squares loss sum |model - observed|^2
+ * (pass d_grad_model = 2 (model - observed)): x solving H x = -g/2 with
+ * H = Re(J^H J), J = [P, jP, b_t dP/df_0, ...], P = prod_d G_d, over the
+ * tone's own parameters (Re b_t, Im b_t, f_t); tones are treated as
+ * decoupled (block-diagonal H), H is solved in FP64 with 1e-6 Levenberg
+ * damping, and a vanishing pivot leaves that parameter unchanged.
+ * d_step_freqs: double [batch][K][D]; d_step_amps: complex64 [batch][K].
+ * d_workspace must hold the factors of the matching forward call.
+ * Async on `stream`.
+ */
+rsft_status rsft_model_backward(rsft_plan_t plan, const void* d_amps, int64_t batch,
+                                int32_t tones, const void* d_grad_model, double* d_grad_freqs,
+                                void* d_grad_amps, double* d_step_freqs, void* d_step_amps,
+                                const void* d_workspace, void* stream);
+
 /* Per-frame derived parameters; frame indexes the descriptors of rsft_plan. */
 rsft_status rsft_plan_info(rsft_plan_t plan, int64_t frame, rsft_plan_info_t* out);
 

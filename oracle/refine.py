@@ -91,3 +91,27 @@ def loss_gradients(freqs, amps, plan, observed, tones=None):
     """Gradients of ``loss``: its output gradient is G = 2 (model - observed)."""
     g = 2.0 * (model(freqs, amps, plan) - observed)
     return gradients(freqs, amps, plan, g, tones)
+
+
+def gauss_newton_steps(freqs, amps, plan, observed):
+    """Each tone's Gauss-Newton step for loss(), tones treated as decoupled:
+    with residual r = model - observed and the tone's Jacobian columns
+    J = [P, jP, b_t dP/df_0, ..., b_t dP/df_{D-1}] (P = Round(v(f_t))), the
+    step x over (Re b_t, Im b_t, f_t) solves Re(J^H J) x = -Re(J^H r).
+    Returns (step_freqs [K][D], step_amps [K] complex)."""
+    r = model(freqs, amps, plan) - observed
+    K = len(freqs)
+    D = len(plan.shape)
+    sf = np.zeros((K, D))
+    sa = np.zeros(K, dtype=np.complex128)
+    for t in range(K):
+        P = round_buckets(tone_signal(plan.shape, freqs[t]), plan)
+        J = [P, 1j * P] + [complex(amps[t]) *
+                           round_buckets(tone_derivative_signal(plan.shape, freqs[t], d), plan)
+                           for d in range(D)]
+        H = np.array([[np.real(np.vdot(Ji, Jj)) for Jj in J] for Ji in J])
+        g = np.array([np.real(np.vdot(Ji, r)) for Ji in J])
+        x = np.linalg.solve(H, -g)
+        sa[t] = x[0] + 1j * x[1]
+        sf[t] = x[2:]
+    return sf, sa

@@ -41,6 +41,7 @@ SYMBOLS = (
     "rsft_destroy", "rsft_status_string", "rsft_last_error",
     "rsft_chebyshev_window", "rsft_flat_window", "rsft_mod_inverse",
     "rsft_stage1_probability", "rsft_draw_sigma",
+    "rsft_model_workspace_size", "rsft_model_forward", "rsft_model_backward",
 )
 
 
@@ -141,6 +142,9 @@ def load_library(path=None):
     lib.rsft_stage1_probability.argtypes = [ctypes.c_double, ctypes.c_int32,
                                             ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_double)]
+    lib.rsft_model_workspace_size.argtypes = [vp, i64, ctypes.c_int32, ctypes.POINTER(i64)]
+    lib.rsft_model_forward.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp]
+    lib.rsft_model_backward.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     lib.rsft_draw_sigma.argtypes = [ctypes.c_uint64, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
@@ -405,6 +409,68 @@ class Plan:
             "fold": {"threads": out.fold_threads, "vec": out.fold_vec,
                      "nontemporal": out.fold_nontemporal},
         }
+
+    # -- bucketized forward model of complex tones (off-grid refinement) --
+
+    def _model_args(self, freqs, amps):
+        import torch
+        if not (isinstance(freqs, torch.Tensor) and freqs.is_cuda and freqs.dtype == torch.float64
+                and freqs.is_contiguous() and freqs.dim() == 3):
+            raise TypeError("freqs must be a contiguous CUDA float64 tensor [batch, K, D]")
+        if not (isinstance(amps, torch.Tensor) and amps.is_cuda and amps.dtype == torch.complex64
+                and amps.is_contiguous() and tuple(amps.shape) == tuple(freqs.shape[:2])):
+            raise TypeError("amps must be a contiguous CUDA complex64 tensor [batch, K]")
+        batch, K, D = (int(v) for v in freqs.shape)
+        if D != len(self.descs[0]["shape"]):
+            raise ValueError("freqs' last dimension must be the frame dimension count")
+        return batch, K
+
+    def model_size(self, batch):
+        """Complex values of a model (or bucket) array for `batch` frames."""
+        return sum(self.rounds * int(np.prod(b)) for b in self._frame_buckets(batch))
+
+    def model_workspace(self, batch, tones):
+        import torch
+        n = ctypes.c_int64()
+        _check(self._lib, self._lib.rsft_model_workspace_size(self._h, int(batch), int(tones),
+                                                              ctypes.byref(n)))
+        return torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+
+    def model_forward(self, freqs, amps, workspace, out=None, stream=None):
+        """model_s[k] = sum_t b_t prod_d G_{s,d}(f_t)[k_d] for every frame:
+        a complex64 tensor in the layout of buckets() (flat). `workspace`
+        (model_workspace) receives the factors the backward call needs."""
+        import torch
+        batch, K = self._model_args(freqs, amps)
+        if out is None:
+            out = torch.empty(self.model_size(batch), dtype=torch.complex64, device="cuda")
+        _check(self._lib, self._lib.rsft_model_forward(
+            self._h, ctypes.c_void_p(freqs.data_ptr()), ctypes.c_void_p(amps.data_ptr()), batch, K,
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+            _stream_handle(stream)))
+        return out
+
+    def model_backward(self, amps, grad_model, workspace, steps=False, stream=None):
+        """(grad_freqs float64 [batch, K, D], grad_amps complex64 [batch, K])
+        for the output gradient grad_model (dL/dRe + j dL/dIm of the model);
+        with steps=True also each tone's Gauss-Newton step (step_freqs,
+        step_amps) for the loss sum |model - observed|^2, given
+        grad_model = 2 (model - observed)."""
+        import torch
+        batch, K = int(amps.shape[0]), int(amps.shape[1])
+        D = len(self.descs[0]["shape"])
+        grad_model = grad_model.contiguous()
+        gf = torch.empty((batch, K, D), dtype=torch.float64, device="cuda")
+        ga = torch.empty((batch, K), dtype=torch.complex64, device="cuda")
+        sf = torch.empty((batch, K, D), dtype=torch.float64, device="cuda") if steps else None
+        sa = torch.empty((batch, K), dtype=torch.complex64, device="cuda") if steps else None
+        _check(self._lib, self._lib.rsft_model_backward(
+            self._h, ctypes.c_void_p(amps.data_ptr()), batch, K,
+            ctypes.c_void_p(grad_model.data_ptr()), ctypes.c_void_p(gf.data_ptr()),
+            ctypes.c_void_p(ga.data_ptr()), ctypes.c_void_p(sf.data_ptr() if steps else 0),
+            ctypes.c_void_p(sa.data_ptr() if steps else 0), ctypes.c_void_p(workspace.data_ptr()),
+            _stream_handle(stream)))
+        return (gf, ga, sf, sa) if steps else (gf, ga)
 
     def set_option(self, option, value):
         _check(self._lib, self._lib.rsft_set_option(self._h, int(option), int(value)))

@@ -732,12 +732,14 @@ __global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int 
       for (int ci = lane; ci < ncand; ci += 64) {
         const uint32_t jl = lst[ci >> lsl];
         const uint32_t u = (jl << lsl) | (uint32_t(ci) & ((1u << lsl) - 1u));
-        const uint32_t il = (sinv_last[s0] * u) & nm[D - 1];
-        int votes = 0;
+        // operands are below N_last <= 4096, so 24-bit products are exact
+        const uint32_t il = __umul24(sinv_last[s0], u) & nm[D - 1];
+        int votes = 1;   // round s0 maps il back to u, whose bucket is flagged
         bool skip = false;
 #pragma unroll
         for (int s = 0; s < TT; ++s) {
-          const uint32_t bit = row_bit(R + s * 4, ((sig[s][D - 1] * il) & nm[D - 1]) >> lsl);
+          if (s == s0) continue;
+          const uint32_t bit = row_bit(R + s * 4, (__umul24(sig[s][D - 1], il) & nm[D - 1]) >> lsl);
           if (s < s0 && bit) skip = true;
           votes += int(bit);
         }

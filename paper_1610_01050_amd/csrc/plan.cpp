@@ -790,6 +790,67 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
   return RSFT_OK;
 }
 
+namespace {
+rsft_status check_model(rsft_plan_s* pl, int64_t batch, int32_t tones) {
+  if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (tones < 1 || tones > 65536) return fail(RSFT_ERROR_INVALID_ARGUMENT, "tones must be in 1..65536");
+  if (batch < 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, "batch must be >= 1");
+  if (pl->uniform ? batch > pl->max_frames : batch != pl->ndesc)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "batch does not match the plan");
+  if (batch > 65535) return fail(RSFT_ERROR_UNSUPPORTED, "more than 65535 frames per model call");
+  if ((pl->dims_mask & (pl->dims_mask - 1)) != 0)
+    return fail(RSFT_ERROR_UNSUPPORTED, "the model needs one dimension count across descriptors");
+  return RSFT_OK;
+}
+
+int64_t model_factor_count(const rsft_plan_s* pl, int64_t batch, int32_t tones) {
+  return batch * pl->T * int64_t(tones) * pl->sum_tw_max;   // complex values per factor array
+}
+}  // namespace
+
+rsft_status rsft_model_workspace_size(rsft_plan_t pl, int64_t batch, int32_t tones, int64_t* bytes) {
+  if (!bytes) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  const rsft_status st = check_model(pl, batch, tones);
+  if (st != RSFT_OK) return st;
+  *bytes = 2 * model_factor_count(pl, batch, tones) * int64_t(sizeof(float) * 2);
+  return RSFT_OK;
+}
+
+rsft_status rsft_model_forward(rsft_plan_t pl, const double* d_freqs, const void* d_amps,
+                               int64_t batch, int32_t tones, void* d_model, void* d_workspace,
+                               void* stream) {
+  rsft_status st = check_model(pl, batch, tones);
+  if (st != RSFT_OK) return st;
+  if (!d_freqs || !d_amps || !d_model || !d_workspace) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL pointer");
+  const int D = pl->descs[0].ndim;
+  float2* G = static_cast<float2*>(d_workspace);
+  float2* dG = G + model_factor_count(pl, batch, tones);
+  LAUNCH_TRY(rsft::launch_model_forward(pl->ptrs, d_freqs, static_cast<const float2*>(d_amps), batch,
+                                        tones, D, pl->T, pl->maxB, pl->sum_tw_max, G, dG,
+                                        static_cast<float2*>(d_model), stream));
+  return RSFT_OK;
+}
+
+rsft_status rsft_model_backward(rsft_plan_t pl, const void* d_amps, int64_t batch, int32_t tones,
+                                const void* d_grad_model, double* d_grad_freqs, void* d_grad_amps,
+                                double* d_step_freqs, void* d_step_amps, const void* d_workspace,
+                                void* stream) {
+  rsft_status st = check_model(pl, batch, tones);
+  if (st != RSFT_OK) return st;
+  if (!d_amps || !d_grad_model || !d_grad_freqs || !d_grad_amps || !d_workspace)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL pointer");
+  if ((d_step_freqs == nullptr) != (d_step_amps == nullptr))
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "step outputs: both or neither");
+  const float2* G = static_cast<const float2*>(d_workspace);
+  const float2* dG = G + model_factor_count(pl, batch, tones);
+  LAUNCH_TRY(rsft::launch_model_backward(pl->ptrs, static_cast<const float2*>(d_amps), batch, tones,
+                                         pl->T, pl->sum_tw_max, G, dG,
+                                         static_cast<const float2*>(d_grad_model), d_grad_freqs,
+                                         static_cast<float2*>(d_grad_amps), d_step_freqs,
+                                         static_cast<float2*>(d_step_amps), stream));
+  return RSFT_OK;
+}
+
 rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* stream) {
   if (!pl || !d_flags) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
   if (pl->last_batch < 0) return fail(RSFT_ERROR_NOT_READY, "no execute yet");

@@ -79,7 +79,7 @@ struct DevPtrs {
   float2* part;
   float2* buckets;
   uint32_t* flags;
-  uint32_t* bitmap;            // detected cells, cleared again by the compaction
+  uint32_t* bitmap;            // detected cells; every word written by the vote stage
   uint32_t* chunk_counts;      // detections per compaction chunk
   int64_t* chunk_offsets;      // rank of a chunk's first detection within its frame
   int64_t* counts;             // [frames] exact detections per frame
@@ -114,5 +114,14 @@ int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t fr
                       int round, int B, void* stream);
 int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int plane, int pad, int sum_tw,
                      void* stream);
+// Bucketized forward model and its gradients (refine.hip). G and dG hold
+// [batch][T][K][sum_b] complex factors (per dimension at offset sum_{e<d} B_e).
+int launch_model_forward(const DevPtrs& p, const double* freqs, const float2* amps, int64_t batch,
+                         int K, int D, int T, int maxB, int sum_b, float2* G, float2* dG,
+                         float2* model, void* stream);
+int launch_model_backward(const DevPtrs& p, const float2* amps, int64_t batch, int K, int T,
+                          int sum_b, const float2* G, const float2* dG, const float2* grad_model,
+                          double* grad_freqs, float2* grad_amps, double* step_freqs,
+                          float2* step_amps, void* stream);
 
 }  // namespace rsft

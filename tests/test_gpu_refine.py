@@ -1,0 +1,200 @@
+"""GPU parity of the refinement kernels (bucketized forward model of off-grid
+tones, its hand-written backward and the per-tone Gauss-Newton step) against
+the FP64 oracle, through the C ABI and the torch.autograd.Function.
+
+Tolerances: model buckets within 1e-4 of the round's rms (FP32 sums, as for
+the RSFT buckets); gradients within 1e-3 of the largest gradient of their
+kind (FP32 accumulations over T*B terms); Gauss-Newton steps within 2e-3 of
+the largest step of their kind.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import refine as RF
+from oracle import rsft as OR
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (shape, buckets, K)
+    "two_dim_256": ((256, 256), (16, 16), 4),
+    "three_dim": ((64, 32, 16), (8, 4, 4), 3),
+    "one_dim": ((4096,), (64,), 3),
+}
+
+
+def _setup(shape, buckets, K, seed, batch=2, noise=True):
+    from paper_1610_01050_amd import Plan
+    rng = np.random.default_rng(seed)
+    sigma = synth.draw_sigma(rng, 3, shape)
+    plan = Plan(shape, buckets, rounds=3, sigma=sigma, pfa=1e-3, max_batch=batch)
+    oplan = OR.OraclePlan(shape, buckets, sigma, 60.0, None, 1e-3)
+    freqs = np.stack([synth.draw_frequencies(rng, shape, K, False, 2.05)[0] for _ in range(batch)])
+    amps = (rng.standard_normal((batch, K)) + 1j * rng.standard_normal((batch, K))) * 1.5
+    return plan, oplan, freqs, amps, rng
+
+
+def _dev(freqs, amps):
+    return (torch.tensor(freqs, dtype=torch.float64, device="cuda").contiguous(),
+            torch.tensor(amps.astype(np.complex64), device="cuda").contiguous())
+
+
+def _frames(model_flat, plan, batch):
+    T = plan.rounds
+    B = tuple(plan.descs[0]["buckets"])
+    return model_flat.cpu().numpy().reshape((batch, T) + B)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_model_forward_matches_oracle(name):
+    shape, buckets, K = CASES[name]
+    print(f"case {name}", flush=True)
+    plan, oplan, freqs, amps, _ = _setup(shape, buckets, K, seed=len(name))
+    f_d, a_d = _dev(freqs, amps)
+    ws = plan.model_workspace(2, K)
+    got = _frames(plan.model_forward(f_d, a_d, ws), plan, 2)
+    for f in range(2):
+        want = RF.model(freqs[f], amps[f].astype(np.complex64), oplan)
+        for s in range(3):
+            rms = np.sqrt(np.mean(np.abs(want[s]) ** 2))
+            assert np.max(np.abs(got[f, s] - want[s])) <= 1e-4 * rms
+    plan.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_backward_matches_oracle_gradients(name):
+    shape, buckets, K = CASES[name]
+    print(f"case {name}", flush=True)
+    plan, oplan, freqs, amps, rng = _setup(shape, buckets, K, seed=7 + len(name))
+    f_d, a_d = _dev(freqs, amps)
+    ws = plan.model_workspace(2, K)
+    plan.model_forward(f_d, a_d, ws)
+    T, B = 3, int(np.prod(buckets))
+    grad = (rng.standard_normal((2, T) + buckets) + 1j * rng.standard_normal((2, T) + buckets))
+    grad = grad.astype(np.complex64)
+    gf, ga = plan.model_backward(a_d, torch.tensor(grad.reshape(-1), device="cuda"), ws)
+    gf, ga = gf.cpu().numpy(), ga.cpu().numpy()
+    for f in range(2):
+        wf, wa = RF.gradients(freqs[f], amps[f].astype(np.complex64), oplan,
+                              grad[f].astype(np.complex128))
+        assert np.max(np.abs(gf[f] - wf)) <= 1e-3 * np.max(np.abs(wf))
+        assert np.max(np.abs(ga[f] - wa)) <= 1e-3 * np.max(np.abs(wa))
+    plan.close()
+
+
+def test_autograd_gradients_match_fp64_central_differences():
+    """loss = sum |model - observed|^2 through BucketModel; its gradients
+    against FP64 central differences (h = 1e-6) of the oracle's loss."""
+    from paper_1610_01050_amd.refine import model_loss
+    shape, buckets, K = (128, 128), (16, 16), 3
+    plan, oplan, freqs, amps, rng = _setup(shape, buckets, K, seed=41, batch=1)
+    truth_f = freqs + rng.uniform(-0.3, 0.3, freqs.shape) / np.array(shape)
+    x = synth.synthesize(shape, truth_f[0], None, amps[0] * 1.2) + synth.complex_noise(rng, shape)
+    observed = RF.round_buckets(x, oplan)
+    obs_d = torch.tensor(observed.astype(np.complex64).reshape(-1), device="cuda")
+    f_d, a_d = _dev(freqs, amps)
+    f_d.requires_grad_(True)
+    a_d.requires_grad_(True)
+    loss = model_loss(f_d, a_d, plan, obs_d)
+    loss.backward()
+    gf = f_d.grad.cpu().numpy()[0]
+    ga = a_d.grad.cpu().numpy()[0]
+    a64 = amps[0].astype(np.complex64).astype(np.complex128)
+    h = 1e-6
+    for t in range(K):
+        for d in range(2):
+            fp, fm = freqs[0].copy(), freqs[0].copy()
+            fp[t, d] += h
+            fm[t, d] -= h
+            cd = (RF.loss(fp, a64, oplan, observed) - RF.loss(fm, a64, oplan, observed)) / (2 * h)
+            assert abs(gf[t, d] - cd) <= 1e-3 * np.max(np.abs(gf))
+        for unit, got in ((1.0, ga[t].real), (1j, ga[t].imag)):
+            ap, am = a64.copy(), a64.copy()
+            ap[t] += h * unit
+            am[t] -= h * unit
+            cd = (RF.loss(freqs[0], ap, oplan, observed) - RF.loss(freqs[0], am, oplan, observed)) / (2 * h)
+            assert abs(got - cd) <= 1e-3 * np.max(np.abs(ga))
+    plan.close()
+
+
+def test_gauss_newton_steps_match_oracle():
+    shape, buckets, K = (256, 128), (16, 16), 3
+    plan, oplan, freqs, amps, rng = _setup(shape, buckets, K, seed=5, batch=1)
+    truth_f = freqs + rng.uniform(-0.2, 0.2, freqs.shape) / np.array(shape)
+    x = synth.synthesize(shape, truth_f[0], None, amps[0]) + synth.complex_noise(rng, shape)
+    observed = RF.round_buckets(x, oplan)
+    obs_d = torch.tensor(observed.astype(np.complex64).reshape(-1), device="cuda")
+    start_a = (amps * 0.9).astype(np.complex64)
+    f_d, a_d = _dev(freqs, start_a)
+    ws = plan.model_workspace(1, K)
+    m = plan.model_forward(f_d, a_d, ws)
+    _, _, sf, sa = plan.model_backward(a_d, 2.0 * (m - obs_d), ws, steps=True)
+    wf, wa = RF.gauss_newton_steps(freqs[0], start_a[0].astype(np.complex128), oplan, observed)
+    assert np.max(np.abs(sf.cpu().numpy()[0] - wf)) <= 2e-3 * np.max(np.abs(wf))
+    assert np.max(np.abs(sa.cpu().numpy()[0] - wa)) <= 2e-3 * np.max(np.abs(wa))
+    plan.close()
+
+
+def test_refinement_reaches_the_noise_floor():
+    """20 Gauss-Newton steps from 0.25 bin / 20% amplitude errors: the loss
+    ends at or below the loss of the true parameters (the fit is noise-
+    limited) and the frequency error shrinks."""
+    from paper_1610_01050_amd.refine import refine
+    shape, buckets, K = (512, 512), (32, 32), 6
+    plan, oplan, freqs, amps, rng = _setup(shape, buckets, K, seed=77, batch=2)
+    amps = amps * 4.0
+    obs = []
+    for f in range(2):
+        x = synth.synthesize(shape, freqs[f], None, amps[f]) + synth.complex_noise(rng, shape)
+        obs.append(RF.round_buckets(x, oplan).astype(np.complex64).reshape(-1))
+    obs_d = torch.tensor(np.concatenate(obs), device="cuda")
+    start_f = freqs + rng.normal(0, 0.25, freqs.shape) / np.array(shape)
+    start_a = amps * (1 + 0.2 * (rng.standard_normal(amps.shape) + 1j * rng.standard_normal(amps.shape)))
+    f_d, a_d = _dev(start_f, start_a)
+    fr, ar, losses = refine(plan, obs_d, f_d, a_d, steps=20)
+    losses = losses.cpu().numpy()
+    truth_loss = sum(RF.loss(freqs[f], amps[f], oplan, obs[f].reshape((3,) + buckets))
+                     for f in range(2))
+    assert losses[-1] <= truth_loss * (1 + 1e-3)
+    err0 = np.abs(((start_f - freqs + 0.5) % 1) - 0.5) * np.array(shape)
+    err1 = np.abs(((fr.cpu().numpy() - freqs + 0.5) % 1) - 0.5) * np.array(shape)
+    print(f"freq error rms {np.sqrt((err0 ** 2).mean()):.3f} -> {np.sqrt((err1 ** 2).mean()):.3f} bin")
+    assert np.sqrt((err1 ** 2).mean()) < 0.5 * np.sqrt((err0 ** 2).mean())
+    plan.close()
+
+
+@pytest.mark.timeout(300)
+def test_refinement_workload_2048x2048_sampled():
+    """16 frames of 2048x2048, K = 32 tones, B = 128x128: the forward model of
+    frame 0 against the oracle, and the gradients of two of its tones."""
+    from paper_1610_01050_amd import Plan
+    cfg = synth.CONFIGS[5]
+    shape, buckets = cfg["shape"], cfg["buckets"]
+    sigma = synth.shared_sigma(5)
+    plan = Plan(shape, buckets, rounds=3, sigma=sigma, pfa=cfg["pfa"], max_batch=16)
+    oplan = OR.OraclePlan(shape, buckets, sigma, 60.0, None, cfg["pfa"])
+    metas = [synth.make_frame(5, f, noise=False) for f in range(16)]
+    freqs = np.stack([m["freqs"] for m in metas])
+    amps = np.stack([m["amps"] for m in metas]).astype(np.complex64)
+    f_d, a_d = _dev(freqs, amps)
+    ws = plan.model_workspace(16, 32)
+    model = _frames(plan.model_forward(f_d, a_d, ws), plan, 16)
+    want = RF.model(freqs[0], amps[0].astype(np.complex128), oplan)
+    for s in range(3):
+        rms = np.sqrt(np.mean(np.abs(want[s]) ** 2))
+        assert np.max(np.abs(model[0, s] - want[s])) <= 1e-4 * rms
+    rng = np.random.default_rng(3)
+    grad = (rng.standard_normal((16, 3) + buckets) + 1j * rng.standard_normal((16, 3) + buckets))
+    grad = grad.astype(np.complex64)
+    gf, ga = plan.model_backward(a_d, torch.tensor(grad.reshape(-1), device="cuda"), ws)
+    gf, ga = gf.cpu().numpy(), ga.cpu().numpy()
+    wf, wa = RF.gradients(freqs[0], amps[0].astype(np.complex128), oplan,
+                          grad[0].astype(np.complex128), tones=[0, 17])
+    for t in (0, 17):
+        assert np.max(np.abs(gf[0, t] - wf[t])) <= 1e-3 * np.max(np.abs(wf[[0, 17]]))
+        assert abs(ga[0, t] - wa[t]) <= 1e-3 * np.max(np.abs(wa[[0, 17]]))
+    plan.close()
