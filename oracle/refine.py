@@ -93,11 +93,12 @@ def loss_gradients(freqs, amps, plan, observed, tones=None):
     return gradients(freqs, amps, plan, g, tones)
 
 
-def gauss_newton_steps(freqs, amps, plan, observed):
+def gauss_newton_steps(freqs, amps, plan, observed, trust_bins=0.25):
     """Each tone's Gauss-Newton step for loss(), tones treated as decoupled:
     with residual r = model - observed and the tone's Jacobian columns
     J = [P, jP, b_t dP/df_0, ..., b_t dP/df_{D-1}] (P = Round(v(f_t))), the
-    step x over (Re b_t, Im b_t, f_t) solves Re(J^H J) x = -Re(J^H r).
+    step x over (Re b_t, Im b_t, f_t) solves Re(J^H J) x = -Re(J^H r); each
+    frequency step is then clipped to trust_bins / N_d (a trust region).
     Returns (step_freqs [K][D], step_amps [K] complex)."""
     r = model(freqs, amps, plan) - observed
     K = len(freqs)
@@ -113,5 +114,6 @@ def gauss_newton_steps(freqs, amps, plan, observed):
         g = np.array([np.real(np.vdot(Ji, r)) for Ji in J])
         x = np.linalg.solve(H, -g)
         sa[t] = x[0] + 1j * x[1]
-        sf[t] = x[2:]
+        cap = trust_bins / np.array(plan.shape, dtype=np.float64)
+        sf[t] = np.clip(x[2:], -cap, cap)
     return sf, sa

@@ -58,7 +58,7 @@ class OraclePlan:
     buckets, permutations, Pfa), with everything derived from them in FP64."""
 
     def __init__(self, shape, buckets, sigma, window_atten_db=60.0,
-                 flat_atten_db=None, pfa=1e-3, mu=None, noise_var=1.0):
+                 flat_atten_db=None, pfa=1e-3, mu=None, noise_var=1.0, stage1_pfa=None):
         self.shape = tuple(int(n) for n in shape)
         self.B = tuple(int(b) for b in buckets)
         self.D = len(self.shape)
@@ -83,7 +83,10 @@ class OraclePlan:
                      for n, b in zip(self.shape, self.B)]
         self.noise_var = float(noise_var)
         self.pfa = float(pfa)
-        self.p1 = stage1_probability(self.pfa, self.T, self.mu)
+        # first-stage false-alarm probability: given directly (e.g. from the
+        # design of eq. opt), or from the final Pfa by the exact binomial
+        self.p1 = (float(stage1_pfa) if stage1_pfa is not None
+                   else stage1_probability(self.pfa, self.T, self.mu))
         self.beta = np.array([self.beta_of_round(s) for s in range(self.T)])
         # eq. tpd: Pfa~(sigma_s) = exp(-gamma / (sigma_n^2 beta(sigma_s))) = p1
         self.gamma = self.noise_var * self.beta * math.log(1.0 / self.p1)
@@ -151,18 +154,22 @@ def reverse_map_into(abar, flags, plan, s):
         abar[np.ix_(*sets)] += 1
 
 
-def rsft(r, plan, noise="known"):
+def rsft(r, plan, noise="known", segments=False):
     """Algorithm 1. Returns a dict with the per-round buckets fhat_s, the
     first-stage flags c_s, the thresholds used, the accumulated votes abar and
     the detections o (row-major flat cell indices, ascending). noise="known"
     uses gamma_s = sigma_n^2 beta(sigma_s) ln(1/p1); "estimated" replaces
-    sigma_n^2 beta(sigma_s) by estimated_noise_floor of the round."""
+    sigma_n^2 beta(sigma_s) by estimated_noise_floor of the round.
+    segments=True: r holds T data segments [T, *shape] and round s processes
+    segment s (the T segments of the signal model, Sec. IV-A)."""
     buckets = []
     flags = []
     gammas = []
     abar = np.zeros(plan.shape, dtype=np.int64)
+    if segments and np.shape(r)[0] != plan.T:
+        raise ValueError("segment mode needs T segments")
     for s in range(plan.T):
-        fhat = rsft_round(r, plan, s)
+        fhat = rsft_round(r[s] if segments else r, plan, s)
         if noise == "known":
             gamma = plan.gamma[s]
         else:
