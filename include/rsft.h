@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define RSFT_MAX_DIMS 4
-#define RSFT_MAX_ROUNDS 32
+#define RSFT_MAX_ROUNDS 64
 
 typedef enum {
   RSFT_OK = 0,
@@ -70,8 +70,9 @@ enum { RSFT_NOISE_KNOWN = 0, RSFT_NOISE_ESTIMATED = 1 };
  * n[d], b[d]      N_d and B_d, powers of two with 1 <= B_d < N_d (Sec. II
  *                 notation; Definition 2 requires B < N). Entries d >= ndim
  *                 are ignored. N = prod N_d must be < 2^40.
- * rounds          T, 1..RSFT_MAX_ROUNDS: iterations of Algorithm 1 over the
- *                 same frame with independent permutations.
+ * rounds          T, 1..RSFT_MAX_ROUNDS: iterations of Algorithm 1 with
+ *                 independent permutations, over the same frame (segments
+ *                 = 0) or over T data segments (segments = 1).
  * sigma           host pointer to T*ndim permutation factors, round-major
  *                 (sigma[s*ndim + d]); each odd and in [1, N_d) (Definition 1:
  *                 sigma invertible mod N_d). NULL: drawn from `seed`,
@@ -100,6 +101,16 @@ enum { RSFT_NOISE_KNOWN = 0, RSFT_NOISE_ESTIMATED = 1 };
  * max_detections  record capacity per frame, 1..2^24; 0 = 16384.
  * max_batch       frames per execute for a uniform plan (nframes == 1),
  *                 >= 1; 0 = 1. Ignored when nframes > 1.
+ * segments        0: every round reads the same frame. 1: segment mode
+ *                 (Sec. IV-A, the T data segments of the signal model, as in
+ *                 the Bartlett method of Appendix A): a frame is T segments
+ *                 of N samples, [T][N_0]...[N_{D-1}], and round s processes
+ *                 segment s with sigma_s; votes accumulate over the segments.
+ *                 Every descriptor of a plan must agree.
+ * reserved0       must be 0.
+ * stage1_pfa      > 0: the first-stage false-alarm probability p1 of every
+ *                 round itself, in (0, 1) (e.g. the design of eq. opt); pfa
+ *                 is then not used to derive it. 0: p1 from pfa as above.
  */
 typedef struct {
   int32_t ndim;
@@ -117,6 +128,9 @@ typedef struct {
   int32_t dtype;
   int32_t max_detections;
   int64_t max_batch;
+  int32_t segments;
+  int32_t reserved0;
+  double stage1_pfa;
 } rsft_params;
 
 /*
@@ -158,8 +172,7 @@ typedef struct {
   double eta_m;              /* product over d of the window's 6-dB width (bins) */
   double max_sparsity;       /* B / eta_m: by Remark 2 (Sec. IV-C) RSFT fails for
                                 K >= this many tones, whatever their SNR */
-  int32_t estimation_rounds; /* bit s set: round s feeds magnitude estimates */
-  int32_t reserved;
+  uint64_t estimation_rounds; /* bit s set: round s feeds magnitude estimates */
   /* plan-wide launch shape of the fold stage (see rsft_autotune) */
   int32_t fold_threads;      /* work-group size */
   int32_t fold_vec;          /* complex samples per thread per row */
@@ -284,8 +297,8 @@ rsft_status rsft_vote_flags(rsft_plan_t plan, const uint32_t* d_flags, void* str
  *   d_workspace  device buffer of rsft_model_workspace_size bytes; the
  *            forward call stores the per-dimension factors there and the
  *            backward call reads them (same plan, batch, K and frequencies)
- * Errors: INVALID_ARGUMENT (NULL, bad batch or K), UNSUPPORTED (mixed D),
- * DEVICE. Async on `stream`.
+ * Errors: INVALID_ARGUMENT (NULL, bad batch or K), UNSUPPORTED (mixed D, or
+ * a segment-mode plan), DEVICE. Async on `stream`.
  */
 rsft_status rsft_model_workspace_size(rsft_plan_t plan, int64_t batch, int32_t tones,
                                       int64_t* bytes);
@@ -306,7 +319,8 @@ rsft_status rsft_model_forward(rsft_plan_t plan, const double* d_freqs, const vo
  * H = Re(J^H J), J = [P, jP, b_t dP/df_0, ...], P = prod_d G_d, over the
  * tone's own parameters (Re b_t, Im b_t, f_t); tones are treated as
  * decoupled (block-diagonal H), H is solved in FP64 with 1e-6 Levenberg
- * damping, and a vanishing pivot leaves that parameter unchanged.
+ * damping, a vanishing pivot leaves that parameter unchanged, and each
+ * frequency step is clipped to a quarter bin (1/(4 N_d)), a trust region.
  * d_step_freqs: double [batch][K][D]; d_step_amps: complex64 [batch][K].
  * d_workspace must hold the factors of the matching forward call.
  * Async on `stream`.

@@ -16,7 +16,7 @@ LIB_NAME = "librsft.so"
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), LIB_NAME)
 
 MAX_DIMS = 4
-MAX_ROUNDS = 32
+MAX_ROUNDS = 64
 
 OK = 0
 STATUS_NAMES = {
@@ -54,7 +54,8 @@ class Params(ctypes.Structure):
         ("pfa", ctypes.c_double), ("mu", ctypes.c_int32),
         ("noise_mode", ctypes.c_int32), ("noise_var", ctypes.c_double),
         ("dtype", ctypes.c_int32), ("max_detections", ctypes.c_int32),
-        ("max_batch", ctypes.c_int64),
+        ("max_batch", ctypes.c_int64), ("segments", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32), ("stage1_pfa", ctypes.c_double),
     ]
 
 
@@ -87,7 +88,7 @@ class PlanInfo(ctypes.Structure):
         ("gamma", ctypes.c_double * MAX_ROUNDS),
         ("p1", ctypes.c_double), ("eta_m", ctypes.c_double),
         ("max_sparsity", ctypes.c_double),
-        ("estimation_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("estimation_rounds", ctypes.c_uint64),
         ("fold_threads", ctypes.c_int32), ("fold_vec", ctypes.c_int32),
         ("fold_nontemporal", ctypes.c_int32), ("reserved2", ctypes.c_int32),
     ]
@@ -208,7 +209,8 @@ def draw_sigma(seed, rounds, shape):
 
 def _make_params(shape, buckets, rounds=3, sigma=None, seed=0, window_atten_db=60.0,
                  flat_atten_db=-1.0, pfa=1e-3, mu=0, noise_mode="known",
-                 noise_var=1.0, dtype="c64", max_detections=0, max_batch=1):
+                 noise_var=1.0, dtype="c64", max_detections=0, max_batch=1,
+                 segments=False, stage1_pfa=0.0):
     """Fill a Params struct; returns (params, keepalive) where keepalive
     holds the sigma array for the duration of rsft_plan."""
     shape = tuple(int(v) for v in shape)
@@ -238,6 +240,8 @@ def _make_params(shape, buckets, rounds=3, sigma=None, seed=0, window_atten_db=6
     p.dtype = {"c64": C64, "c128": C128}[dtype]
     p.max_detections = int(max_detections)
     p.max_batch = int(max_batch)
+    p.segments = int(segments)
+    p.stage1_pfa = float(stage1_pfa)
     return p, keep
 
 
@@ -297,6 +301,8 @@ class Plan:
         if not x.is_contiguous():
             raise ValueError("input must be contiguous")
         need = sum(int(np.prod(s)) for s in self._frame_shapes(batch))
+        if self.descs[0].get("segments"):
+            need *= self.rounds                     # [T] segments per frame
         if x.numel() < need:
             raise ValueError(f"input holds {x.numel()} elements, batch needs {need}")
 

@@ -119,7 +119,9 @@ __device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restr
   const float2* __restrict__ wrow = p.wrow + d.wrow_off;
   const float2* __restrict__ wcol = p.wcol + d.wcol_off;
   const int32_t* __restrict__ rl = p.rowlist + d.rowlist_off + int64_t(cls) * R;
-  const int64_t in_base = d.in_off + rel * d.in_stride;
+  // segment mode: a launch folds one round (round0), whose samples are the
+  // frame's segment round0
+  const int64_t in_base = d.in_off + rel * d.in_stride + (d.segments ? int64_t(round0) * d.N : 0);
   const void* in = C128 ? static_cast<const void*>(static_cast<const double2*>(input) + in_base)
                         : static_cast<const void*>(static_cast<const float2*>(input) + in_base);
 
@@ -1338,7 +1340,7 @@ __global__ __launch_bounds__(kPlainThreads) void plain_fold_kernel(DevPtrs p, co
   const int lane = threadIdx.x & 63;
   const int b = blockIdx.x * (kPlainThreads / 64) + (threadIdx.x >> 6);
   if (b >= d.B) return;
-  const int64_t in_base = d.in_off + rel * d.in_stride;
+  const int64_t in_base = d.in_off + rel * d.in_stride + (d.segments ? int64_t(s) * d.N : 0);
   const int64_t L = int64_t(1) << d.Lshift;
   float accr = 0.f, acci = 0.f;
   for (int64_t l = lane; l < L; l += 64) {

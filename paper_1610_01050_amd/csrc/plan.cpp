@@ -65,6 +65,7 @@ struct rsft_plan_s {
   int64_t ndesc = 0;
   int64_t max_frames = 0;      // frames one execute may process
   int T = 0, mu = 0, dtype = 0;
+  int segments = 0;            // 1: round s of a frame reads its segment s
   std::vector<rsft::FrameDesc> descs;
   std::vector<rsft_plan_info_t> info;
   rsft::FoldConfig fold{256, 4, 0};
@@ -101,7 +102,7 @@ rsft_status validate(const rsft_params& p, int64_t idx) {
   const std::string at = "frame descriptor " + std::to_string(idx) + ": ";
   if (p.ndim < 1 || p.ndim > RSFT_MAX_DIMS) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "ndim must be 1..4");
   if (p.rounds < 1 || p.rounds > RSFT_MAX_ROUNDS)
-    return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "rounds must be 1..32");
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "rounds must be 1..64");
   int64_t N = 1, B = 1;
   for (int d = 0; d < p.ndim; ++d) {
     if (!is_pow2(p.n[d]) || !is_pow2(p.b[d]))
@@ -128,6 +129,10 @@ rsft_status validate(const rsft_params& p, int64_t idx) {
   if (p.max_detections < 0 || p.max_detections > rsft::kMaxDetectionsPerFrame)
     return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "max_detections must be 0..2^24");
   if (p.max_batch < 0) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "max_batch must be >= 0");
+  if (p.segments != 0 && p.segments != 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "segments must be 0 or 1");
+  if (p.reserved0 != 0) return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "reserved0 must be 0");
+  if (!(p.stage1_pfa >= 0.0 && p.stage1_pfa < 1.0))
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, at + "stage1_pfa must be in [0, 1)");
   if (p.sigma) {
     for (int s = 0; s < p.rounds; ++s)
       for (int d = 0; d < p.ndim; ++d) {
@@ -174,9 +179,9 @@ struct HostTables {
 // main-lobe bins of one tone never share a bucket; the first (up to
 // kMaxEstRounds) clean rounds are used, else the one whose worst distance is
 // largest (first on ties).
-int estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma) {
+uint64_t estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma) {
   std::vector<int64_t> score(static_cast<size_t>(p.rounds));
-  int mask = 0;
+  uint64_t mask = 0;
   for (int s = 0; s < p.rounds; ++s) {
     int64_t worst = INT64_MAX;
     for (int d = 0; d < p.ndim; ++d) {
@@ -188,13 +193,13 @@ int estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma) {
       }
     }
     score[size_t(s)] = worst;
-    if (worst >= 0 && __builtin_popcount(unsigned(mask)) < rsft::kMaxEstRounds) mask |= 1 << s;
+    if (worst >= 0 && __builtin_popcountll(mask) < rsft::kMaxEstRounds) mask |= uint64_t(1) << s;
   }
   if (mask) return mask;
   int best = 0;
   for (int s = 1; s < p.rounds; ++s)
     if (score[size_t(s)] > score[size_t(best)]) best = s;
-  return 1 << best;
+  return uint64_t(1) << best;
 }
 
 rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan_info_t& info,
@@ -206,6 +211,7 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
   const int mu = p.mu == 0 ? T : p.mu;
   d.ndim = D;
   d.T = T;
+  d.segments = p.segments;
   d.mu = mu;
   d.noise_mode = p.noise_mode;
   int64_t N = 1, B = 1;
@@ -253,7 +259,7 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
   d.est_mask = estimation_mask(p, sigma);
   d.n_est = 0;
   for (int s = 0; s < T; ++s)
-    if ((d.est_mask >> s) & 1) d.est_rounds[d.n_est++] = s;
+    if ((d.est_mask >> s) & 1u) d.est_rounds[d.n_est++] = s;
 
   // windows (Sec. III-C.1, Sec. IV-B) per dimension, FP64
   const double flat_db = p.flat_atten_db < 0.0 ? p.window_atten_db : p.flat_atten_db;
@@ -276,7 +282,7 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
         v[size_t(m)] = w[size_t(k)][size_t(m)] * wbar[size_t(k)][size_t((inv * m) % p.n[k])];
     }
   // beta(sigma_s) = ||Wbar P_sigma w||^2 (eq. alpha_beta), separable over dims
-  const double p1 = rsft::stage1_probability(p.pfa, T, mu);
+  const double p1 = p.stage1_pfa > 0.0 ? p.stage1_pfa : rsft::stage1_probability(p.pfa, T, mu);
   d.log_inv_p1 = std::log(1.0 / p1);
   for (int s = 0; s < T; ++s) {
     double beta = 1.0;
@@ -422,6 +428,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   pl->T = frames[0].rounds;
   pl->mu = frames[0].mu == 0 ? frames[0].rounds : frames[0].mu;
   pl->dtype = frames[0].dtype;
+  pl->segments = frames[0].segments;
   pl->max_frames = pl->uniform ? std::max<int64_t>(frames[0].max_batch, 1) : nframes;
 
   // fold launch shape: P = threads * vec covers the largest B_{D-1}
@@ -454,7 +461,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     auto& d = pl->descs[size_t(i)];
     const int64_t mult = pl->uniform ? pl->max_frames : 1;
     d.in_off = in_off;
-    d.in_stride = d.N;
+    d.in_stride = pl->segments ? d.N * d.T : d.N;   // segment mode: [T][N] per frame
     d.part_off = part_off;
     d.part_stride = int64_t(d.nchunks) * d.T * d.B;
     d.bucket_off = bucket_off;
@@ -589,6 +596,13 @@ rsft_status fold_stage(rsft_plan_s* pl, const void* d_input, int64_t batch, hipS
   const auto& q = pl->ptrs;
   const int64_t ntiles = pl->uniform ? batch * pl->tiles_per_frame : pl->ntiles_uneven;
   if (ntiles >= (int64_t(1) << 31)) return fail(RSFT_ERROR_UNSUPPORTED, "more than 2^31 fold tiles");
+  if (pl->segments) {
+    // round s folds segment s of every frame (the kernels offset by s * N)
+    for (int r = 0; r < pl->T; ++r)
+      LAUNCH_TRY(rsft::launch_fold(q, d_input, pl->dtype, batch, pl->tiles_per_frame, ntiles, r, 1, pl->T,
+                                   cfg, st));
+    return RSFT_OK;
+  }
   for (int r0 = 0; r0 < pl->T; r0 += rsft::kFoldRoundGroup) {
     const int rounds = std::min(rsft::kFoldRoundGroup, pl->T - r0);
     LAUNCH_TRY(rsft::launch_fold(q, d_input, pl->dtype, batch, pl->tiles_per_frame, ntiles, r0, rounds,
@@ -649,8 +663,10 @@ rsft_status rsft_plan(const rsft_params* frames, int64_t nframes, rsft_plan_t* o
     if (vs != RSFT_OK) return vs;
     const int mu_i = frames[i].mu == 0 ? frames[i].rounds : frames[i].mu;
     const int mu_0 = frames[0].mu == 0 ? frames[0].rounds : frames[0].mu;
-    if (frames[i].rounds != frames[0].rounds || mu_i != mu_0 || frames[i].dtype != frames[0].dtype)
-      return fail(RSFT_ERROR_INVALID_ARGUMENT, "rounds, mu and dtype must agree across frame descriptors");
+    if (frames[i].rounds != frames[0].rounds || mu_i != mu_0 || frames[i].dtype != frames[0].dtype ||
+        frames[i].segments != frames[0].segments)
+      return fail(RSFT_ERROR_INVALID_ARGUMENT,
+                  "rounds, mu, dtype and segments must agree across frame descriptors");
   }
   auto* pl = new (std::nothrow) rsft_plan_s();
   if (!pl) return fail(RSFT_ERROR_OUT_OF_MEMORY, "host allocation failed");
@@ -800,6 +816,8 @@ rsft_status check_model(rsft_plan_s* pl, int64_t batch, int32_t tones) {
   if (batch > 65535) return fail(RSFT_ERROR_UNSUPPORTED, "more than 65535 frames per model call");
   if ((pl->dims_mask & (pl->dims_mask - 1)) != 0)
     return fail(RSFT_ERROR_UNSUPPORTED, "the model needs one dimension count across descriptors");
+  if (pl->segments)
+    return fail(RSFT_ERROR_UNSUPPORTED, "the model describes one frame seen by every round, not segments");
   return RSFT_OK;
 }
 

@@ -384,7 +384,11 @@ __global__ __launch_bounds__(kBackThreads) void model_backward_kernel(
   for (int d = 0; d < D; ++d) rhs[2 + d] = -0.5 * gfv[d];
   solve_small(H, rhs, n, x);
   step_amps[f * K + t] = make_float2(float(x[0]), float(x[1]));
-  for (int d = 0; d < D; ++d) step_freqs[(f * K + t) * D + d] = x[2 + d];
+  // trust region: at most a quarter bin per step and dimension
+  for (int d = 0; d < D; ++d) {
+    const double cap = 0.25 / double(de.n[d]);
+    step_freqs[(f * K + t) * D + d] = x[2 + d] < -cap ? -cap : (x[2 + d] > cap ? cap : x[2 + d]);
+  }
 }
 
 int launch_model_forward(const DevPtrs& p, const double* freqs, const float2* amps, int64_t batch,

@@ -36,9 +36,9 @@ struct FrameDesc {
   int32_t chunk_cols, nchunks;
   int32_t words;              // flag words per round = ceil(B / 32)
   int32_t cap;                // detection capacity of a frame
-  int32_t est_mask;           // rounds used for magnitude estimates
-  int32_t n_est;              // their number (<= kMaxEstRounds)
-  int32_t est_rounds[kMaxEstRounds];
+  int32_t n_est;              // rounds used for magnitude estimates (<= kMaxEstRounds)
+  int32_t est_rounds[kMaxEstRounds];  // their indices
+  uint64_t est_mask;                   // the same rounds as a bit mask
   int32_t sigma[kMaxRounds][kMaxDims];
   int32_t sigma_inv[kMaxRounds][kMaxDims];
   int32_t tau[kMaxRounds][kMaxDims];      // sigma_inv mod B_d
@@ -63,6 +63,8 @@ struct FrameDesc {
   int64_t chunk_off, chunk_stride;     // uint32 counts / int64 ranks: [cchunks]
   int32_t cchunks;                     // compaction chunks = ceil(N / 2^15)
   int32_t bitmap_words;                // ceil(N / 32)
+  int32_t segments;                    // 1: round s reads segment s (input [T][N] per frame)
+  int32_t pad0;
 };
 
 // Device-side view of a launch: pointers into the plan's arrays.

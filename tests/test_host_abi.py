@@ -96,7 +96,10 @@ def _params(rsft, **kw):
     (dict(sigma=[[65, 3]] * 3), 3),                  # sigma >= N_d
     (dict(pfa=1.5), 1),
     (dict(rounds=0), 1),
-    (dict(rounds=40), 1),
+    (dict(rounds=65), 1),
+    (dict(segments=2), 1),
+    (dict(stage1_pfa=1.0), 1),
+    (dict(stage1_pfa=-0.1), 1),
     (dict(mu=4), 1),
     (dict(shape=(512, 512), buckets=(256, 8)), 4),   # B_d > 128 unsupported
     (dict(noise_var=0.0), 1),
@@ -110,6 +113,14 @@ def test_invalid_plans_fail_before_device(rsft, kw, status):
     assert st == status
     assert h.value is None
     assert rsft.load_library().rsft_last_error()
+
+
+def test_reserved_field_must_be_zero(rsft):
+    p, keep = _params(rsft)
+    p.reserved0 = 7
+    arr = (rsft.Params * 1)(p)
+    h = ctypes.c_void_p()
+    assert rsft.load_library().rsft_plan(arr, 1, ctypes.byref(h)) == 1
 
 
 def test_status_strings(rsft):
