@@ -25,6 +25,7 @@ dense     Algorithm 2 (Bartlett) with T=1 exact exponential threshold and the
 evaluate  the complexity model of Tables I-II.
 refine    the bucketized forward model of off-grid tones (eq. f with a
           continuous frequency) and its gradients, for refinement.
+design    the optimal threshold design (eq. opt, Claims 2-3, eq. bpd).
 """
 
-from . import windows, hashing, rsft, dense, evaluate, refine  # noqa: F401
+from . import windows, hashing, rsft, dense, evaluate, refine, design  # noqa: F401
