@@ -399,6 +399,70 @@ rsft_status rsft_stage1_probability(double pfa, int32_t rounds, int32_t mu,
 rsft_status rsft_draw_sigma(uint64_t seed, int32_t rounds, int32_t ndim,
                             const int64_t* n, int64_t* out);
 
+/*
+ * Optimal threshold design (eq. opt, Sec. IV-C): the smallest SNR of the
+ * weakest tone for which the two-stage detector reaches (pd, pfa), with the
+ * first-stage probabilities of eq. bpd and the asymptotic Normal laws of the
+ * vote count (Claims 2 and 3, variance upper bounds):
+ *   H1: mean T Pd_bar, variance T Pd_bar (1 - Pd_bar)
+ *   H0: mean F eta_p Pd_bar + (T - F) Pfa_bar, variance
+ *       F eta_p Pd_bar (1 - eta_p Pd_bar) + (T - F) Pfa_bar (1 - Pfa_bar),
+ *   F = T K eta_m / B;
+ * mu is enumerated over 1..T (a cell is declared at >= mu votes); for each,
+ * the two tails fix Pd_bar and Pfa_bar, eq. bpd gives
+ *   SNR = beta_bar (ln Pfa_bar / ln Pd_bar - 1) / alpha_bar,
+ * and the minimum over mu is SNR*_min at mu*. alpha_bar and beta_bar are the
+ * averages of alpha(p, sigma, omega) and beta(sigma) (eq. alpha_beta, p the
+ * bucket of Claim 1) over all odd sigma of each dimension, multiplied over
+ * dimensions (independent permutations per dimension). FP64, host only.
+ *
+ * in:  ndim, rounds T, n[d], b[d] (as rsft_params); window_atten_db,
+ *      flat_atten_db (< 0: same as the window); omega_bins[d], the frequency
+ *      of the weakest tone in bins; sparsity K; eta_m (6-dB width of the
+ *      pre-window in bins, product over dimensions; <= 0: measured from the
+ *      window); pd, pfa: targets after the second stage; upper_bound: 0 for
+ *      eta_p = 1, 1 for eta_p = 1 / Pd_bar (the bounds of Remark 3);
+ *      noise_var sigma_n^2 (> 0).
+ * out: feasible (0 when no mu meets both targets, e.g. K eta_m >= B,
+ *      Remark 2; the other fields are then 0), mu*, SNR*_min (linear and
+ *      dB), Pd_bar, Pfa_bar (pass it as rsft_params.stage1_pfa, and mu* as
+ *      rsft_params.mu, to run the design), gamma* = -noise_var beta_bar
+ *      ln Pfa_bar, alpha_bar, beta_bar, F, eta_p, eta_m used.
+ */
+typedef struct {
+  int32_t ndim;
+  int32_t rounds;
+  int64_t n[RSFT_MAX_DIMS];
+  int64_t b[RSFT_MAX_DIMS];
+  double window_atten_db;
+  double flat_atten_db;
+  double omega_bins[RSFT_MAX_DIMS];
+  double sparsity;
+  double eta_m;
+  double pd;
+  double pfa;
+  int32_t upper_bound;
+  int32_t reserved;
+  double noise_var;
+} rsft_design_params;
+
+typedef struct {
+  int32_t feasible;
+  int32_t mu;
+  double snr_min;
+  double snr_min_db;
+  double pd_bar;
+  double pfa_bar;
+  double gamma;
+  double alpha_bar;
+  double beta_bar;
+  double F;
+  double eta_p;
+  double eta_m;
+} rsft_design_result;
+
+rsft_status rsft_design_thresholds(const rsft_design_params* in, rsft_design_result* out);
+
 #ifdef __cplusplus
 }
 #endif

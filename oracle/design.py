@@ -118,3 +118,56 @@ def design(T, K, B, eta_m, pd, pfa, alpha_bar, beta_bar, bound="lower", noise_va
     best["snr_min_db"] = 10.0 * math.log10(best["snr_min"])
     best["gamma"] = -noise_var * beta_bar * math.log(best["pfa_bar"])
     return best
+
+
+def stage1_detection(alpha, beta, snr, p1):
+    """eq. tpd for one round: with gamma = sigma_n^2 beta ln(1/p1), a bucket
+    holding the tone (|fhat|^2 exponential with mean sigma_n^2 (alpha SNR +
+    beta)) is flagged with probability p1 ** (beta / (alpha SNR + beta))."""
+    return p1 ** (beta / (alpha * snr + beta))
+
+
+def poisson_binomial_tail(probs, mu):
+    """P[sum of independent Bernoulli(probs[s]) >= mu] by dynamic programming
+    over the rounds (the exact law of the vote count of eq. a_i when the
+    rounds see independent data)."""
+    dist = np.zeros(len(probs) + 1)
+    dist[0] = 1.0
+    for q in probs:
+        dist[1:] = dist[1:] * (1.0 - q) + dist[:-1] * q
+        dist[0] *= 1.0 - q
+    return float(dist[mu:].sum())
+
+
+def exact_cell_rates(plan, tones, p1, noise_var=1.0):
+    """Per-cell probability of >= mu votes in segment mode (round s on its
+    own data segment) for a frame of K tones, tones = [(freq_bins [D],
+    snr)], with Swerling-I amplitudes drawn independently per segment and
+    CN(0, noise_var) noise, at thresholds gamma_s = noise_var beta_s ln(1/p1).
+    Round s's bucket j is a sum of independent circular Gaussians, so its
+    power is exponential with mean noise_var (beta_s + sum_t snr_t A_{s,t}[j])
+    (A_{s,t}: the bucket powers of the unit tone t through the literal
+    round), and it is flagged with probability p1 ** (beta_s / (beta_s +
+    sum_t snr_t A_{s,t}[j])) (eq. exp, eq. tpd), independently across rounds;
+    a cell collects the flags of its buckets M(i, sigma_s) (Def. 3), so its
+    count is Poisson-binomial. Returns an array of the plan's shape."""
+    T = plan.T
+    q = []
+    for s in range(T):
+        mean = np.full(plan.B, plan.beta[s], dtype=np.float64)
+        for fb, snr in tones:
+            freq = np.asarray(fb, dtype=np.float64) / np.asarray(plan.shape, dtype=np.float64)
+            v = np.ones((), dtype=np.complex128)
+            for d, n in enumerate(plan.shape):
+                v = np.multiply.outer(v, np.exp(2j * np.pi * freq[d] * np.arange(n)))
+            mean = mean + snr * np.abs(_rsft.rsft_round(v, plan, s)) ** 2 / noise_var
+        flag = p1 ** (plan.beta[s] / mean)
+        idx = [((int(plan.sigma[s, d]) * np.arange(n, dtype=np.int64)) % n) // plan.L[d]
+               for d, n in enumerate(plan.shape)]
+        q.append(flag[np.ix_(*idx)])
+    dist = np.zeros((T + 1,) + plan.shape)
+    dist[0] = 1.0
+    for qs in q:
+        dist[1:] = dist[1:] * (1.0 - qs) + dist[:-1] * qs
+        dist[0] = dist[0] * (1.0 - qs)
+    return dist[plan.mu:].sum(axis=0)

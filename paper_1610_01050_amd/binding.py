@@ -42,6 +42,7 @@ SYMBOLS = (
     "rsft_chebyshev_window", "rsft_flat_window", "rsft_mod_inverse",
     "rsft_stage1_probability", "rsft_draw_sigma",
     "rsft_model_workspace_size", "rsft_model_forward", "rsft_model_backward",
+    "rsft_design_thresholds",
 )
 
 
@@ -74,6 +75,29 @@ DETECTION_DTYPE = np.dtype([
     ("freq", "<f8", (MAX_DIMS,)),
 ])
 assert DETECTION_DTYPE.itemsize == ctypes.sizeof(Detection)
+
+
+class DesignParams(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("rounds", ctypes.c_int32),
+        ("n", ctypes.c_int64 * MAX_DIMS), ("b", ctypes.c_int64 * MAX_DIMS),
+        ("window_atten_db", ctypes.c_double), ("flat_atten_db", ctypes.c_double),
+        ("omega_bins", ctypes.c_double * MAX_DIMS), ("sparsity", ctypes.c_double),
+        ("eta_m", ctypes.c_double), ("pd", ctypes.c_double), ("pfa", ctypes.c_double),
+        ("upper_bound", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("noise_var", ctypes.c_double),
+    ]
+
+
+class DesignResult(ctypes.Structure):
+    _fields_ = [
+        ("feasible", ctypes.c_int32), ("mu", ctypes.c_int32),
+        ("snr_min", ctypes.c_double), ("snr_min_db", ctypes.c_double),
+        ("pd_bar", ctypes.c_double), ("pfa_bar", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("alpha_bar", ctypes.c_double),
+        ("beta_bar", ctypes.c_double), ("F", ctypes.c_double),
+        ("eta_p", ctypes.c_double), ("eta_m", ctypes.c_double),
+    ]
 
 
 class PlanInfo(ctypes.Structure):
@@ -146,6 +170,8 @@ def load_library(path=None):
     lib.rsft_model_workspace_size.argtypes = [vp, i64, ctypes.c_int32, ctypes.POINTER(i64)]
     lib.rsft_model_forward.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp]
     lib.rsft_model_backward.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    lib.rsft_design_thresholds.argtypes = [ctypes.POINTER(DesignParams),
+                                           ctypes.POINTER(DesignResult)]
     lib.rsft_draw_sigma.argtypes = [ctypes.c_uint64, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
@@ -203,6 +229,34 @@ def draw_sigma(seed, rounds, shape):
     out = (ctypes.c_int64 * (int(rounds) * len(shape)))()
     _check(lib, lib.rsft_draw_sigma(int(seed), int(rounds), len(shape), n, out))
     return np.array(list(out), dtype=np.int64).reshape(int(rounds), len(shape))
+
+
+def design_thresholds(shape, buckets, rounds, sparsity, pd, pfa, omega_bins,
+                      window_atten_db=60.0, flat_atten_db=-1.0, eta_m=0.0,
+                      upper_bound=False, noise_var=1.0):
+    """Optimal thresholds of eq. opt (rsft_design_thresholds): returns a
+    dict with feasible, mu, snr_min, snr_min_db, pd_bar, pfa_bar (use as
+    stage1_pfa of a plan, with mu), gamma, alpha_bar, beta_bar, F, eta_p,
+    eta_m."""
+    lib = load_library()
+    q = DesignParams()
+    q.ndim = len(shape)
+    q.rounds = int(rounds)
+    for d in range(len(shape)):
+        q.n[d] = int(shape[d])
+        q.b[d] = int(buckets[d])
+        q.omega_bins[d] = float(omega_bins[d])
+    q.window_atten_db = float(window_atten_db)
+    q.flat_atten_db = float(flat_atten_db)
+    q.sparsity = float(sparsity)
+    q.eta_m = float(eta_m)
+    q.pd = float(pd)
+    q.pfa = float(pfa)
+    q.upper_bound = 1 if upper_bound else 0
+    q.noise_var = float(noise_var)
+    r = DesignResult()
+    _check(lib, lib.rsft_design_thresholds(ctypes.byref(q), ctypes.byref(r)))
+    return {name: getattr(r, name) for name, _ in DesignResult._fields_}
 
 
 # ---- plans ------------------------------------------------------------------

@@ -170,4 +170,48 @@ double six_db_width(const std::vector<double>& w) {
   return 2.0 * 0.5 * (lo + hi) * double(n);
 }
 
+void alpha_beta_average(int64_t n, int64_t b, double window_db, double flat_db, double omega_bins,
+                        double* alpha_bar, double* beta_bar) {
+  const std::vector<double> w = chebyshev_window(n, window_db);
+  const std::vector<std::complex<double>> wbar = flat_window(n, b, flat_db);
+  const double two_pi = 6.283185307179586476925286766559;
+  const int64_t k0 = int64_t(std::floor(omega_bins));
+  const double frac = omega_bins - std::floor(omega_bins);
+  double asum = 0.0, bsum = 0.0;
+  int64_t count = 0;
+  for (int64_t sigma = 1; sigma < n; sigma += 2) {
+    // Claim 1: p = floor(B/N [sigma floor(omega / dw)]_N)
+    const int64_t p = ((sigma * k0) % n) * b / n;
+    std::complex<double> acc = 0.0;
+    double beta = 0.0;
+    for (int64_t m = 0; m < n; ++m) {
+      const int64_t u = (sigma * m) % n;             // permuted index [sigma m]_N
+      // exp(j omega u) with omega u / 2 pi = (k0 u mod N + frac u) / N
+      const double cyc = (double((k0 * u) % n) + frac * double(u)) / double(n);
+      // DFT kernel exp(-2 pi i p m / B), phase reduced as an integer
+      const double dft = double((p * m) % b) / double(b);
+      const double ph = two_pi * (cyc - dft);
+      const std::complex<double> z = wbar[size_t(m)] * w[size_t(u)];
+      acc += z * std::complex<double>(std::cos(ph), std::sin(ph));
+      beta += std::norm(z);
+    }
+    asum += std::norm(acc);
+    bsum += beta;
+    ++count;
+  }
+  *alpha_bar = asum / double(count);
+  *beta_bar = bsum / double(count);
+}
+
+static double normal_tail(double z) { return 0.5 * std::erfc(z / std::sqrt(2.0)); }
+
+void stage2_tails(int mu, int T, double F, double eta_p, double pd_bar, double pfa_bar, double* pd,
+                  double* pfa) {
+  const double m1 = T * pd_bar, v1 = T * pd_bar * (1.0 - pd_bar);
+  const double m0 = F * eta_p * pd_bar + (T - F) * pfa_bar;
+  const double v0 = F * eta_p * pd_bar * (1.0 - eta_p * pd_bar) + (T - F) * pfa_bar * (1.0 - pfa_bar);
+  *pd = v1 > 0.0 ? normal_tail((mu - m1) / std::sqrt(v1)) : (m1 >= mu ? 1.0 : 0.0);
+  *pfa = v0 > 0.0 ? normal_tail((mu - m0) / std::sqrt(v0)) : (m0 >= mu ? 1.0 : 0.0);
+}
+
 }  // namespace rsft

@@ -25,5 +25,12 @@ double stage1_probability(double pfa, int T, int mu);
 int64_t draw_sigma(uint64_t seed, int64_t counter, int64_t n);
 // 6-dB main-lobe width in bins.
 double six_db_width(const std::vector<double>& w);
+// Averages over all odd sigma of alpha(p, sigma, omega) (p: Claim 1's bucket)
+// and beta(sigma) for one dimension (eq. alpha_beta).
+void alpha_beta_average(int64_t n, int64_t b, double window_db, double flat_db, double omega_bins,
+                        double* alpha_bar, double* beta_bar);
+// P[vote count >= mu] under H1 and H0 (Claims 2 and 3, variance upper bounds).
+void stage2_tails(int mu, int T, double F, double eta_p, double pd_bar, double pfa_bar, double* pd,
+                  double* pfa);
 
 }  // namespace rsft

@@ -1053,6 +1053,79 @@ rsft_status rsft_stage1_probability(double pfa, int32_t rounds, int32_t mu, doub
   return RSFT_OK;
 }
 
+rsft_status rsft_design_thresholds(const rsft_design_params* in, rsft_design_result* out) {
+  if (!in || !out) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  const rsft_design_params& q = *in;
+  if (q.ndim < 1 || q.ndim > RSFT_MAX_DIMS) return fail(RSFT_ERROR_INVALID_ARGUMENT, "ndim must be 1..4");
+  if (q.rounds < 1 || q.rounds > 100000) return fail(RSFT_ERROR_INVALID_ARGUMENT, "rounds must be >= 1");
+  double B = 1.0;
+  for (int d = 0; d < q.ndim; ++d) {
+    if (!is_pow2(q.n[d]) || !is_pow2(q.b[d])) return fail(RSFT_ERROR_NOT_POW2, "N_d and B_d must be powers of two");
+    if (q.b[d] >= q.n[d]) return fail(RSFT_ERROR_INVALID_ARGUMENT, "need B_d < N_d");
+    if (q.n[d] > (int64_t(1) << 16)) return fail(RSFT_ERROR_UNSUPPORTED, "N_d > 65536 in the design");
+    if (!(q.omega_bins[d] >= 0.0 && q.omega_bins[d] < double(q.n[d])))
+      return fail(RSFT_ERROR_INVALID_ARGUMENT, "omega_bins must be in [0, N_d)");
+    B *= double(q.b[d]);
+  }
+  if (!(q.pd > 0.0 && q.pd < 1.0) || !(q.pfa > 0.0 && q.pfa < 1.0))
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "pd and pfa must be in (0, 1)");
+  if (!(q.sparsity >= 0.0) || !(q.noise_var > 0.0) || !std::isfinite(q.eta_m))
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "sparsity >= 0, noise_var > 0, finite eta_m");
+  if (q.window_atten_db < 0.0 || q.reserved != 0) return fail(RSFT_ERROR_INVALID_ARGUMENT, "bad window or reserved field");
+  const double flat_db = q.flat_atten_db < 0.0 ? q.window_atten_db : q.flat_atten_db;
+  double a_bar = 1.0, b_bar = 1.0, eta_m = 1.0;
+  for (int d = 0; d < q.ndim; ++d) {
+    double a = 0.0, b = 0.0;
+    rsft::alpha_beta_average(q.n[d], q.b[d], q.window_atten_db, flat_db, q.omega_bins[d], &a, &b);
+    a_bar *= a;
+    b_bar *= b;
+    eta_m *= rsft::six_db_width(rsft::chebyshev_window(q.n[d], q.window_atten_db));
+  }
+  if (q.eta_m > 0.0) eta_m = q.eta_m;
+  const int T = q.rounds;
+  const double F = T * q.sparsity * eta_m / B;
+  out->alpha_bar = a_bar;
+  out->beta_bar = b_bar;
+  out->F = F;
+  out->eta_m = eta_m;
+  if (F >= T) return RSFT_OK;                        // Remark 2: infeasible
+  auto bisect = [](auto fun, double lo, double hi, double target) {
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (fun(mid) < target) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+  };
+  bool found = false;
+  for (int mu = 1; mu <= T; ++mu) {
+    const double pd_bar = bisect([&](double x) { double pd, pfa; rsft::stage2_tails(mu, T, F, 1.0, x, 0.0, &pd, &pfa); return pd; },
+                                 1e-15, 1.0 - 1e-15, q.pd);
+    const double eta_p = q.upper_bound ? 1.0 / pd_bar : 1.0;
+    double pd0, pfa0;
+    rsft::stage2_tails(mu, T, F, eta_p, pd_bar, 1e-300, &pd0, &pfa0);
+    if (pfa0 > q.pfa) continue;                       // the co-existing tones alone exceed Pfa
+    const double pfa_bar = bisect([&](double y) { double pd, pfa; rsft::stage2_tails(mu, T, F, eta_p, pd_bar, y, &pd, &pfa); return pfa; },
+                                  1e-300, 1.0 - 1e-15, q.pfa);
+    if (!(pfa_bar < pd_bar)) continue;
+    const double snr = b_bar * (std::log(pfa_bar) / std::log(pd_bar) - 1.0) / a_bar;
+    if (!found || snr < out->snr_min) {
+      found = true;
+      out->feasible = 1;
+      out->mu = mu;
+      out->snr_min = snr;
+      out->pd_bar = pd_bar;
+      out->pfa_bar = pfa_bar;
+      out->eta_p = eta_p;
+    }
+  }
+  if (found) {
+    out->snr_min_db = 10.0 * std::log10(out->snr_min);
+    out->gamma = -q.noise_var * b_bar * std::log(out->pfa_bar);
+  }
+  return RSFT_OK;
+}
+
 rsft_status rsft_draw_sigma(uint64_t seed, int32_t rounds, int32_t ndim, const int64_t* n, int64_t* out) {
   if (!n || !out || rounds < 1 || ndim < 1 || ndim > RSFT_MAX_DIMS) return fail(RSFT_ERROR_INVALID_ARGUMENT, "bad arguments");
   for (int d = 0; d < ndim; ++d)

@@ -137,6 +137,31 @@ def test_product_path_has_no_cpu_fallback(rsft, monkeypatch, tmp_path):
         rsft.load_library()
 
 
+@pytest.mark.parametrize("bound", ["lower", "upper"])
+def test_design_thresholds_match_oracle(rsft, bound):
+    """The library's FP64 design (direct sums, C++) against the oracle's
+    (literal rounds, numpy) on the setting of Figs. 6 and 7."""
+    from oracle import design as DS
+    a_bar, b_bar = DS.alpha_beta_bar((1024,), (64,), 40.0, 40.0, (64.5,))
+    want = DS.design(50, 4, 64, 1.8, 0.9, 1e-6, a_bar, b_bar, bound=bound)
+    got = rsft.design_thresholds((1024,), (64,), 50, 4, 0.9, 1e-6, (64.5,), window_atten_db=40.0,
+                                 eta_m=1.8, upper_bound=bound == "upper")
+    assert got["feasible"] == 1 and got["mu"] == want["mu"]
+    assert abs(got["alpha_bar"] / a_bar - 1) < 1e-9 and abs(got["beta_bar"] / b_bar - 1) < 1e-9
+    for key in ("snr_min", "pd_bar", "pfa_bar", "gamma"):
+        assert abs(got[key] / want[key] - 1) < 1e-6, key
+
+
+def test_design_thresholds_two_dim_and_infeasible(rsft):
+    from oracle import design as DS
+    a_bar, b_bar = DS.alpha_beta_bar((64, 128), (8, 16), 60.0, 60.0, (10.5, 77.25))
+    want = DS.design(20, 3, 128, 4.0, 0.9, 1e-4, a_bar, b_bar)
+    got = rsft.design_thresholds((64, 128), (8, 16), 20, 3, 0.9, 1e-4, (10.5, 77.25), eta_m=4.0)
+    assert got["mu"] == want["mu"] and abs(got["snr_min"] / want["snr_min"] - 1) < 1e-6
+    bad = rsft.design_thresholds((1024,), (64,), 50, 40, 0.9, 1e-6, (64.5,), eta_m=1.8)
+    assert bad["feasible"] == 0
+
+
 def test_struct_layouts_match_header(rsft, tmp_path):
     """The ctypes structures have the sizes and field offsets the C compiler
     gives the header's structs."""
@@ -150,6 +175,8 @@ def test_struct_layouts_match_header(rsft, tmp_path):
         "rsft_params": [f for f, _ in rsft.Params._fields_],
         "rsft_detection": [f for f, _ in rsft.Detection._fields_],
         "rsft_plan_info_t": [f for f, _ in rsft.PlanInfo._fields_],
+        "rsft_design_params": [f for f, _ in rsft.DesignParams._fields_],
+        "rsft_design_result": [f for f, _ in rsft.DesignResult._fields_],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rsft.h"', "int main(void) {"]
     for st, fs in fields.items():
@@ -163,7 +190,7 @@ def test_struct_layouts_match_header(rsft, tmp_path):
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     want = []
-    for cls in (rsft.Params, rsft.Detection, rsft.PlanInfo):
+    for cls in (rsft.Params, rsft.Detection, rsft.PlanInfo, rsft.DesignParams, rsft.DesignResult):
         want.append(ctypes.sizeof(cls))
         want.extend(getattr(cls, f).offset for f, _ in cls._fields_)
     assert got == want

@@ -78,3 +78,85 @@ def test_alpha_beta_closed_forms():
     a, bb = DS.alpha_beta_one_dim(n, b, 0.0, 0.0, 37.0)
     assert np.allclose(bb, n * (n // b), rtol=1e-12)
     assert np.allclose(a, float(n) ** 2, rtol=1e-12)
+
+
+def test_poisson_binomial_tail():
+    """Equal probabilities give the binomial tail; a mixed set matches brute
+    force over all 2^T outcomes."""
+    from scipy import stats
+    import itertools
+    assert abs(DS.poisson_binomial_tail([0.3] * 20, 7) - stats.binom.sf(6, 20, 0.3)) < 1e-14
+    probs = [0.1, 0.5, 0.9, 0.33, 0.2, 0.75]
+    brute = 0.0
+    for bits in itertools.product([0, 1], repeat=len(probs)):
+        if sum(bits) >= 3:
+            brute += np.prod([q if b else 1 - q for q, b in zip(probs, bits)])
+    assert abs(DS.poisson_binomial_tail(probs, 3) - brute) < 1e-14
+
+
+def test_stage1_detection_exponential_law():
+    """Noise-only buckets (alpha SNR = 0) are flagged with probability p1;
+    the tone's rate is the exponential survival exp(-gamma / mean)."""
+    import math
+    assert abs(DS.stage1_detection(3.0, 5.0, 0.0, 0.07) - 0.07) < 1e-15
+    beta, alpha, snr, p1 = 9.0, 0.4, 12.0, 0.05
+    gamma = beta * math.log(1 / p1)
+    assert abs(DS.stage1_detection(alpha, beta, snr, p1) - math.exp(-gamma / (alpha * snr + beta))) < 1e-15
+
+
+def _seg_plan(n, b, T, mu, p1, seed):
+    import synth
+    from oracle import rsft as R
+    sigma = synth.draw_sigma(np.random.default_rng(seed), T, (n,))
+    return R.OraclePlan((n,), (b,), sigma, 40.0, None, 1e-3, mu, 1.0, p1)
+
+
+def test_exact_cell_rates_noise_only_and_tone_cell():
+    """No tone: every cell has the binomial tail. One tone: its cell's rate
+    equals the Poisson-binomial of eq. tpd with alpha_s, beta_s of Claim 1's
+    bucket, computed through alpha_beta_one_dim."""
+    from scipy import stats
+    n, b, T, mu, p1 = 256, 16, 12, 4, 0.08
+    plan = _seg_plan(n, b, T, mu, p1, 4)
+    assert np.allclose(DS.exact_cell_rates(plan, [], p1), stats.binom.sf(mu - 1, T, p1), atol=1e-14)
+    fb, snr = 37.5, 0.6
+    rates = DS.exact_cell_rates(plan, [((fb,), snr)], p1)
+    a, bb = DS.alpha_beta_one_dim(n, b, 40.0, 40.0, fb)
+    probs = [DS.stage1_detection(a[(int(s) - 1) // 2], bb[(int(s) - 1) // 2], snr, p1)
+             for s in plan.sigma[:, 0]]
+    assert abs(rates[37] - DS.poisson_binomial_tail(probs, mu)) < 1e-12
+
+
+def test_exact_cell_rates_monte_carlo():
+    """The literal oracle in segment mode over 600 CPIs (Swerling-I tones in
+    noise): the detection rate of the tone cell and the false-alarm count
+    elsewhere agree with exact_cell_rates."""
+    import math
+    import synth
+    from oracle import rsft as R
+    n, b, T, mu, p1 = 256, 16, 10, 4, 0.08
+    plan = _seg_plan(n, b, T, mu, p1, 9)
+    tones = [((37.5,), 0.5), ((141.2,), 1.5)]
+    rates = DS.exact_cell_rates(plan, tones, p1)
+    rng = np.random.default_rng(33)
+    m = np.arange(n)
+    hits = 0
+    counts = np.zeros(n)
+    cpis = 600
+    for _ in range(cpis):
+        segs = []
+        for s in range(T):
+            x = synth.complex_noise(rng, (n,))
+            for fb, snr in tones:
+                x = x + synth.complex_noise(rng, (), snr) * np.exp(2j * np.pi * fb[0] * m / n)
+            segs.append(x)
+        det = R.rsft(np.stack(segs), plan, segments=True)["detections"]
+        counts[det] += 1
+    emp = counts / cpis
+    se = np.sqrt(rates * (1 - rates) / cpis)
+    assert abs(emp[37] - rates[37]) <= 3 * se[37] + 1e-12
+    far = np.ones(n, dtype=bool)
+    for c in (37, 141):
+        far[[(c + o) % n for o in range(-3, 4)]] = False
+    want = rates[far].sum() * cpis
+    assert abs(counts[far].sum() - want) <= 5 * math.sqrt(want) + 0.1 * want
