@@ -7,9 +7,9 @@
 //             |.|^2, first-stage NP threshold (eq. exp, eq. tpd) and flags
 //   vote      reverse mapping + accumulation + second stage (Def. 3-4,
 //             eq. a_i), enumerating only the preimages of flagged buckets
-//   scan      per-frame record offsets
-//   estimate  sort detections, gain-corrected magnitudes, peak test and
-//             log-parabolic off-grid offsets
+//   scan      per-frame detection counts and record offsets
+//   estimate  ordered compaction of the detections, gain-corrected
+//             magnitudes, peak test and log-parabolic off-grid offsets
 //
 // Why the fold reads the input in natural order: with tau = 0 the round-s
 // bucket before the DFT is f_s[b] = sum_{n = b mod B} wbar[n] y[[sigma n]_N].
@@ -288,9 +288,10 @@ int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
 // MFMA (v_mfma_f32_16x16x4_f32): for a dimension of length n, the lines
 // along it are the columns of an n x (B/n) matrix X and Y = D_n X with
 // D_n[k][b] = exp(-2 pi i ((k b) mod n) / n), the phase reduced exactly as
-// an integer before the table lookup. Each wave owns 16 lines at a time and
-// keeps all n outputs of its lines in registers until written back, so the
-// transform can be done in place. The epilogue reads the transform at the
+// an integer before the table lookup. The work is split into (16-line group,
+// 16-output tile) items over all waves; a round of items holds whole line
+// groups and is written back only after every item of the round is computed,
+// so the transform is done in place. The epilogue reads the transform at the
 // relabelled index (tau_s j mod B_d per dimension), writes the buckets in
 // the paper's indexing, and sets flag bits |fhat|^2 >= gamma_s with ballots.
 // ---------------------------------------------------------------------------
