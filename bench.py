@@ -40,7 +40,10 @@ HBM_PEAK_GBS = 8000.0
 CONFIG = 2
 FRAMES = 128
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "fold_c2_hbm_counters.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_01050_amd", "csrc", "kernels.hip")
+# the sources the fold kernel is built from: its counters stay valid while
+# these are unchanged
+FOLD_SOURCES = [os.path.join(ROOT, "paper_1610_01050_amd", "csrc", f)
+                for f in ("fold.hip", "device_common.h", "rsft_internal.h")]
 
 
 def log(*a):
@@ -48,8 +51,11 @@ def log(*a):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in FOLD_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def fold_kernel_key(rounds, fold_cfg):
@@ -329,7 +335,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=40)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-comparators", action="store_true")
     ap.add_argument("--skip-refine", action="store_true")

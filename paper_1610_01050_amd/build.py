@@ -6,7 +6,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["kernels.hip", "refine.hip", "plan.cpp", "design.cpp"]
+SOURCES = ["fold.hip", "dft.hip", "vote.hip", "estimate.hip", "refine.hip", "plan.cpp", "design.cpp"]
 OUTPUT = os.path.join(HERE, "librsft.so")
 
 FLAGS = [

@@ -1,0 +1,276 @@
+// dft stage of the RSFT hot path: B-point N-D DFT on MFMA, threshold, flags.
+
+#include "device_common.h"
+
+namespace rsft {
+
+// ---------------------------------------------------------------------------
+// dft: one work-group per (round, frame). The round's B partial buckets are
+// summed over column chunks into LDS (separate re / im planes), then the DFT
+// is applied along each dimension in place as complex matrix products on
+// MFMA (v_mfma_f32_16x16x4_f32): for a dimension of length n, the lines
+// along it are the columns of an n x (B/n) matrix X and Y = D_n X with
+// D_n[k][b] = exp(-2 pi i ((k b) mod n) / n), the phase reduced exactly as
+// an integer before the table lookup. The work is split into (16-line group,
+// 16-output tile) items over all waves; a round of items holds whole line
+// groups and is written back only after every item of the round is computed,
+// so the transform is done in place. The epilogue reads the transform at the
+// relabelled index (tau_s j mod B_d per dimension), writes the buckets in
+// the paper's indexing, and sets flag bits |fhat|^2 >= gamma_s with ballots.
+// ---------------------------------------------------------------------------
+
+constexpr int kDftThreads = 1024;
+constexpr int kDftWaves = kDftThreads / 64;
+constexpr int kDftItems = 4;   // output tiles per wave between barriers
+
+// LDS position of bucket index idx: one pad float after every row of the
+// last dimension (row length 2^nl_shift), so that 16 lines read at the same
+// position along that dimension fall into different banks.
+__device__ __forceinline__ int lds_at(int idx, int nl_shift) { return idx + (idx >> nl_shift); }
+
+// One 16-line x 16-output tile of Y = D_n X along a dimension: lines
+// grp*16 .. grp*16+15, outputs k = kt*16 .. kt*16+15.
+__device__ __forceinline__ void dft_tile(const float* __restrict__ re, const float* __restrict__ im,
+                                         const float2* __restrict__ tw, int n, int inner_shift,
+                                         int nlines, int nl_shift, int grp, int kt, floatx4& accR,
+                                         floatx4& accI) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15;
+  const int krow = lane >> 4;
+  const int line = grp * 16 + col;
+  const bool lvalid = line < nlines;
+  const int inner = 1 << inner_shift;
+  const int base = (line >> inner_shift) * n * inner + (line & (inner - 1));
+  const int k = kt * 16 + col;
+  accR = floatx4{0.f, 0.f, 0.f, 0.f};
+  accI = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int b0 = 0; b0 < n; b0 += 4) {
+    const int b = b0 + krow;
+    float xr = 0.f, xi = 0.f, dr = 0.f, di = 0.f;
+    if (lvalid && b < n) {
+      const int at = lds_at(base + b * inner, nl_shift);
+      xr = re[at];
+      xi = im[at];
+    }
+    if (k < n && b < n) {
+      const float2 t = tw[(k * b) & (n - 1)];
+      dr = t.x;
+      di = t.y;
+    }
+    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xr, accR, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-di, xi, accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xi, accI, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(di, xr, accI, 0, 0, 0);
+  }
+}
+
+// The DFT along one dimension of length n for all B / n lines, in place.
+// Work items are (line group, output tile) pairs in group-major order; a
+// round of kDftWaves * R items holds whole groups (the tiles per group,
+// ceil(n/16) <= 8, divide 16), every item of a round is computed before any
+// of its outputs is written, and rounds touch disjoint lines.
+__device__ __forceinline__ void mode_product(float* __restrict__ re, float* __restrict__ im,
+                                             const float2* __restrict__ tw, int n, int inner_shift,
+                                             int nlines, int nl_shift) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;
+  const int krow = lane >> 4;
+  const int nkt = (n + 15) >> 4;
+  const int items = ((nlines + 15) >> 4) * nkt;
+  const int per_wave = (items + kDftWaves - 1) / kDftWaves;
+  const int R = per_wave < kDftItems ? per_wave : kDftItems;
+  const int inner = 1 << inner_shift;
+  for (int r0 = 0; r0 < items; r0 += R * kDftWaves) {
+    floatx4 accR[kDftItems], accI[kDftItems];
+#pragma unroll
+    for (int q = 0; q < kDftItems; ++q) {
+      const int item = r0 + q * kDftWaves + wave;
+      if (q < R && item < items)
+        dft_tile(re, im, tw, n, inner_shift, nlines, nl_shift, item / nkt, item % nkt, accR[q], accI[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kDftItems; ++q) {
+      const int item = r0 + q * kDftWaves + wave;
+      if (q < R && item < items) {
+        const int grp = item / nkt;
+        const int kt = item % nkt;
+        const int line = grp * 16 + col;
+        if (line < nlines) {
+          const int base = (line >> inner_shift) * n * inner + (line & (inner - 1));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = kt * 16 + krow * 4 + r;
+            if (k < n) {
+              const int at = lds_at(base + k * inner, nl_shift);
+              re[at] = accR[q][r];
+              im[at] = accI[q][r];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int plane, int pad,
+                                                          int frame0, int identity,
+                                                          int nchunks_override) {
+  extern __shared__ float smem[];
+  float* re = smem;
+  float* im = smem + plane;
+  float2* tws = reinterpret_cast<float2*>(smem + 2 * plane);
+  __shared__ uint32_t sel_prefix, sel_rank;
+  __shared__ uint32_t hist[256];
+
+  const int s = blockIdx.x;
+  const int64_t f = frame0 + int64_t(blockIdx.y);
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  const int B = d.B;
+  // log2 of the last dimension's B (pads on), or no pads
+  const int nls = pad ? __builtin_ctz(uint32_t(d.b_last)) : 31;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+
+
+  // twiddles of each dimension, concatenated
+  int twoff[kMaxDims];
+  {
+    int acc = 0;
+    for (int dd = 0; dd < d.ndim; ++dd) {
+      twoff[dd] = acc;
+      for (int m = tid; m < d.b[dd]; m += kDftThreads) tws[acc + m] = p.tw[d.tw_off[dd] + m];
+      acc += d.b[dd];
+    }
+  }
+  // sum the column-chunk partials of this round
+  const int nch = nchunks_override > 0 ? nchunks_override : d.nchunks;
+  const float2* part = p.part + d.part_off + rel * d.part_stride;
+  for (int idx = tid; idx < B; idx += kDftThreads) {
+    float sr = 0.f, si = 0.f;
+    for (int c = 0; c < nch; ++c) {
+      const float2 v = part[(int64_t(c) * T + s) * B + idx];
+      sr += v.x;
+      si += v.y;
+    }
+    re[lds_at(idx, nls)] = sr;
+    im[lds_at(idx, nls)] = si;
+  }
+  __syncthreads();
+
+  for (int dd = 0; dd < d.ndim; ++dd) {
+    const int n = d.b[dd];
+    mode_product(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
+  }
+
+  float2* bout = p.buckets + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
+  uint32_t* fout = p.flags + d.flag_off + rel * d.flag_stride + int64_t(s) * d.words;
+
+  auto relabel = [&](int j) {
+    int kf = 0;
+    for (int dd = 0; dd < d.ndim; ++dd) {
+      const int jd = (j >> d.bshift[dd]) & (d.b[dd] - 1);
+      const int kd = identity ? jd : ((d.tau[s][dd] * jd) & (d.b[dd] - 1));
+      kf |= kd << d.bshift[dd];
+    }
+    return kf;
+  };
+
+  double gamma = d.gamma[s];
+  if (d.noise_mode == RSFT_NOISE_ESTIMATED) {
+    // pass 1: buckets out, powers into the re plane (relabel is a bijection)
+    for (int j = tid; j < B; j += kDftThreads) {
+      const int kf = lds_at(relabel(j), nls);
+      const float xr = re[kf], xi = im[kf];
+      bout[j] = make_float2(xr, xi);
+      re[kf] = xr * xr + xi * xi;
+    }
+    __syncthreads();
+    // lower median X_(h), h = B/2, by 4 passes of 8-bit radix selection
+    // (non-negative floats order like their bit patterns)
+    uint32_t prefix = 0u, pmask = 0u, rank = uint32_t(B / 2 > 0 ? B / 2 : 1);
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      for (int q = tid; q < 256; q += kDftThreads) hist[q] = 0u;
+      __syncthreads();
+      for (int idx = tid; idx < B; idx += kDftThreads) {
+        const uint32_t u = __float_as_uint(re[lds_at(idx, nls)]);
+        if ((u & pmask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t cum = 0u;
+        for (uint32_t dg = 0; dg < 256u; ++dg) {
+          if (cum + hist[dg] >= rank) {
+            sel_prefix = prefix | (dg << shift);
+            sel_rank = rank - cum;
+            break;
+          }
+          cum += hist[dg];
+        }
+      }
+      __syncthreads();
+      prefix = sel_prefix;
+      rank = sel_rank;
+      pmask |= 255u << shift;
+      __syncthreads();
+    }
+    const double xh = double(__uint_as_float(prefix));
+    gamma = xh / d.renyi_h * d.log_inv_p1;
+    for (int j0 = wave * 64; j0 < B; j0 += kDftThreads) {
+      const int j = j0 + lane;
+      bool flag = false;
+      if (j < B) flag = double(re[lds_at(relabel(j), nls)]) >= gamma;
+      const unsigned long long m = __ballot(flag);
+      if (lane == 0) {
+        const int w = j0 >> 5;
+        fout[w] = uint32_t(m & 0xffffffffull);
+        if (w + 1 < d.words) fout[w + 1] = uint32_t(m >> 32);
+      }
+    }
+  } else {
+    for (int j0 = wave * 64; j0 < B; j0 += kDftThreads) {
+      const int j = j0 + lane;
+      bool flag = false;
+      if (j < B) {
+        const int kf = lds_at(relabel(j), nls);
+        const float xr = re[kf], xi = im[kf];
+        bout[j] = make_float2(xr, xi);
+        flag = double(xr * xr + xi * xi) >= gamma;
+      }
+      const unsigned long long m = __ballot(flag);
+      if (lane == 0) {
+        const int w = j0 >> 5;
+        fout[w] = uint32_t(m & 0xffffffffull);
+        if (w + 1 < d.words) fout[w + 1] = uint32_t(m >> 32);
+      }
+    }
+  }
+}
+
+int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw, int identity,
+               int nchunks_override, void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  const size_t shmem = size_t(2 * plane) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
+  hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), unsigned(nframes)), dim3(kDftThreads), shmem,
+                     static_cast<hipStream_t>(stream), p, T, plane, pad, 0, identity, nchunks_override);
+  return hipGetLastError();
+}
+
+static int launch_dft_frame(const DevPtrs& p, int64_t frame, int T, int plane, int pad, int sum_tw,
+                            hipStream_t st) {
+  const size_t shmem = size_t(2 * plane) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
+  hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), 1u), dim3(kDftThreads), shmem, st, p, T, plane,
+                     pad, int(frame), 1, 1);
+  return hipGetLastError();
+}
+
+int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int plane, int pad, int sum_tw,
+                     void* stream) {
+  return launch_dft_frame(p, frame, T, plane, pad, sum_tw, static_cast<hipStream_t>(stream));
+}
+
+}  // namespace rsft

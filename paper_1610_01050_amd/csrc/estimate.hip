@@ -1,0 +1,444 @@
+// compact + estimate stage of the RSFT hot path.
+
+#include "device_common.h"
+
+namespace rsft {
+
+// ---------------------------------------------------------------------------
+// compact + estimate: one work-group per (frame, compaction chunk of 2^15
+// cells). It reads the chunk's bitmap words in row-major order, lists the
+// detected cells in LDS (popcount + block prefix sum) and gives each cell its
+// rank in the frame's record range; then every listed cell gets its record:
+// votes recounted from the flags, gain-corrected magnitude (median over the
+// estimation rounds of |fhat_s[M(i, sigma_s)]| times the inverse flat-window
+// response at the cell's offset inside its bucket), a peak test against the
+// 3^D - 1 circular neighbours (strictly above lower-index neighbours, at
+// least equal to higher-index ones) and per dimension the vertex of a
+// parabola through the log magnitudes at offsets -1, 0, +1, clamped to
+// [-1/2, 1/2]. Ranks beyond the frame's capacity are dropped.
+//
+// Magnitudes are handled squared: the median, the peak comparisons and the
+// vertex (a ratio of differences of logarithms) are unchanged by squaring,
+// except the mean of the two middle values for an even number of rounds,
+// which is taken on the square roots. FP32 magnitudes, FP64 vertex and
+// frequency.
+//
+// With at least 16 frames, block b serves frames congruent to b mod 8: work-
+// groups are dealt to the eight XCDs round-robin, so each XCD's L2 holds the
+// buckets and flags of only its own frames.
+// ---------------------------------------------------------------------------
+
+constexpr int kEstThreads = 256;
+constexpr int kListMax = 2048;   // cells listed at once: a chunk's, else one pass's
+
+// Per-frame constants of the estimate, uniform across the work-group.
+template <int D, int M>
+struct EstFrame {
+  uint32_t nm[D], lm[D], ls[D], bs[D], ns[D];
+  const float* ig[D];              // inverse flat-window gains per dimension
+  uint32_t sig_est[M][D];
+  const float2* bk_est[M];
+  const uint32_t* fl;              // flags [T][words]
+  const int32_t* sig;              // sigma [kMaxRounds][kMaxDims] of the descriptor
+  int words;
+};
+
+template <int D, int M>
+__device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d, int64_t rel,
+                                           EstFrame<D, M>& e) {
+  const float2* bk = p.buckets + d.bucket_off + rel * d.bucket_stride;
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    e.nm[dd] = uint32_t(d.n[dd] - 1);
+    e.lm[dd] = uint32_t(d.l[dd] - 1);
+    e.ls[dd] = uint32_t(d.lshift[dd]);
+    e.bs[dd] = uint32_t(d.bshift[dd]);
+    e.ns[dd] = uint32_t(d.nshift[dd]);
+    e.ig[dd] = p.inv_gains + d.gain_off[dd];
+  }
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const int s = d.est_rounds[q];
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) e.sig_est[q][dd] = uint32_t(d.sigma[s][dd]);
+    e.bk_est[q] = bk + int64_t(s) * d.B;
+  }
+  e.fl = p.flags + d.flag_off + rel * d.flag_stride;
+  e.sig = &d.sigma[0][0];
+  e.words = d.words;
+}
+
+// Median of M values (an odd-even transposition network on fixed indices);
+// for even M the mean of the middle two is taken on their square roots (the
+// values are squared magnitudes).
+template <int M>
+__device__ __forceinline__ float median_of(float (&v)[M]) {
+#pragma unroll
+  for (int pass = 0; pass < M; ++pass) {
+#pragma unroll
+    for (int q = pass & 1; q + 1 < M; q += 2) {
+      const float lo = fminf(v[q], v[q + 1]);
+      const float hi = fmaxf(v[q], v[q + 1]);
+      v[q] = lo;
+      v[q + 1] = hi;
+    }
+  }
+  if constexpr (M & 1) {
+    return v[M / 2];
+  } else {
+    const float a = 0.5f * (sqrtf(v[M / 2 - 1]) + sqrtf(v[M / 2]));
+    return a * a;
+  }
+}
+
+// Vertex of the parabola through (-1, log am), (0, log a0), (1, log ap) from
+// the squared magnitudes (the factor 2 of the logarithms cancels), clamped to
+// [-1/2, 1/2]; 0 when the points are not concave. Base-2 logarithms of the
+// FP32 powers, vertex in FP64.
+__device__ __forceinline__ double log_parabola_offset(float pm, float p0, float pp) {
+  const float tiny = 1e-37f;
+  const double lm = double(__builtin_amdgcn_logf(pm > tiny ? pm : tiny));
+  const double l0 = double(__builtin_amdgcn_logf(p0 > tiny ? p0 : tiny));
+  const double lp = double(__builtin_amdgcn_logf(pp > tiny ? pp : tiny));
+  const double den = 2.0 * l0 - lm - lp;
+  if (!(den > 0.0)) return 0.0;
+  double v = 0.5 * (lp - lm) / den;
+  v = v < -0.5 ? -0.5 : v;
+  v = v > 0.5 ? 0.5 : v;
+  return v;
+}
+
+// Squared gain-corrected magnitude of neighbour `code` (digit d of code in
+// base 3 is o_d + 1): the median over the estimation rounds, from the
+// per-round squared inverse gains g and bucket offsets jb of the offsets.
+template <int D, int M>
+__device__ __forceinline__ float neighbour_power(const EstFrame<D, M>& e, const float (&g)[M][D][3],
+                                                 const uint32_t (&jb)[M][D][3], int code) {
+  float v[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    uint32_t jf = 0u;
+    float gg = 1.f;
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3;
+      c /= 3;
+      jf |= jb[q][dd][o];
+      gg *= g[q][dd][o];
+    }
+    const float2 b = e.bk_est[q][jf];
+    v[q] = (b.x * b.x + b.y * b.y) * gg;
+  }
+  return median_of<M>(v);
+}
+
+// The same for D >= 3, from the permuted index u0[q][d] = [sigma c]_N of the
+// cell itself (no array indexed at run time).
+template <int D, int M>
+__device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, const uint32_t (&u0)[M][D],
+                                                     int code) {
+  float v[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    uint32_t jf = 0u;
+    float gg = 1.f;
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      const uint32_t u = (u0[q][dd] + e.sig_est[q][dd] * uint32_t(o)) & e.nm[dd];
+      const float ig = e.ig[dd][u & e.lm[dd]];
+      gg *= ig * ig;
+      jf |= (u >> e.ls[dd]) << e.bs[dd];
+    }
+    const float2 b = e.bk_est[q][jf];
+    v[q] = (b.x * b.x + b.y * b.y) * gg;
+  }
+  return median_of<M>(v);
+}
+
+// One record. D <= 2: the 3^D neighbourhood lives in registers (loops
+// unrolled); D >= 3: its 27 or 81 values are kept in this thread's LDS
+// column `pcol` (stride kEstThreads) and visited by ordinary loops.
+template <int D, int M>
+__device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int64_t f,
+                                             unsigned long long flat, rsft_detection* out,
+                                             float* pcol) {
+  constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
+  constexpr bool kRegs = D <= 2;
+  constexpr int kCentre = (kNb - 1) / 2;
+  uint32_t cell[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) cell[dd] = uint32_t(flat >> e.ns[dd]) & e.nm[dd];
+  int votes = 0;
+  for (int s = 0; s < T; ++s) {
+    uint32_t jf = 0u;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) {
+      const uint32_t u = (uint32_t(e.sig[s * kMaxDims + dd]) * cell[dd]) & e.nm[dd];
+      jf |= (u >> e.ls[dd]) << e.bs[dd];
+    }
+    votes += int((e.fl[int64_t(s) * e.words + (jf >> 5)] >> (jf & 31u)) & 1u);
+  }
+  float preg[kRegs ? kNb : 1];
+  if constexpr (kRegs) {
+    // Per round and dimension the three offsets o_d = -1, 0, 1 share one
+    // permuted index, [sigma (c + o)]_N = [sigma c + sigma o]_N, so their
+    // squared inverse gains and bucket offsets are formed once.
+    float g[M][D][3];
+    uint32_t jb[M][D][3];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd) {
+        const uint32_t sg = e.sig_est[q][dd];
+        const uint32_t u0 = sg * cell[dd];
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          const uint32_t u = (u0 + sg * uint32_t(o - 1)) & e.nm[dd];
+          const float ig = e.ig[dd][u & e.lm[dd]];
+          g[q][dd][o] = ig * ig;
+          jb[q][dd][o] = (u >> e.ls[dd]) << e.bs[dd];
+        }
+      }
+    }
+#pragma unroll
+    for (int code = 0; code < kNb; ++code) preg[code] = neighbour_power<D, M>(e, g, jb, code);
+  } else {
+    uint32_t u0[M][D];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd) u0[q][dd] = e.sig_est[q][dd] * cell[dd];
+    }
+#pragma unroll 1
+    for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_dyn<D, M>(e, u0, code);
+  }
+  auto P = [&](int code) -> float {
+    if constexpr (kRegs) return preg[code];
+    else return pcol[code * kEstThreads];
+  };
+  const float p0 = P(kCentre);
+  bool peak = true;
+  auto visit = [&](int code) {
+    if (code == kCentre) return;
+    unsigned long long nflat = 0ull;
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      const uint32_t nb = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
+      nflat |= (unsigned long long)nb << e.ns[dd];
+    }
+    if (nflat == flat) return;       // a dimension of length <= 2 wraps onto the cell
+    const float pc = P(code);
+    if (nflat < flat) {
+      if (!(p0 > pc)) peak = false;
+    } else {
+      if (!(p0 >= pc)) peak = false;
+    }
+  };
+  if constexpr (kRegs) {
+#pragma unroll
+    for (int code = 0; code < kNb; ++code) visit(code);
+  } else {
+#pragma unroll 1
+    for (int code = 0; code < kNb; ++code) visit(code);
+  }
+  rsft_detection rec;
+  rec.frame = f;
+#pragma unroll
+  for (int dd = 0; dd < kMaxDims; ++dd) {
+    rec.idx[dd] = 0;
+    rec.freq[dd] = 0.0;
+  }
+  int stride = 1;
+#pragma unroll
+  for (int dd = D - 1; dd >= 0; --dd) {
+    const double delta = log_parabola_offset(P(kCentre - stride), p0, P(kCentre + stride));
+    double fr = (double(cell[dd]) + delta) / double(e.nm[dd] + 1u);
+    if (fr < 0.0) fr += 1.0;
+    if (fr >= 1.0) fr -= 1.0;
+    rec.idx[dd] = cell[dd];
+    rec.freq[dd] = fr;
+    stride *= 3;
+  }
+  rec.votes = votes;
+  rec.is_peak = peak ? 1 : 0;
+  rec.magnitude = sqrtf(p0);
+  rec.reserved = 0.f;
+  *out = rec;
+}
+
+// Records of list[0 .. min(n, room)) in batches of kEstThreads: each thread
+// builds one record in LDS, then the work-group copies the batch out with
+// contiguous 8-byte stores (a record is 88 bytes, 8-byte aligned).
+template <int D, int M>
+__device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc& d, int64_t f,
+                                              int64_t rel, int T, const uint32_t* list, int n,
+                                              unsigned long long cell0, rsft_detection* out,
+                                              int64_t room, float* pcol, rsft_detection* stage) {
+  EstFrame<D, M> e;
+  load_frame<D, M>(p, d, rel, e);
+  const int lim = int(n < room ? n : room);
+  constexpr int kWords = int(sizeof(rsft_detection) / 8);
+  for (int q0 = 0; q0 < lim; q0 += kEstThreads) {
+    const int q = q0 + int(threadIdx.x);
+    if (q < lim) write_record<D, M>(e, T, f, cell0 | (unsigned long long)list[q], stage + threadIdx.x, pcol);
+    __syncthreads();
+    const int nw = (lim - q0 < kEstThreads ? lim - q0 : kEstThreads) * kWords;
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(stage);
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(out + q0);
+    for (int w = int(threadIdx.x); w < nw; w += kEstThreads) dst[w] = src[w];
+    __syncthreads();
+  }
+}
+
+template <int D, int M>
+__global__ __launch_bounds__(kEstThreads) void compact_estimate_kernel(DevPtrs p, int T,
+                                                                       int64_t nframes,
+                                                                       int max_cchunks,
+                                                                       int xcd_groups) {
+  constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
+  __shared__ uint32_t list[kListMax];
+  __shared__ uint32_t wsum[kEstThreads / 64];
+  __shared__ rsft_detection stage[kEstThreads];
+  __shared__ float pbuf[D >= 3 ? kNb * kEstThreads : 1];
+  int64_t f;
+  int c;
+  const int64_t b = blockIdx.x;
+  if (xcd_groups) {
+    const int64_t k = b >> 3;
+    f = (k / max_cchunks) * 8 + (b & 7);
+    c = int(k % max_cchunks);
+  } else {
+    f = b / max_cchunks;
+    c = int(b % max_cchunks);
+  }
+  if (f >= nframes) return;
+  const FrameDesc& d = desc_of(p, f);
+  if (c >= d.cchunks || d.ndim != D || d.n_est != M) return;
+  const int64_t rel = rel_of(p, f);
+  const int64_t ck = d.chunk_off + rel * d.chunk_stride + c;
+  if (p.chunk_counts[ck] == 0u) return;
+  const int64_t rank0 = p.chunk_offsets[ck];
+  const int64_t cap = d.cap;
+  if (rank0 >= cap) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  rsft_detection* out = p.records + p.offsets[f] + rank0;
+  const uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride;
+  const int w0 = c << (kCompactShift - 5);
+  const int wend = min(d.bitmap_words, w0 + (1 << (kCompactShift - 5)));
+  const unsigned long long cell0 = (unsigned long long)c << kCompactShift;
+  const int64_t room0 = cap - rank0;
+  float* pcol = pbuf + threadIdx.x;
+  const uint32_t chunk_count = p.chunk_counts[ck];
+  if (chunk_count <= uint32_t(kListMax)) {
+    // one pass: thread t lists the set bits of words w0 + 4t .. w0 + 4t + 3
+    constexpr int kWpt = (1 << (kCompactShift - 5)) / kEstThreads;
+    uint32_t wv[kWpt];
+    int pc = 0;
+#pragma unroll
+    for (int q = 0; q < kWpt; ++q) {
+      const int w = w0 + tid * kWpt + q;
+      wv[q] = w < wend ? bm[w] : 0u;
+      pc += __popc(wv[q]);
+    }
+    int incl = pc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = uint32_t(incl);
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < kEstThreads / 64; ++q) {
+      if (q < wave) base += int(wsum[q]);
+      total += int(wsum[q]);
+    }
+    int k = base + incl - pc;
+#pragma unroll
+    for (int q = 0; q < kWpt; ++q) {
+      uint32_t word = wv[q];
+      const uint32_t wrel = uint32_t(tid * kWpt + q) << 5;
+      while (word) {
+        const int bit = __ffs(word) - 1;
+        word &= word - 1u;
+        if (k < kListMax) list[k] = wrel | uint32_t(bit);
+        ++k;
+      }
+    }
+    __syncthreads();
+    estimate_list<D, M>(p, d, f, rel, T, list, min(total, kListMax), cell0, out, room0, pcol, stage);
+    return;
+  }
+  // dense chunk: passes of kListMax / 32 words (at most kListMax cells each)
+  constexpr int kPassWords = kListMax / 32;
+  int64_t running = 0;
+  for (int wb = w0; wb < wend; wb += kPassWords) {
+    const int w = wb + tid;
+    uint32_t word = (tid < kPassWords && w < wend) ? bm[w] : 0u;
+    const int pc = __popc(word);
+    int incl = pc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = uint32_t(incl);
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < kEstThreads / 64; ++q) {
+      if (q < wave) base += int(wsum[q]);
+      total += int(wsum[q]);
+    }
+    int k = base + incl - pc;
+    while (word) {
+      const int bit = __ffs(word) - 1;
+      word &= word - 1u;
+      list[k++] = (uint32_t(w - w0) << 5) | uint32_t(bit);
+    }
+    __syncthreads();
+    estimate_list<D, M>(p, d, f, rel, T, list, total, cell0, out + running, room0 - running, pcol,
+                        stage);
+    running += total;
+    if (running >= room0) return;   // uniform: the frame's capacity is used up
+    __syncthreads();
+  }
+}
+
+template <int D>
+static void launch_estimate_d(const DevPtrs& p, dim3 grid, hipStream_t st, int T, int64_t nframes,
+                              int max_cchunks, int xcd, int est_mask) {
+  if (est_mask & 2) hipLaunchKernelGGL((compact_estimate_kernel<D, 1>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask & 4) hipLaunchKernelGGL((compact_estimate_kernel<D, 2>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask & 8) hipLaunchKernelGGL((compact_estimate_kernel<D, 3>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask & 16) hipLaunchKernelGGL((compact_estimate_kernel<D, 4>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask & 32) hipLaunchKernelGGL((compact_estimate_kernel<D, 5>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+}
+
+int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
+                    int est_mask, void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int xcd = nframes >= 16 ? 1 : 0;
+  const int64_t rows = xcd ? ((nframes + 7) / 8) * 8 : nframes;
+  const int64_t blocks = rows * int64_t(max_cchunks);
+  if (blocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+  const dim3 grid{unsigned(blocks), 1u, 1u};
+  if (dims_mask & 1) launch_estimate_d<1>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 2) launch_estimate_d<2>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 4) launch_estimate_d<3>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 8) launch_estimate_d<4>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
+  return hipGetLastError();
+}
+
+}  // namespace rsft

@@ -99,7 +99,7 @@ struct FoldConfig {
 };
 constexpr int kFoldMaxP = 2048;   // largest threads * vec a plan may be tuned to
 
-// Launchers (kernels.hip). All enqueue on `stream` and return hipError_t.
+// Launchers (fold.hip, dft.hip, vote.hip, estimate.hip). All enqueue on `stream` and return hipError_t.
 int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
                 int64_t tiles_per_frame, int64_t ntiles, int round0, int rounds,
                 int T, const FoldConfig& cfg, void* stream);

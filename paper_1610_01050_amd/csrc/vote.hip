@@ -1,0 +1,347 @@
+// vote and scan stages of the RSFT hot path.
+
+#include "device_common.h"
+
+namespace rsft {
+
+// ---------------------------------------------------------------------------
+// vote: abar_i = sum_s c_s[M(i, sigma_s)] with M_d(i) = [sigma_{s,d} i_d] >>
+// log2 L_d (Def. 3), which by Properties 3-4 equals the accumulation of the
+// reverse-mapped flags (Def. 4, eq. a_i); detection iff abar_i >= mu.
+// One work-group per compaction chunk of 2^15 cells; each chunk's bitmap
+// words are written completely and its detection count stored, so no atomics
+// touch global memory. Index products are taken modulo 2^32 and masked,
+// which equals the product modulo N_d (a power of two).
+//
+// vote_rows_kernel (rows of 64..4096 cells, T <= 4): a cell with >= mu votes
+// is flagged in one of the rounds 0..T-mu, so each wave takes one row at a
+// time and visits only the preimages of that row's flagged buckets (Def. 4):
+// within a row the leading indices fix the leading bucket indices, so the
+// candidates are i_last = [sigma_inv u]_N for u in [j L, (j + 1) L) over the
+// flagged j of the row's bucket row. Work is proportional to the flagged
+// buckets times L, the reverse-mapping cost of the paper's complexity table,
+// instead of N T. A cell reached from round s0 is skipped when an earlier
+// candidate round flags it (each cell is counted once). Hits go to a
+// wave-private row bitmap in LDS, written out once per row.
+//
+// vote_kernel (any shape): the dense gather, every cell evaluated.
+// ---------------------------------------------------------------------------
+
+constexpr int kVoteThreads = 256;
+constexpr int kRowWordsMax = 128;   // rows of up to 4096 cells
+
+template <int D>
+__global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, int mu, int frame0) {
+  extern __shared__ uint32_t sflags[];
+  __shared__ uint32_t wcount[kVoteThreads / 64];
+  __shared__ uint32_t ssig[kMaxRounds * kMaxDims];
+  const int c = blockIdx.x;
+  const int64_t f = frame0 + int64_t(blockIdx.y);
+  const FrameDesc& d = desc_of(p, f);
+  if (c >= d.cchunks || d.ndim != D) return;
+  const int64_t rel = rel_of(p, f);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int words = d.words;
+  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
+  for (int w = tid; w < T * words; w += kVoteThreads) sflags[w] = fl[w];
+  if (tid < T * D) ssig[tid] = uint32_t(d.sigma[tid / D][tid % D]);
+  uint32_t nm[D], ls[D], bs[D], ns[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    nm[dd] = uint32_t(d.n[dd] - 1);
+    ls[dd] = uint32_t(d.lshift[dd]);
+    bs[dd] = uint32_t(d.bshift[dd]);
+    ns[dd] = uint32_t(d.nshift[dd]);
+  }
+  const int64_t cell0 = int64_t(c) << kCompactShift;
+  const int64_t rem = d.N - cell0;
+  const int ncell = int(rem < (int64_t(1) << kCompactShift) ? rem : (int64_t(1) << kCompactShift));
+  uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride + (cell0 >> 5);
+  __syncthreads();
+
+  uint32_t cnt = 0u;
+  for (int base = wave * 64; base < ncell; base += kVoteThreads) {
+    const int64_t i = cell0 + base + lane;
+    bool hit = false;
+    if (base + lane < ncell) {
+      int votes = 0;
+      for (int s = 0; s < T; ++s) {
+        uint32_t jf = 0u;
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+          const uint32_t cd = uint32_t(i >> ns[dd]) & nm[dd];
+          jf |= (((ssig[s * D + dd] * cd) & nm[dd]) >> ls[dd]) << bs[dd];
+        }
+        votes += int((sflags[s * words + (jf >> 5)] >> (jf & 31u)) & 1u);
+      }
+      hit = votes >= mu;
+    }
+    const unsigned long long m = __ballot(hit);
+    if (lane == 0) {
+      bm[base >> 5] = uint32_t(m & 0xffffffffull);
+      if (base + 32 < ncell) bm[(base >> 5) + 1] = uint32_t(m >> 32);
+      cnt += uint32_t(__popcll(m));
+    }
+  }
+  if (lane == 0) wcount[wave] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t total = 0u;
+    for (int w = 0; w < kVoteThreads / 64; ++w) total += wcount[w];
+    p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = total;
+  }
+}
+
+// bit j (< 128) of a 128-bit row held as four words
+__device__ __forceinline__ uint32_t row_bit(const uint32_t* w, uint32_t j) {
+  return __builtin_amdgcn_ubfe(w[j >> 5], j & 31u, 1u);
+}
+
+template <int D, int TT>
+__global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int mu, int frame0) {
+  extern __shared__ uint32_t sflags[];
+  __shared__ uint32_t wcount[kVoteThreads / 64];
+  __shared__ uint32_t rowbm[kVoteThreads / 64][kRowWordsMax];
+  __shared__ uint32_t blist[kVoteThreads / 64][128];
+  __shared__ uint32_t rowflags[kVoteThreads / 64][TT * 4];
+  const int c = blockIdx.x;
+  const int64_t f = frame0 + int64_t(blockIdx.y);
+  const FrameDesc& d = desc_of(p, f);
+  if (c >= d.cchunks || d.ndim != D) return;
+  const int64_t rel = rel_of(p, f);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int words = d.words;
+  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
+  for (int w = tid; w < TT * words; w += kVoteThreads) sflags[w] = fl[w];
+  uint32_t nm[D], ls[D], bs[D], ns[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    nm[dd] = uint32_t(d.n[dd] - 1);
+    ls[dd] = uint32_t(d.lshift[dd]);
+    bs[dd] = uint32_t(d.bshift[dd]);
+    ns[dd] = uint32_t(d.nshift[dd]);
+  }
+  uint32_t sig[TT][D], sinv_last[TT];
+#pragma unroll
+  for (int s = 0; s < TT; ++s) {
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) sig[s][dd] = uint32_t(d.sigma[s][dd]);
+    sinv_last[s] = uint32_t(d.sigma_inv[s][D - 1]);
+  }
+  const uint32_t nl = nm[D - 1] + 1u;
+  const uint32_t lsl = ls[D - 1];
+  const uint32_t bl = uint32_t(d.b_last);
+  const int row_words = int(nl >> 5);
+  const int64_t cell0 = int64_t(c) << kCompactShift;
+  const int64_t rem = d.N - cell0;
+  const int ncell = int(rem < (int64_t(1) << kCompactShift) ? rem : (int64_t(1) << kCompactShift));
+  const int nrows = ncell / int(nl);
+  uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride + (cell0 >> 5);
+  uint32_t* rb = rowbm[wave];
+  uint32_t* lst = blist[wave];
+  uint32_t* R = rowflags[wave];
+  __syncthreads();
+
+  uint32_t cnt = 0u;
+  for (int r = wave; r < nrows; r += kVoteThreads / 64) {
+    const int64_t iw = cell0 + int64_t(r) * nl;               // first cell of the row
+    // the row's flags in every round: a 128-bit window at the row's bucket
+    // row, kept in wave-private LDS (lane 4s + q fills word q of round s)
+    if (lane < TT * 4) {
+      const int s = lane >> 2;
+      const int q = lane & 3;
+      uint32_t rowpart = 0u;
+#pragma unroll
+      for (int ss = 0; ss < TT; ++ss) {   // uniform per round, then picked per lane
+        uint32_t rp = 0u;
+#pragma unroll
+        for (int dd = 0; dd < D - 1; ++dd) {
+          const uint32_t cd = uint32_t(iw >> ns[dd]) & nm[dd];
+          rp |= (((sig[ss][dd] * cd) & nm[dd]) >> ls[dd]) << bs[dd];
+        }
+        if (ss == s) rowpart = rp;
+      }
+      const int wi = s * words + int(rowpart >> 5);
+      uint32_t v = 0u;
+      if (q == 0) {
+        v = sflags[wi] >> (rowpart & 31u);                     // offset only when B_last < 32
+        if (bl < 32u) v &= (1u << bl) - 1u;
+      } else if (uint32_t(q) * 32u < bl) {
+        v = sflags[wi + q];
+      }
+      R[lane] = v;
+    }
+    for (int q = lane; q < row_words; q += 64) rb[q] = 0u;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int s0 = 0; s0 < TT; ++s0) {
+      if (s0 > TT - mu) continue;
+      // ordered list of the flagged bucket positions of the row in round s0
+      const bool b0 = uint32_t(lane) < bl && row_bit(R + s0 * 4, uint32_t(lane)) != 0u;
+      const bool b1 = bl > 64u && row_bit(R + s0 * 4, uint32_t(lane) + 64u) != 0u;
+      const unsigned long long m0 = __ballot(b0);
+      const unsigned long long m1 = __ballot(b1);
+      const unsigned long long below = (1ull << lane) - 1ull;
+      const int k0 = __popcll(m0);
+      if (b0) lst[__popcll(m0 & below)] = uint32_t(lane);
+      if (b1) lst[k0 + __popcll(m1 & below)] = uint32_t(lane) + 64u;
+      __builtin_amdgcn_wave_barrier();
+      const int ncand = (k0 + __popcll(m1)) << lsl;
+      for (int ci = lane; ci < ncand; ci += 64) {
+        const uint32_t jl = lst[ci >> lsl];
+        const uint32_t u = (jl << lsl) | (uint32_t(ci) & ((1u << lsl) - 1u));
+        // operands are below N_last <= 4096, so 24-bit products are exact
+        const uint32_t il = __umul24(sinv_last[s0], u) & nm[D - 1];
+        int votes = 1;   // round s0 maps il back to u, whose bucket is flagged
+        bool skip = false;
+#pragma unroll
+        for (int s = 0; s < TT; ++s) {
+          if (s == s0) continue;
+          const uint32_t bit = row_bit(R + s * 4, (__umul24(sig[s][D - 1], il) & nm[D - 1]) >> lsl);
+          if (s < s0 && bit) skip = true;
+          votes += int(bit);
+        }
+        if (!skip && votes >= mu) atomicOr(&rb[il >> 5], 1u << (il & 31u));
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int q = lane; q < row_words; q += 64) {
+      const uint32_t v = rb[q];
+      bm[int64_t(r) * row_words + q] = v;
+      cnt += uint32_t(__popc(v));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // wave total, then work-group total
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_down(cnt, o);
+  if (lane == 0) wcount[wave] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t total = 0u;
+    for (int w = 0; w < kVoteThreads / 64; ++w) total += wcount[w];
+    p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = total;
+  }
+}
+
+template <int D>
+static void launch_vote_d(const DevPtrs& p, dim3 grid, size_t shmem, hipStream_t st, int T, int mu,
+                          int frame0, bool rows) {
+  if (rows) {
+    switch (T) {
+      case 1: hipLaunchKernelGGL((vote_rows_kernel<D, 1>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      case 2: hipLaunchKernelGGL((vote_rows_kernel<D, 2>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      case 3: hipLaunchKernelGGL((vote_rows_kernel<D, 3>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      case 4: hipLaunchKernelGGL((vote_rows_kernel<D, 4>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      default: break;
+    }
+  }
+  hipLaunchKernelGGL(vote_kernel<D>, grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0);
+}
+
+int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks, int max_words,
+                int dims_mask, int rows_ok, int frame0, void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  const size_t shmem = size_t(T) * size_t(max_words) * sizeof(uint32_t);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid{unsigned(max_cchunks), unsigned(nframes), 1u};
+  const bool rows = rows_ok != 0 && T <= 4;
+  if (dims_mask & 1) launch_vote_d<1>(p, grid, shmem, st, T, mu, frame0, rows);
+  if (dims_mask & 2) launch_vote_d<2>(p, grid, shmem, st, T, mu, frame0, rows);
+  if (dims_mask & 4) launch_vote_d<3>(p, grid, shmem, st, T, mu, frame0, rows);
+  if (dims_mask & 8) launch_vote_d<4>(p, grid, shmem, st, T, mu, frame0, rows);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scan: one work-group per frame turns the frame's chunk counters into
+// chunk_offsets (rank of each compaction chunk's first detection in its
+// frame, a running sum in row-major cell order) and counts[f]. The last
+// work-group to finish (a device-scope counter, released and acquired with
+// fences) computes offsets[f] = sum_{g<f} min(count_g, cap_g),
+// offsets[nframes] = total, and resets the counter for the next launch.
+// ---------------------------------------------------------------------------
+
+constexpr int kScanThreads = 256;
+
+// inclusive scan of v over the work-group; returns it and the block total
+__device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wtot, int64_t& total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int64_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wtot[wave] = incl;
+  __syncthreads();
+  int64_t pre = 0;
+  total = 0;
+#pragma unroll
+  for (int q = 0; q < kScanThreads / 64; ++q) {
+    if (q < wave) pre += wtot[q];
+    total += wtot[q];
+  }
+  __syncthreads();
+  return pre + incl;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t nframes) {
+  __shared__ int64_t wtot[kScanThreads / 64];
+  __shared__ int is_last;
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x;
+  const FrameDesc& d = desc_of(p, f);
+  const int64_t rel = rel_of(p, f);
+  const int64_t base = d.chunk_off + rel * d.chunk_stride;
+  int64_t run = 0;
+  for (int c0 = 0; c0 < d.cchunks; c0 += kScanThreads) {
+    const int c = c0 + tid;
+    const int64_t v = c < d.cchunks ? int64_t(p.chunk_counts[base + c]) : 0;
+    int64_t total;
+    const int64_t incl = block_inclusive_scan(v, wtot, total);
+    if (c < d.cchunks) p.chunk_offsets[base + c] = run + incl - v;
+    run += total;
+  }
+  if (tid == 0) {
+    p.counts[f] = run;
+    __threadfence();
+    const unsigned prev = atomicAdd(p.scan_done, 1u);
+    is_last = prev == unsigned(nframes - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  int64_t carry = 0;
+  for (int64_t g0 = 0; g0 < nframes; g0 += kScanThreads) {
+    const int64_t g = g0 + tid;
+    int64_t v = 0;
+    if (g < nframes) {
+      const int64_t cnt = __atomic_load_n(p.counts + g, __ATOMIC_RELAXED);
+      const int64_t cap = desc_of(p, g).cap;
+      v = cnt < cap ? cnt : cap;
+    }
+    int64_t total;
+    const int64_t incl = block_inclusive_scan(v, wtot, total);
+    if (g < nframes) p.offsets[g + 1] = carry + incl;
+    carry += total;
+  }
+  if (tid == 0) {
+    p.offsets[0] = 0;
+    atomicExch(p.scan_done, 0u);
+  }
+}
+
+int launch_scan(const DevPtrs& p, int64_t nframes, void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  if (nframes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan_kernel, dim3(unsigned(nframes)), dim3(kScanThreads), 0,
+                     static_cast<hipStream_t>(stream), p, nframes);
+  return hipGetLastError();
+}
+
+}  // namespace rsft
