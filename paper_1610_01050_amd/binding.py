@@ -330,6 +330,10 @@ class Plan:
         self.rounds = int(_descs[0].get("rounds", 3))
         self.dtype = _descs[0].get("dtype", "c64")
         self.last_batch = None
+        # input elements: per frame of a uniform plan, in all of an uneven one
+        seg = self.rounds if _descs[0].get("segments") else 1
+        self._elems = [int(np.prod(d["shape"])) * seg for d in self.descs]
+        self._elems_total = sum(self._elems)
 
     @classmethod
     def uneven(cls, frames):
@@ -354,9 +358,7 @@ class Plan:
             raise TypeError(f"input dtype must be {want}")
         if not x.is_contiguous():
             raise ValueError("input must be contiguous")
-        need = sum(int(np.prod(s)) for s in self._frame_shapes(batch))
-        if self.descs[0].get("segments"):
-            need *= self.rounds                     # [T] segments per frame
+        need = self._elems[0] * int(batch) if self.uniform else self._elems_total
         if x.numel() < need:
             raise ValueError(f"input holds {x.numel()} elements, batch needs {need}")
 

@@ -21,7 +21,7 @@ namespace rsft {
 
 constexpr int kDftThreads = 1024;
 constexpr int kDftWaves = kDftThreads / 64;
-constexpr int kDftItems = 4;   // output tiles per wave between barriers
+constexpr int kDftItems = 2;   // output tiles per wave between barriers
 
 // LDS position of bucket index idx: one pad float after every row of the
 // last dimension (row length 2^nl_shift), so that 16 lines read at the same
@@ -29,7 +29,10 @@ constexpr int kDftItems = 4;   // output tiles per wave between barriers
 __device__ __forceinline__ int lds_at(int idx, int nl_shift) { return idx + (idx >> nl_shift); }
 
 // One 16-line x 16-output tile of Y = D_n X along a dimension: lines
-// grp*16 .. grp*16+15, outputs k = kt*16 .. kt*16+15.
+// grp*16 .. grp*16+15, outputs k = kt*16 .. kt*16+15. Four k-steps of the
+// contraction are read from LDS at once (branch-free: an index outside the
+// matrix reads element 0 and is replaced by zero), then fed to two
+// accumulator pairs, which halves the chain of dependent MFMAs.
 __device__ __forceinline__ void dft_tile(const float* __restrict__ re, const float* __restrict__ im,
                                          const float2* __restrict__ tw, int n, int inner_shift,
                                          int nlines, int nl_shift, int grp, int kt, floatx4& accR,
@@ -42,26 +45,39 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ re, const flo
   const int inner = 1 << inner_shift;
   const int base = (line >> inner_shift) * n * inner + (line & (inner - 1));
   const int k = kt * 16 + col;
-  accR = floatx4{0.f, 0.f, 0.f, 0.f};
-  accI = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int b0 = 0; b0 < n; b0 += 4) {
-    const int b = b0 + krow;
-    float xr = 0.f, xi = 0.f, dr = 0.f, di = 0.f;
-    if (lvalid && b < n) {
-      const int at = lds_at(base + b * inner, nl_shift);
-      xr = re[at];
-      xi = im[at];
-    }
-    if (k < n && b < n) {
+  const bool kvalid = k < n;
+  floatx4 aR0{0.f, 0.f, 0.f, 0.f}, aI0{0.f, 0.f, 0.f, 0.f};
+  floatx4 aR1{0.f, 0.f, 0.f, 0.f}, aI1{0.f, 0.f, 0.f, 0.f};
+  for (int b0 = 0; b0 < n; b0 += 16) {
+    float xr[4], xi[4], dr[4], di[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + 4 * u + krow;
+      const bool xv = lvalid && b < n;
+      const bool dv = kvalid && b < n;
+      const int at = xv ? lds_at(base + b * inner, nl_shift) : 0;
+      const float vr = re[at];
+      const float vi = im[at];
       const float2 t = tw[(k * b) & (n - 1)];
-      dr = t.x;
-      di = t.y;
+      xr[u] = xv ? vr : 0.f;
+      xi[u] = xv ? vi : 0.f;
+      dr[u] = dv ? t.x : 0.f;
+      di[u] = dv ? t.y : 0.f;
     }
-    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xr, accR, 0, 0, 0);
-    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-di, xi, accR, 0, 0, 0);
-    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, xi, accI, 0, 0, 0);
-    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(di, xr, accI, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; u += 2) {
+      aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[u], xr[u], aR0, 0, 0, 0);
+      aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[u], xi[u], aI0, 0, 0, 0);
+      aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[u + 1], xr[u + 1], aR1, 0, 0, 0);
+      aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(dr[u + 1], xi[u + 1], aI1, 0, 0, 0);
+      aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-di[u], xi[u], aR0, 0, 0, 0);
+      aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(di[u], xr[u], aI0, 0, 0, 0);
+      aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-di[u + 1], xi[u + 1], aR1, 0, 0, 0);
+      aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(di[u + 1], xr[u + 1], aI1, 0, 0, 0);
+    }
   }
+  accR = aR0 + aR1;
+  accI = aI0 + aI1;
 }
 
 // The DFT along one dimension of length n for all B / n lines, in place.
@@ -137,28 +153,59 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   const int wave = tid >> 6;
 
 
-  // twiddles of each dimension, concatenated
+  // Twiddles of each dimension (concatenated; B_d <= 128, one per thread)
+  // and the column-chunk partials of this round: the loads of a group are
+  // issued before the first of them is used.
   int twoff[kMaxDims];
+  float2 twv[kMaxDims];
   {
     int acc = 0;
-    for (int dd = 0; dd < d.ndim; ++dd) {
+#pragma unroll
+    for (int dd = 0; dd < kMaxDims; ++dd) {
       twoff[dd] = acc;
-      for (int m = tid; m < d.b[dd]; m += kDftThreads) tws[acc + m] = p.tw[d.tw_off[dd] + m];
-      acc += d.b[dd];
+      twv[dd] = make_float2(0.f, 0.f);
+      if (dd < d.ndim) {
+        if (tid < d.b[dd]) twv[dd] = p.tw[d.tw_off[dd] + tid];
+        acc += d.b[dd];
+      }
     }
   }
-  // sum the column-chunk partials of this round
   const int nch = nchunks_override > 0 ? nchunks_override : d.nchunks;
-  const float2* part = p.part + d.part_off + rel * d.part_stride;
-  for (int idx = tid; idx < B; idx += kDftThreads) {
-    float sr = 0.f, si = 0.f;
-    for (int c = 0; c < nch; ++c) {
-      const float2 v = part[(int64_t(c) * T + s) * B + idx];
-      sr += v.x;
-      si += v.y;
+  const float2* part = p.part + d.part_off + rel * d.part_stride + int64_t(s) * B;
+#pragma unroll
+  for (int dd = 0; dd < kMaxDims; ++dd)
+    if (dd < d.ndim && tid < d.b[dd]) tws[twoff[dd] + tid] = twv[dd];
+  // groups of kGrp buckets per thread (one group when B <= 4096)
+  constexpr int kGrp = 4;
+  for (int g0 = 0; g0 < B; g0 += kGrp * kDftThreads) {
+    float2 sum[kGrp];
+#pragma unroll
+    for (int q = 0; q < kGrp; ++q) {
+      const int idx = g0 + q * kDftThreads + tid;
+      sum[q] = idx < B ? part[idx] : make_float2(0.f, 0.f);
     }
-    re[lds_at(idx, nls)] = sr;
-    im[lds_at(idx, nls)] = si;
+    for (int c = 1; c < nch; ++c) {
+      const float2* pc = part + int64_t(c) * T * B;
+      float2 v[kGrp];
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) {
+        const int idx = g0 + q * kDftThreads + tid;
+        v[q] = idx < B ? pc[idx] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int q = 0; q < kGrp; ++q) {
+        sum[q].x += v[q].x;
+        sum[q].y += v[q].y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kGrp; ++q) {
+      const int idx = g0 + q * kDftThreads + tid;
+      if (idx < B) {
+        re[lds_at(idx, nls)] = sum[q].x;
+        im[lds_at(idx, nls)] = sum[q].y;
+      }
+    }
   }
   __syncthreads();
 
