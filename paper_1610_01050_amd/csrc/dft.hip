@@ -131,6 +131,73 @@ __device__ __forceinline__ void mode_product(float* __restrict__ re, float* __re
   }
 }
 
+// The DFT along one dimension of length n = 16 r (r = 1, 2, 4, 8), in
+// place, by decimation in frequency: with j = j1 + 16 j2 and k = k2 + r k1
+// (j1, k1 < 16; j2, k2 < r), W_m = exp(-2 pi i / m),
+//   Z[k2 + r k1] = sum_{j1} W_16^{j1 k1} y_{k2}[j1],
+//   y_{k2}[j1]   = W_n^{j1 k2} sum_{j2} W_r^{j2 k2} x[j1 + 16 j2].
+// Each lane forms its y on the VALU (r complex products and one twiddle per
+// k-step, twiddles read from the LDS table) and the 16-point DFTs run on MFMA: a tile is 16 columns (line,
+// k2) = 16 / r whole lines, so it reads and writes only its own lines and
+// the transform needs no barrier between reading and writing. Every
+// exponent is reduced modulo n as an integer before the table lookup
+// (W_16^a = tw[a r], W_r^a = tw[16 a]).
+__device__ __forceinline__ void mode_product_r16(float* __restrict__ re, float* __restrict__ im,
+                                                 const float2* __restrict__ tw, int n, int inner_shift,
+                                                 int nlines, int nl_shift) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;
+  const int kk = lane >> 4;
+  const int r = n >> 4;
+  const int rshift = __builtin_ctz(uint32_t(r));
+  const int k2 = col & (r - 1);
+  const int inner = 1 << inner_shift;
+  const int mask = n - 1;
+  const int ntiles = ((nlines << rshift) + 15) >> 4;
+  for (int tile = wave; tile < ntiles; tile += kDftWaves) {
+    const int line = (tile << (4 - rshift)) + (col >> rshift);
+    const bool lvalid = line < nlines;
+    const int base = lvalid ? (line >> inner_shift) * n * inner + (line & (inner - 1)) : 0;
+    floatx4 accR{0.f, 0.f, 0.f, 0.f}, accI{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+      const int j1 = 4 * t + kk;
+      const float2 a = tw[(j1 * col * r) & mask];    // W_16^{j1 k1}, k1 = col (MFMA A operand)
+      const float2 t1 = tw[(j1 * k2) & mask];        // W_n^{j1 k2}
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int j2 = 0; j2 < 8; ++j2) {
+        if (j2 < r) {
+          const int at = lds_at(base + (j1 + 16 * j2) * inner, nl_shift);
+          const float xr = re[at], xi = im[at];
+          const float2 w = tw[(16 * j2 * k2) & mask];
+          sr += w.x * xr - w.y * xi;
+          si += w.x * xi + w.y * xr;
+        }
+      }
+      float yr = t1.x * sr - t1.y * si;
+      float yi = t1.x * si + t1.y * sr;
+      yr = lvalid ? yr : 0.f;
+      yi = lvalid ? yi : 0.f;
+      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, yr, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, yi, accI, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, yi, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, yr, accI, 0, 0, 0);
+    }
+    if (lvalid) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k2 + r * (4 * kk + q);
+        const int at = lds_at(base + k * inner, nl_shift);
+        re[at] = accR[q];
+        im[at] = accI[q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int plane, int pad,
                                                           int frame0, int identity,
                                                           int nchunks_override) {
@@ -211,7 +278,10 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
 
   for (int dd = 0; dd < d.ndim; ++dd) {
     const int n = d.b[dd];
-    mode_product(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
+    if (n >= 16)
+      mode_product_r16(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
+    else
+      mode_product(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
   }
 
   float2* bout = p.buckets + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
