@@ -7,16 +7,20 @@ namespace rsft {
 // ---------------------------------------------------------------------------
 // dft: one work-group per (round, frame). The round's B partial buckets are
 // summed over column chunks into LDS (separate re / im planes), then the DFT
-// is applied along each dimension in place as complex matrix products on
-// MFMA (v_mfma_f32_16x16x4_f32): for a dimension of length n, the lines
-// along it are the columns of an n x (B/n) matrix X and Y = D_n X with
-// D_n[k][b] = exp(-2 pi i ((k b) mod n) / n), the phase reduced exactly as
-// an integer before the table lookup. The work is split into (16-line group,
-// 16-output tile) items over all waves; a round of items holds whole line
-// groups and is written back only after every item of the round is computed,
-// so the transform is done in place. The epilogue reads the transform at the
-// relabelled index (tau_s j mod B_d per dimension), writes the buckets in
-// the paper's indexing, and sets flag bits |fhat|^2 >= gamma_s with ballots.
+// is applied along each dimension in place, with complex products on MFMA
+// (v_mfma_f32_16x16x4_f32, four real products per complex one). For a
+// dimension of length n the lines along it are the columns of an n x (B/n)
+// matrix X, and Y = D_n X with D_n[k][b] = exp(-2 pi i ((k b) mod n) / n),
+// the phase reduced exactly as an integer before the table lookup:
+//   n = 16 r  decimation in frequency, radix-r pre-combination on the VALU
+//             and 16-point DFTs on MFMA (mode_product_r16);
+//   n < 16    the dense product, in (16-line group, 16-output tile) items
+//             over all waves; a round of items holds whole line groups and
+//             is written back only after every item of the round is
+//             computed (mode_product).
+// The epilogue reads the transform at the relabelled index (tau_s j mod B_d
+// per dimension), writes the buckets in the paper's indexing, and sets flag
+// bits |fhat|^2 >= gamma_s with ballots.
 // ---------------------------------------------------------------------------
 
 constexpr int kDftThreads = 1024;
