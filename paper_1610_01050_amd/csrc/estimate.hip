@@ -259,7 +259,8 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
 #pragma unroll
   for (int dd = D - 1; dd >= 0; --dd) {
     const double delta = log_parabola_offset(P(kCentre - stride), p0, P(kCentre + stride));
-    double fr = (double(cell[dd]) + delta) / double(e.nm[dd] + 1u);
+    // N_d is a power of two: scaling by 2^-log2(N_d) equals the division exactly
+    double fr = ldexp(double(cell[dd]) + delta, -__builtin_ctz(e.nm[dd] + 1u));
     if (fr < 0.0) fr += 1.0;
     if (fr >= 1.0) fr -= 1.0;
     rec.idx[dd] = cell[dd];
