@@ -37,9 +37,9 @@ from synth import scoring  # noqa: E402
 
 METRIC = "frames/s + HBM GB/s: batched fused RSFT vs per-frame RSFT at equal Pd/Pfa"
 HBM_PEAK_GBS = 8000.0
-CONFIG = 2
+WORKLOAD = "offgrid_1024x1024"
 FRAMES = 128
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "fold_c2_hbm_counters.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "fold_1024x1024x128_hbm_counters.json")
 # the sources the fold kernel is built from: its counters stay valid while
 # these are unchanged
 FOLD_SOURCES = [os.path.join(ROOT, "paper_1610_01050_amd", "csrc", f)
@@ -99,7 +99,7 @@ def summarize_counters(fetch_dir, write_dir, command_fetch, command_write):
     dispatch) into HBM bytes per fold launch. Both counters are scaled by what
     they read for the elementwise negation that makes the second input buffer,
     a kernel that reads and writes exactly 1 GiB."""
-    calib_bytes = FRAMES * int(np.prod(synth.CONFIGS[CONFIG]["shape"])) * 8
+    calib_bytes = FRAMES * int(np.prod(synth.WORKLOADS[WORKLOAD]["shape"])) * 8
     out = {"kernel_source_sha256_16": kernel_source_hash(),
            "commands": {"FETCH_SIZE": command_fetch, "WRITE_SIZE": command_write},
            "calibration": {"kernel": "elementwise negation (torch.neg) of the 1 GiB input batch",
@@ -123,9 +123,9 @@ def summarize_counters(fetch_dir, write_dir, command_fetch, command_write):
                 continue
             key = name[name.index("fold_kernel<"):name.index(">", name.index("fold_kernel<")) + 1]
             per.setdefault(key, {})[counter] = (float(np.mean(v)), len(v), scale)
-    N = int(np.prod(synth.CONFIGS[CONFIG]["shape"]))
-    B = int(np.prod(synth.CONFIGS[CONFIG]["buckets"]))
-    T = synth.CONFIGS[CONFIG]["rounds"]
+    N = int(np.prod(synth.WORKLOADS[WORKLOAD]["shape"]))
+    B = int(np.prod(synth.WORKLOADS[WORKLOAD]["buckets"]))
+    T = synth.WORKLOADS[WORKLOAD]["rounds"]
     algorithmic = FRAMES * (N * 8 + T * B * 8)
     for key, c in sorted(per.items()):
         if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
@@ -195,12 +195,12 @@ def refine_section(dev, steps=20):
     import torch
     from paper_1610_01050_amd import Plan
     from paper_1610_01050_amd.refine import refine
-    cfg = synth.CONFIGS[5]
+    cfg = synth.WORKLOADS["offgrid_2048x2048"]
     F, K = 16, cfg["K"]
     shape = cfg["shape"]
     log(f"refinement: generating {F} frames {shape} ...")
-    frames, metas = synth.make_batch(5, F)
-    plan = Plan(shape, cfg["buckets"], rounds=cfg["rounds"], sigma=synth.shared_sigma(5),
+    frames, metas = synth.make_batch("offgrid_2048x2048", F)
+    plan = Plan(shape, cfg["buckets"], rounds=cfg["rounds"], sigma=synth.shared_sigma("offgrid_2048x2048"),
                 pfa=cfg["pfa"], max_batch=F)
     x = torch.from_numpy(frames).to(dev)
     plan.execute(x)
@@ -352,8 +352,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(frames shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(frames would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -361,20 +361,20 @@ def main():
     load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    cfg = synth.CONFIGS[CONFIG]
+    cfg = synth.WORKLOADS[WORKLOAD]
     shape, buckets, T, pfa = cfg["shape"], cfg["buckets"], cfg["rounds"], cfg["pfa"]
     N = int(np.prod(shape))
     B = int(np.prod(buckets))
 
     log(f"generating {FRAMES} frames {shape} ...")
     t0 = time.perf_counter()
-    frames_np, metas = synth.make_batch(CONFIG, FRAMES)
+    frames_np, metas = synth.make_batch(WORKLOAD, FRAMES)
     log(f"  done in {time.perf_counter() - t0:.1f} s")
     xa = torch.from_numpy(frames_np).to(dev)
     xb = torch.neg(xa)   # second buffer: same statistics, other bytes; this kernel reads
                          # and writes exactly 1 GiB and calibrates the HBM counters
     bufs = [xa, xb]
-    sigma = synth.shared_sigma(CONFIG)
+    sigma = synth.shared_sigma(WORKLOAD)
     plan = Plan(shape, buckets, rounds=T, sigma=sigma, window_atten_db=cfg["atten_db"],
                 pfa=pfa, dtype="c64", max_batch=FRAMES, max_detections=1 << 16)
     torch.cuda.synchronize()

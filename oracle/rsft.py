@@ -13,7 +13,7 @@ Every step follows the paper's order and notation:
   abar <- abar + a_s          accumulation (eq. a_i)
   o <- abar >= mu             second-stage detection (Sec. III-C.5)
 
-Readings where the paper is silent or ambiguous (listed in the design doc):
+Readings where the paper is silent or ambiguous:
 exactly T rounds on the same data with different sigma; detection means
 ``>=`` at both stages; mu in {1..T}; the first-stage threshold of round s is
 gamma_s = sigma_n^2 beta(sigma_s) ln(1/p1) with p1 solving the exact binomial

@@ -6,23 +6,28 @@ This module holds none of RSFT's arithmetic. It only produces inputs; both
 the FP64 oracle and the HIP library consume what it returns, so neither of
 them depends on the other.
 
-Recipes (one per workload; seed 1610010500 + config number, per-frame
-generator numpy.random.default_rng([seed, frame])). Draw order per frame:
+Recipes (one per workload; the workload's seed, per-frame generator
+numpy.random.default_rng([seed, frame])). Draw order per frame:
 (shape, for the uneven batch), tone count, frequencies (re-drawn until every
 pair of tones is more than ``min_sep`` bins apart in circular L-infinity
 distance), per-tone SNR in dB, complex amplitudes, noise, and (for per-frame
 permutations) sigma.
 
-  C1  256x256 complex128, K=4 on-grid tones >= 3 bins apart, unit magnitude,
+  ongrid_256x256_c128
+      256x256 complex128, K=4 on-grid tones >= 3 bins apart, unit magnitude,
       uniform phase, CN(0,1) noise (0 dB per sample), B=16x16, T=3,
       Pfa=1e-3, 60 dB Chebyshev windows, one sigma set for the batch.
-  C2  1024x1024 complex64, K=20 off-grid tones f ~ U[0,1)^2, SNR ~ U[-10,10]
+  offgrid_1024x1024
+      1024x1024 complex64, K=20 off-grid tones f ~ U[0,1)^2, SNR ~ U[-10,10]
       dB, Rayleigh amplitudes b ~ CN(0, 10^(SNR/10)), B=64x64, T=3, Pfa=1e-4.
-  C3  256x128x32 complex64 radar cube (range, Doppler, antenna), K=16 off-grid
+  cube_256x128x32
+      256x128x32 complex64 radar cube (range, Doppler, antenna), K=16 off-grid
       tones, SNR ~ U[-5,15] dB, B=32x16x8, T=3, Pfa=1e-4, sigma per CPI.
-  C4  uneven batch: N_d drawn per dimension from {128,...,2048}, K ~ U{1..50},
+  uneven_128_to_2048
+      uneven batch: N_d drawn per dimension from {128,...,2048}, K ~ U{1..50},
       SNR ~ U[-10,10] dB, B_d = N_d/16, T=3, Pfa=1e-4, sigma per frame.
-  C5  2048x2048 complex64, K=32 off-grid, SNR ~ U[-10,10] dB, B=128x128,
+  offgrid_2048x2048
+      2048x2048 complex64, K=32 off-grid, SNR ~ U[-10,10] dB, B=128x128,
       T=3, Pfa=1e-4.
 """
 
@@ -30,27 +35,27 @@ import numpy as np
 
 BASE_SEED = 1610010500
 
-CONFIGS = {
-    1: dict(shape=(256, 256), buckets=(16, 16), K=4, ongrid=True,
-            unit_amplitude=True, snr_db=(0.0, 0.0), dtype=np.complex128,
-            rounds=3, pfa=1e-3, atten_db=60.0, sigma_per_frame=False,
-            min_sep=3.0),
-    2: dict(shape=(1024, 1024), buckets=(64, 64), K=20, ongrid=False,
-            unit_amplitude=False, snr_db=(-10.0, 10.0), dtype=np.complex64,
-            rounds=3, pfa=1e-4, atten_db=60.0, sigma_per_frame=False,
-            min_sep=2.05),
-    3: dict(shape=(256, 128, 32), buckets=(32, 16, 8), K=16, ongrid=False,
-            unit_amplitude=False, snr_db=(-5.0, 15.0), dtype=np.complex64,
-            rounds=3, pfa=1e-4, atten_db=60.0, sigma_per_frame=True,
-            min_sep=2.05),
-    4: dict(shape=None, buckets=None, K=(1, 50), ongrid=False,
-            unit_amplitude=False, snr_db=(-10.0, 10.0), dtype=np.complex64,
-            rounds=3, pfa=1e-4, atten_db=60.0, sigma_per_frame=True,
-            min_sep=2.05, sides=(128, 256, 512, 1024, 2048)),
-    5: dict(shape=(2048, 2048), buckets=(128, 128), K=32, ongrid=False,
-            unit_amplitude=False, snr_db=(-10.0, 10.0), dtype=np.complex64,
-            rounds=3, pfa=1e-4, atten_db=60.0, sigma_per_frame=False,
-            min_sep=2.05),
+WORKLOADS = {
+    "ongrid_256x256_c128": dict(
+        seed=BASE_SEED + 1, shape=(256, 256), buckets=(16, 16), K=4, ongrid=True,
+        unit_amplitude=True, snr_db=(0.0, 0.0), dtype=np.complex128, rounds=3, pfa=1e-3,
+        atten_db=60.0, sigma_per_frame=False, min_sep=3.0),
+    "offgrid_1024x1024": dict(
+        seed=BASE_SEED + 2, shape=(1024, 1024), buckets=(64, 64), K=20, ongrid=False,
+        unit_amplitude=False, snr_db=(-10.0, 10.0), dtype=np.complex64, rounds=3, pfa=1e-4,
+        atten_db=60.0, sigma_per_frame=False, min_sep=2.05),
+    "cube_256x128x32": dict(
+        seed=BASE_SEED + 3, shape=(256, 128, 32), buckets=(32, 16, 8), K=16, ongrid=False,
+        unit_amplitude=False, snr_db=(-5.0, 15.0), dtype=np.complex64, rounds=3, pfa=1e-4,
+        atten_db=60.0, sigma_per_frame=True, min_sep=2.05),
+    "uneven_128_to_2048": dict(
+        seed=BASE_SEED + 4, shape=None, buckets=None, K=(1, 50), ongrid=False,
+        unit_amplitude=False, snr_db=(-10.0, 10.0), dtype=np.complex64, rounds=3, pfa=1e-4,
+        atten_db=60.0, sigma_per_frame=True, min_sep=2.05, sides=(128, 256, 512, 1024, 2048)),
+    "offgrid_2048x2048": dict(
+        seed=BASE_SEED + 5, shape=(2048, 2048), buckets=(128, 128), K=32, ongrid=False,
+        unit_amplitude=False, snr_db=(-10.0, 10.0), dtype=np.complex64, rounds=3, pfa=1e-4,
+        atten_db=60.0, sigma_per_frame=False, min_sep=2.05),
 }
 
 
@@ -136,23 +141,23 @@ def complex_noise(rng, shape, var=1.0):
     return (re + 1j * im) * np.sqrt(var / 2.0)
 
 
-def config_seed(config):
-    return BASE_SEED + int(config)
+def workload_seed(workload):
+    return WORKLOADS[workload]["seed"]
 
 
-def shared_sigma(config, rounds=None, shape=None):
+def shared_sigma(workload, rounds=None, shape=None):
     """One sigma set shared by every frame of a batch."""
-    cfg = CONFIGS[config]
-    rng = np.random.default_rng([config_seed(config), 1 << 30])
+    cfg = WORKLOADS[workload]
+    rng = np.random.default_rng([workload_seed(workload), 1 << 30])
     return draw_sigma(rng, rounds or cfg["rounds"], shape or cfg["shape"])
 
 
-def make_frame(config, frame, K=None, noise=True, noise_var=1.0):
-    """One synthetic frame of a configuration. Returns a dict with the frame
-    (config dtype), the tone frequencies (cycles/sample, [K][D]), the complex
+def make_frame(workload, frame, K=None, noise=True, noise_var=1.0):
+    """One synthetic frame of a workload. Returns a dict with the frame
+    (workload dtype), the tone frequencies (cycles/sample, [K][D]), the complex
     amplitudes, the shape, and sigma (per-frame configs only)."""
-    cfg = CONFIGS[config]
-    rng = np.random.default_rng([config_seed(config), int(frame)])
+    cfg = WORKLOADS[workload]
+    rng = np.random.default_rng([workload_seed(workload), int(frame)])
     if cfg["shape"] is None:
         shape = tuple(int(rng.choice(cfg["sides"])) for _ in range(2))
     else:
@@ -179,10 +184,10 @@ def make_frame(config, frame, K=None, noise=True, noise_var=1.0):
     return out
 
 
-def make_batch(config, nframes, start=0, K=None, noise=True):
+def make_batch(workload, nframes, start=0, K=None, noise=True):
     """`nframes` consecutive frames of a uniform-shape configuration stacked
-    into one array [F, *shape] (config dtype), with per-frame metadata."""
-    metas = [make_frame(config, start + f, K=K, noise=noise)
+    into one array [F, *shape] (workload dtype), with per-frame metadata."""
+    metas = [make_frame(workload, start + f, K=K, noise=noise)
              for f in range(nframes)]
     frames = np.stack([m.pop("frame") for m in metas]) if metas else None
     return frames, metas

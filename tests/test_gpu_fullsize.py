@@ -54,12 +54,12 @@ def _sampled(sample, frames, oplans, recs, gbk, gfl):
         check_frame(f, oplans[f], ref, recs, gbk[f], gfl[f])
 
 
-def _run_uniform(config, nframes, sample, max_detections, bench_launch=False):
+def _run_uniform(workload, nframes, sample, max_detections, bench_launch=False):
     from paper_1610_01050_amd import OPT_GRAPH, Plan
-    cfg = synth.CONFIGS[config]
-    print(f"workload {config}: {nframes} x {cfg['shape']} generating", flush=True)
-    frames, _ = synth.make_batch(config, nframes)
-    sigma = synth.shared_sigma(config)
+    cfg = synth.WORKLOADS[workload]
+    print(f"workload {workload}: {nframes} x {cfg['shape']} generating", flush=True)
+    frames, _ = synth.make_batch(workload, nframes)
+    sigma = synth.shared_sigma(workload)
     dtype = "c128" if cfg["dtype"] == np.complex128 else "c64"
     plan = Plan(cfg["shape"], cfg["buckets"], rounds=cfg["rounds"], sigma=sigma,
                 window_atten_db=cfg["atten_db"], pfa=cfg["pfa"], dtype=dtype,
@@ -107,28 +107,28 @@ def _run_uneven(metas, sample, max_detections):
 @pytest.mark.timeout(300)
 def test_headline_batch_in_benchmark_launch_configuration():
     """128 frames of 1024x1024 complex64, B = 64x64, T = 3, Pfa = 1e-4."""
-    _run_uniform(2, 128, sample=(0, 77, 127), max_detections=1 << 16, bench_launch=True)
+    _run_uniform("offgrid_1024x1024", 128, sample=(0, 77, 127), max_detections=1 << 16, bench_launch=True)
 
 
 @pytest.mark.timeout(300)
 def test_ongrid_256x256_complex128_batch_1024():
-    _run_uniform(1, 1024, sample=(0, 511, 1023), max_detections=1 << 15)
+    _run_uniform("ongrid_256x256_c128", 1024, sample=(0, 511, 1023), max_detections=1 << 15)
 
 
 @pytest.mark.timeout(300)
 def test_2048x2048_batch_16():
-    _run_uniform(5, 16, sample=(0, 15), max_detections=1 << 17)
+    _run_uniform("offgrid_2048x2048", 16, sample=(0, 15), max_detections=1 << 17)
 
 
 @pytest.mark.timeout(300)
 def test_radar_cube_64_cpis_sigma_per_cpi():
     """64 CPIs of 256 x 128 x 32 (range, Doppler, antenna), each with its own
     sigma, as one batch of per-frame descriptors."""
-    cfg = synth.CONFIGS[3]
+    cfg = synth.WORKLOADS["cube_256x128x32"]
     print("workload 3: 64 CPIs generating", flush=True)
     metas = []
     for f in range(64):
-        m = synth.make_frame(3, f)
+        m = synth.make_frame("cube_256x128x32", f)
         m.update(rounds=cfg["rounds"], pfa=cfg["pfa"], buckets=cfg["buckets"])
         metas.append(m)
     _run_uneven(metas, sample=(0, 31, 63), max_detections=1 << 16)
@@ -138,11 +138,11 @@ def test_radar_cube_64_cpis_sigma_per_cpi():
 def test_uneven_batch_512_frames():
     """512 frames with sides drawn from {128..2048} per dimension, B_d = N_d/16,
     sigma per frame, in one launch."""
-    cfg = synth.CONFIGS[4]
+    cfg = synth.WORKLOADS["uneven_128_to_2048"]
     print("workload 4: 512 uneven frames generating", flush=True)
     metas = []
     for f in range(512):
-        m = synth.make_frame(4, f)
+        m = synth.make_frame("uneven_128_to_2048", f)
         m.update(rounds=cfg["rounds"], pfa=cfg["pfa"], buckets=None)
         metas.append(m)
     sizes = [int(np.prod(m["shape"])) for m in metas]

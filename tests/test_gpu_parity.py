@@ -40,9 +40,9 @@ def _plan(**kw):
 
 CASES = {
     # name: (shape, buckets, rounds, mu, dtype, batch, K, pfa, atten)
-    "c1_256x256_c128": ((256, 256), (16, 16), 3, 0, "c128", 3, 4, 1e-3, 60.0),
-    "c2_1024x1024": ((1024, 1024), (64, 64), 3, 0, "c64", 2, 20, 1e-4, 60.0),
-    "c3_cube_256x128x32": ((256, 128, 32), (32, 16, 8), 3, 0, "c64", 2, 6, 1e-4, 60.0),
+    "ongrid_256x256_c128": ((256, 256), (16, 16), 3, 0, "c128", 3, 4, 1e-3, 60.0),
+    "offgrid_1024x1024": ((1024, 1024), (64, 64), 3, 0, "c64", 2, 20, 1e-4, 60.0),
+    "cube_256x128x32": ((256, 128, 32), (32, 16, 8), 3, 0, "c64", 2, 6, 1e-4, 60.0),
     "one_dim_4096": ((4096,), (64,), 3, 0, "c64", 3, 3, 1e-3, 60.0),
     "four_dim": ((16, 8, 16, 32), (4, 2, 4, 8), 3, 0, "c64", 2, 3, 1e-3, 60.0),
     "short_rows_512x64": ((512, 64), (32, 8), 3, 0, "c64", 2, 5, 1e-3, 60.0),
@@ -92,7 +92,7 @@ def test_fused_path_matches_oracle(name):
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["c1_256x256_c128", "c3_cube_256x128x32", "one_dim_4096"])
+@pytest.mark.parametrize("name", ["ongrid_256x256_c128", "cube_256x128x32", "one_dim_4096"])
 def test_per_frame_path_matches_oracle(name):
     plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name, per_frame=True)
     for f, ref in enumerate(refs):
@@ -100,7 +100,7 @@ def test_per_frame_path_matches_oracle(name):
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["c2_1024x1024", "short_rows_512x64"])
+@pytest.mark.parametrize("name", ["offgrid_1024x1024", "short_rows_512x64"])
 def test_estimated_noise_floor_matches_oracle(name):
     plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name, noise="estimated")
     for f, ref in enumerate(refs):
@@ -108,7 +108,7 @@ def test_estimated_noise_floor_matches_oracle(name):
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["c1_256x256_c128", "c3_cube_256x128x32", "four_dim",
+@pytest.mark.parametrize("name", ["ongrid_256x256_c128", "cube_256x128x32", "four_dim",
                                   "five_rounds_mu3", "one_dim_4096"])
 def test_votes_bit_exact_from_oracle_flags(name):
     """Voting, second stage and ordering are integer work: given the oracle's
@@ -266,7 +266,7 @@ def test_dense_chunk_every_cell_detected():
 def test_autotuned_fold_keeps_parity():
     """Whatever launch shape the tuner picks, the results stay within the
     parity contract."""
-    name = "c2_1024x1024"
+    name = "offgrid_1024x1024"
     plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name)
     xd = torch.from_numpy(np.stack(frames)).to("cuda")
     ms = plan.autotune(xd, repeats=2)

@@ -172,12 +172,12 @@ def test_refinement_workload_2048x2048_sampled():
     """16 frames of 2048x2048, K = 32 tones, B = 128x128: the forward model of
     frame 0 against the oracle, and the gradients of two of its tones."""
     from paper_1610_01050_amd import Plan
-    cfg = synth.CONFIGS[5]
+    cfg = synth.WORKLOADS["offgrid_2048x2048"]
     shape, buckets = cfg["shape"], cfg["buckets"]
-    sigma = synth.shared_sigma(5)
+    sigma = synth.shared_sigma("offgrid_2048x2048")
     plan = Plan(shape, buckets, rounds=3, sigma=sigma, pfa=cfg["pfa"], max_batch=16)
     oplan = OR.OraclePlan(shape, buckets, sigma, 60.0, None, cfg["pfa"])
-    metas = [synth.make_frame(5, f, noise=False) for f in range(16)]
+    metas = [synth.make_frame("offgrid_2048x2048", f, noise=False) for f in range(16)]
     freqs = np.stack([m["freqs"] for m in metas])
     amps = np.stack([m["amps"] for m in metas]).astype(np.complex64)
     f_d, a_d = _dev(freqs, amps)

@@ -168,7 +168,7 @@ def test_noise_free_tones_all_detected():
     {i : sum_s c_s[M(i, sigma_s)] >= mu}."""
     shape, b = (256, 256), (16, 16)
     plan = _plan(shape, b, pfa=1e-3, seed=31)
-    meta = synth.make_frame(1, 0, noise=False)
+    meta = synth.make_frame("ongrid_256x256_c128", 0, noise=False)
     out = R.rsft(meta["frame"], plan)
     cells = [int(np.ravel_multi_index(tuple(int(round(f[d] * shape[d])) % shape[d]
                                             for d in range(2)), shape))
