@@ -339,11 +339,6 @@ class Plan:
     def uneven(cls, frames):
         return cls(_descs=list(frames))
 
-    def _frame_shapes(self, batch):
-        if self.uniform:
-            return [tuple(self.descs[0]["shape"])] * batch
-        return [tuple(d["shape"]) for d in self.descs]
-
     def _frame_buckets(self, batch):
         if self.uniform:
             return [tuple(self.descs[0]["buckets"])] * batch
