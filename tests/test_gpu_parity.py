@@ -52,6 +52,7 @@ CASES = {
     "five_rounds_mu3": ((256, 256), (16, 16), 5, 3, "c64", 2, 5, 1e-3, 60.0),
     "rectangular_windows": ((256, 256), (16, 16), 3, 0, "c64", 2, 5, 1e-3, 0.0),
     "forty_db": ((1024, 256), (32, 16), 3, 0, "c64", 2, 8, 1e-3, 40.0),
+    "max_rounds_64": ((512, 256), (16, 16), 64, 40, "c64", 1, 4, 1e-3, 60.0),
 }
 
 

@@ -37,6 +37,7 @@ CASES = {
     "two_dim_T5_mu3": ((256, 256), (16, 16), 5, 3, 0.0, 2),
     "one_dim_T40_mu12_given_p1": ((4096,), (64,), 40, 12, 0.2, 2),
     "three_dim_T3": ((64, 32, 16), (8, 4, 4), 3, 0, 0.0, 2),
+    "one_dim_T64_mu20_given_p1": ((2048,), (32,), 64, 20, 0.2, 1),
 }
 
 
