@@ -19,8 +19,8 @@ namespace rsft {
 //             is written back only after every item of the round is
 //             computed (mode_product).
 // The epilogue reads the transform at the relabelled index (tau_s j mod B_d
-// per dimension), writes the buckets in the paper's indexing, and sets flag
-// bits |fhat|^2 >= gamma_s with ballots.
+// per dimension), writes the buckets and their squared magnitudes in the
+// paper's indexing, and sets flag bits |fhat|^2 >= gamma_s with ballots.
 // ---------------------------------------------------------------------------
 
 constexpr int kDftThreads = 1024;
@@ -289,6 +289,7 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   }
 
   float2* bout = p.buckets + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
+  float* pout = p.powers + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
   uint32_t* fout = p.flags + d.flag_off + rel * d.flag_stride + int64_t(s) * d.words;
 
   auto relabel = [&](int j) {
@@ -307,8 +308,10 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
     for (int j = tid; j < B; j += kDftThreads) {
       const int kf = lds_at(relabel(j), nls);
       const float xr = re[kf], xi = im[kf];
+      const float pw = xr * xr + xi * xi;
       bout[j] = make_float2(xr, xi);
-      re[kf] = xr * xr + xi * xi;
+      pout[j] = pw;
+      re[kf] = pw;
     }
     __syncthreads();
     // lower median X_(h), h = B/2, by 4 passes of 8-bit radix selection
@@ -359,8 +362,10 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
       if (j < B) {
         const int kf = lds_at(relabel(j), nls);
         const float xr = re[kf], xi = im[kf];
+        const float pw = xr * xr + xi * xi;
         bout[j] = make_float2(xr, xi);
-        flag = double(xr * xr + xi * xi) >= gamma;
+        pout[j] = pw;
+        flag = double(pw) >= gamma;
       }
       const unsigned long long m = __ballot(flag);
       if (lane == 0) {

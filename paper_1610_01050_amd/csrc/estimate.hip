@@ -37,7 +37,7 @@ struct EstFrame {
   uint32_t nm[D], lm[D], ls[D], bs[D], ns[D];
   const float* ig[D];              // inverse flat-window gains per dimension
   uint32_t sig_est[M][D];
-  const float2* bk_est[M];
+  const float* pw_est[M];          // squared magnitudes |fhat_s|^2 of the estimation rounds
   const uint32_t* fl;              // flags [T][words]
   const int32_t* sig;              // sigma [kMaxRounds][kMaxDims] of the descriptor
   int words;
@@ -46,7 +46,7 @@ struct EstFrame {
 template <int D, int M>
 __device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d, int64_t rel,
                                            EstFrame<D, M>& e) {
-  const float2* bk = p.buckets + d.bucket_off + rel * d.bucket_stride;
+  const float* pw = p.powers + d.bucket_off + rel * d.bucket_stride;
 #pragma unroll
   for (int dd = 0; dd < D; ++dd) {
     e.nm[dd] = uint32_t(d.n[dd] - 1);
@@ -61,7 +61,7 @@ __device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d,
     const int s = d.est_rounds[q];
 #pragma unroll
     for (int dd = 0; dd < D; ++dd) e.sig_est[q][dd] = uint32_t(d.sigma[s][dd]);
-    e.bk_est[q] = bk + int64_t(s) * d.B;
+    e.pw_est[q] = pw + int64_t(s) * d.B;
   }
   e.fl = p.flags + d.flag_off + rel * d.flag_stride;
   e.sig = &d.sigma[0][0];
@@ -127,8 +127,7 @@ __device__ __forceinline__ float neighbour_power(const EstFrame<D, M>& e, const 
       jf |= jb[q][dd][o];
       gg *= g[q][dd][o];
     }
-    const float2 b = e.bk_est[q][jf];
-    v[q] = (b.x * b.x + b.y * b.y) * gg;
+    v[q] = e.pw_est[q][jf] * gg;
   }
   return median_of<M>(v);
 }
@@ -153,8 +152,7 @@ __device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, co
       gg *= ig * ig;
       jf |= (u >> e.ls[dd]) << e.bs[dd];
     }
-    const float2 b = e.bk_est[q][jf];
-    v[q] = (b.x * b.x + b.y * b.y) * gg;
+    v[q] = e.pw_est[q][jf] * gg;
   }
   return median_of<M>(v);
 }
@@ -299,7 +297,7 @@ __device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc&
 }
 
 template <int D, int M>
-__global__ __launch_bounds__(kEstThreads) void compact_estimate_kernel(DevPtrs p, int T,
+__global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(5))) void compact_estimate_kernel(DevPtrs p, int T,
                                                                        int64_t nframes,
                                                                        int max_cchunks,
                                                                        int xcd_groups) {

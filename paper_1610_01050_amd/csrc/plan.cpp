@@ -78,7 +78,7 @@ struct rsft_plan_s {
   int64_t ntiles_uneven = 0;     // uneven plans
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles;
-  DeviceBuffer d_part, d_buckets, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
+  DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
       d_offsets, d_records, d_scan_done;
   rsft::DevPtrs ptrs{};
   // state of the last execute
@@ -415,7 +415,7 @@ void free_plan(rsft_plan_s* pl) {
   if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
   DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
                           &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_part,
-                          &pl->d_buckets, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
+                          &pl->d_buckets, &pl->d_powers, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
                           &pl->d_scan_done};
   for (auto* b : bufs) release(*b);
@@ -541,6 +541,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = upload(pl->d_tiles, tiles)) != RSFT_OK) return st;
   if ((st = alloc(pl->d_part, size_t(part_off) * sizeof(float2))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_buckets, size_t(bucket_off) * sizeof(float2))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_powers, size_t(bucket_off) * sizeof(float))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_flags, size_t(flag_off) * sizeof(uint32_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_bitmap, size_t(bitmap_off) * sizeof(uint32_t))) != RSFT_OK) return st;
   HIP_TRY(hipMemset(pl->d_bitmap.ptr, 0, pl->d_bitmap.bytes));  // kept clear by the compaction
@@ -565,6 +566,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.flat = static_cast<const float2*>(pl->d_flat.ptr);
   q.part = static_cast<float2*>(pl->d_part.ptr);
   q.buckets = static_cast<float2*>(pl->d_buckets.ptr);
+  q.powers = static_cast<float*>(pl->d_powers.ptr);
   q.flags = static_cast<uint32_t*>(pl->d_flags.ptr);
   q.bitmap = static_cast<uint32_t*>(pl->d_bitmap.ptr);
   q.chunk_counts = static_cast<uint32_t*>(pl->d_chunk_counts.ptr);

@@ -80,6 +80,7 @@ struct DevPtrs {
   const float2* flat;
   float2* part;
   float2* buckets;
+  float* powers;               // |buckets|^2, same layout
   uint32_t* flags;
   uint32_t* bitmap;            // detected cells; every word written by the vote stage
   uint32_t* chunk_counts;      // detections per compaction chunk
