@@ -170,15 +170,25 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
   uint32_t cell[D];
 #pragma unroll
   for (int dd = 0; dd < D; ++dd) cell[dd] = uint32_t(flat >> e.ns[dd]) & e.nm[dd];
+  // votes: the flag of the cell's bucket in every round, four rounds' flag
+  // words loaded at a time (s < s0 + 4 <= 64 stays inside the sigma table)
   int votes = 0;
-  for (int s = 0; s < T; ++s) {
-    uint32_t jf = 0u;
+  for (int s0 = 0; s0 < T; s0 += 4) {
+    uint32_t wd[4], sh[4];
 #pragma unroll
-    for (int dd = 0; dd < D; ++dd) {
-      const uint32_t u = (uint32_t(e.sig[s * kMaxDims + dd]) * cell[dd]) & e.nm[dd];
-      jf |= (u >> e.ls[dd]) << e.bs[dd];
+    for (int k = 0; k < 4; ++k) {
+      const int s = s0 + k;
+      uint32_t jf = 0u;
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd) {
+        const uint32_t u = (uint32_t(e.sig[s * kMaxDims + dd]) * cell[dd]) & e.nm[dd];
+        jf |= (u >> e.ls[dd]) << e.bs[dd];
+      }
+      sh[k] = jf & 31u;
+      wd[k] = s < T ? e.fl[int64_t(s) * e.words + (jf >> 5)] : 0u;
     }
-    votes += int((e.fl[int64_t(s) * e.words + (jf >> 5)] >> (jf & 31u)) & 1u);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) votes += int((wd[k] >> sh[k]) & 1u);
   }
   float preg[kRegs ? kNb : 1];
   if constexpr (kRegs) {
@@ -319,35 +329,41 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(5))
   }
   if (f >= nframes) return;
   const FrameDesc& d = desc_of(p, f);
-  if (c >= d.cchunks || d.ndim != D || d.n_est != M) return;
+  // The descriptor fields, then the chunk's counters and bitmap words, are
+  // each loaded together before they are tested (no chain of dependent
+  // loads behind early exits).
+  const int cch = d.cchunks, nd = d.ndim, ne = d.n_est;
+  if ((c >= cch) | (nd != D) | (ne != M)) return;
   const int64_t rel = rel_of(p, f);
   const int64_t ck = d.chunk_off + rel * d.chunk_stride + c;
-  if (p.chunk_counts[ck] == 0u) return;
-  const int64_t rank0 = p.chunk_offsets[ck];
   const int64_t cap = d.cap;
-  if (rank0 >= cap) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  rsft_detection* out = p.records + p.offsets[f] + rank0;
   const uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride;
   const int w0 = c << (kCompactShift - 5);
   const int wend = min(d.bitmap_words, w0 + (1 << (kCompactShift - 5)));
+  // thread t's words w0 + 4t .. w0 + 4t + 3 (the one-pass listing below)
+  constexpr int kWpt = (1 << (kCompactShift - 5)) / kEstThreads;
+  uint32_t wv[kWpt];
+#pragma unroll
+  for (int q = 0; q < kWpt; ++q) {
+    const int w = w0 + tid * kWpt + q;
+    wv[q] = w < wend ? bm[w] : 0u;
+  }
+  const uint32_t chunk_count = p.chunk_counts[ck];
+  const int64_t rank0 = p.chunk_offsets[ck];
+  const int64_t frame_off = p.offsets[f];
+  if ((chunk_count == 0u) | (rank0 >= cap)) return;
+  rsft_detection* out = p.records + frame_off + rank0;
   const unsigned long long cell0 = (unsigned long long)c << kCompactShift;
   const int64_t room0 = cap - rank0;
   float* pcol = pbuf + threadIdx.x;
-  const uint32_t chunk_count = p.chunk_counts[ck];
   if (chunk_count <= uint32_t(kListMax)) {
-    // one pass: thread t lists the set bits of words w0 + 4t .. w0 + 4t + 3
-    constexpr int kWpt = (1 << (kCompactShift - 5)) / kEstThreads;
-    uint32_t wv[kWpt];
+    // one pass: thread t lists the set bits of its words
     int pc = 0;
 #pragma unroll
-    for (int q = 0; q < kWpt; ++q) {
-      const int w = w0 + tid * kWpt + q;
-      wv[q] = w < wend ? bm[w] : 0u;
-      pc += __popc(wv[q]);
-    }
+    for (int q = 0; q < kWpt; ++q) pc += __popc(wv[q]);
     int incl = pc;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
