@@ -227,25 +227,33 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   // Twiddles of each dimension (concatenated; B_d <= 128, one per thread)
   // and the column-chunk partials of this round: the loads of a group are
   // issued before the first of them is used.
+  // (every dimension's descriptor fields are read first, then the loads are
+  // issued together; entries beyond ndim exist and are not used)
   int twoff[kMaxDims];
   float2 twv[kMaxDims];
   {
+    const int nd = d.ndim;
+    int bd[kMaxDims];
+    int64_t toff[kMaxDims];
+#pragma unroll
+    for (int dd = 0; dd < kMaxDims; ++dd) {
+      bd[dd] = d.b[dd];
+      toff[dd] = d.tw_off[dd];
+    }
     int acc = 0;
 #pragma unroll
     for (int dd = 0; dd < kMaxDims; ++dd) {
       twoff[dd] = acc;
-      twv[dd] = make_float2(0.f, 0.f);
-      if (dd < d.ndim) {
-        if (tid < d.b[dd]) twv[dd] = p.tw[d.tw_off[dd] + tid];
-        acc += d.b[dd];
-      }
+      const bool use = dd < nd && tid < bd[dd];
+      twv[dd] = use ? p.tw[toff[dd] + tid] : make_float2(0.f, 0.f);
+      if (dd < nd) acc += bd[dd];
     }
   }
   const int nch = nchunks_override > 0 ? nchunks_override : d.nchunks;
   const float2* part = p.part + d.part_off + rel * d.part_stride + int64_t(s) * B;
 #pragma unroll
   for (int dd = 0; dd < kMaxDims; ++dd)
-    if (dd < d.ndim && tid < d.b[dd]) tws[twoff[dd] + tid] = twv[dd];
+    if (dd < d.ndim && tid < d.b[dd]) tws[twoff[dd] + tid] = twv[dd];   // fields cached by now
   // groups of kGrp buckets per thread (one group when B <= 4096)
   constexpr int kGrp = 4;
   for (int g0 = 0; g0 < B; g0 += kGrp * kDftThreads) {

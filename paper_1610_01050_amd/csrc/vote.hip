@@ -30,6 +30,26 @@ namespace rsft {
 constexpr int kVoteThreads = 256;
 constexpr int kRowWordsMax = 128;   // rows of up to 4096 cells
 
+// Stage n flag words from global memory into LDS, up to four per thread
+// loaded before any is stored (one memory round trip per 4 * kVoteThreads).
+__device__ __forceinline__ void stage_flags(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                            int n) {
+  constexpr int kPer = 4;
+  for (int w0 = 0; w0 < n; w0 += kPer * kVoteThreads) {
+    uint32_t v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int w = w0 + k * kVoteThreads + int(threadIdx.x);
+      v[k] = w < n ? src[w] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int w = w0 + k * kVoteThreads + int(threadIdx.x);
+      if (w < n) dst[w] = v[k];
+    }
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, int mu, int frame0) {
   extern __shared__ uint32_t sflags[];
@@ -38,14 +58,15 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, in
   const int c = blockIdx.x;
   const int64_t f = frame0 + int64_t(blockIdx.y);
   const FrameDesc& d = desc_of(p, f);
-  if (c >= d.cchunks || d.ndim != D) return;
+  const int cch = d.cchunks, nd = d.ndim;   // loaded together, then tested
+  if ((c >= cch) | (nd != D)) return;
   const int64_t rel = rel_of(p, f);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int words = d.words;
   const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
-  for (int w = tid; w < T * words; w += kVoteThreads) sflags[w] = fl[w];
+  stage_flags(sflags, fl, T * words);
   if (tid < T * D) ssig[tid] = uint32_t(d.sigma[tid / D][tid % D]);
   uint32_t nm[D], ls[D], bs[D], ns[D];
 #pragma unroll
@@ -109,14 +130,15 @@ __global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int 
   const int c = blockIdx.x;
   const int64_t f = frame0 + int64_t(blockIdx.y);
   const FrameDesc& d = desc_of(p, f);
-  if (c >= d.cchunks || d.ndim != D) return;
+  const int cch = d.cchunks, nd = d.ndim;   // loaded together, then tested
+  if ((c >= cch) | (nd != D)) return;
   const int64_t rel = rel_of(p, f);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int words = d.words;
   const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
-  for (int w = tid; w < TT * words; w += kVoteThreads) sflags[w] = fl[w];
+  stage_flags(sflags, fl, TT * words);
   uint32_t nm[D], ls[D], bs[D], ns[D];
 #pragma unroll
   for (int dd = 0; dd < D; ++dd) {
