@@ -249,6 +249,132 @@ def refine_section(dev, steps=20):
     return out
 
 
+# The other batched workloads, each at its full batch: (name, frames,
+# max detections per frame).
+OTHER_WORKLOADS = (
+    ("ongrid_256x256_c128", 1024, 1 << 15),
+    ("cube_256x128x32", 64, 1 << 16),
+    ("uneven_128_to_2048", 512, 1 << 17),
+    ("offgrid_2048x2048", 16, 1 << 17),
+)
+
+
+def _workload_plan(name, nframes, max_det):
+    """Plan, input array and per-frame metadata for one batched workload.
+    Workloads with one sigma per frame get one descriptor per frame."""
+    from paper_1610_01050_amd import Plan
+    cfg = synth.WORKLOADS[name]
+    dtype = "c128" if cfg["dtype"] == np.complex128 else "c64"
+    if not cfg["sigma_per_frame"]:
+        frames, metas = synth.make_batch(name, nframes)
+        for m in metas:
+            m["buckets"] = cfg["buckets"]
+        plan = Plan(cfg["shape"], cfg["buckets"], rounds=cfg["rounds"], sigma=synth.shared_sigma(name),
+                    window_atten_db=cfg["atten_db"], pfa=cfg["pfa"], dtype=dtype,
+                    max_batch=nframes, max_detections=max_det)
+        return plan, frames, metas
+    metas = [synth.make_frame(name, f) for f in range(nframes)]
+    descs = []
+    for m in metas:
+        m["buckets"] = cfg["buckets"] or tuple(n // 16 for n in m["shape"])
+        descs.append(dict(shape=m["shape"], buckets=m["buckets"], rounds=cfg["rounds"], sigma=m["sigma"],
+                          window_atten_db=cfg["atten_db"], pfa=cfg["pfa"], dtype=dtype,
+                          max_detections=max_det))
+    frames = np.concatenate([m.pop("frame").ravel() for m in metas])
+    return Plan.uneven(descs), frames, metas
+
+
+def workloads_section(dev, steps, warmup, names=None):
+    """Every other batched workload at its full batch, in the launch
+    configuration of the headline measurement: autotuned fold, graph replay
+    over two alternating input buffers (throughput), then eager launches
+    with events around each stage (fold bandwidth)."""
+    import torch
+    from paper_1610_01050_amd import OPT_GRAPH, OPT_TIMING
+    out = {}
+    for name, nframes, max_det in OTHER_WORKLOADS:
+        if names is not None and name not in names:
+            continue
+        cfg = synth.WORKLOADS[name]
+        log(f"workload {name}: generating {nframes} frames ...")
+        plan, frames_np, metas = _workload_plan(name, nframes, max_det)
+        esize = np.dtype(cfg["dtype"]).itemsize
+        T = cfg["rounds"]
+        in_bytes = sum(int(np.prod(m["shape"])) for m in metas) * esize
+        part_bytes = sum(T * int(np.prod(m["buckets"])) * 8 for m in metas)
+        xa = torch.from_numpy(frames_np).to(dev)
+        del frames_np
+        xb = torch.neg(xa)
+        bufs = [xa, xb]
+        plan.autotune(xa, repeats=3)
+        plan.set_option(OPT_TIMING, 0)
+        plan.set_option(OPT_GRAPH, 1)
+        for w in range(warmup):
+            plan.execute(bufs[w % 2])
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for k in range(steps):
+            plan.execute(bufs[k % 2])
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        replay = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+        plan.set_option(OPT_GRAPH, 0)
+        plan.set_option(OPT_TIMING, 1)
+        for w in range(warmup):
+            plan.execute(bufs[w % 2])
+        torch.cuda.synchronize()
+        plan.stage_times(reset=True)
+        for k in range(steps):
+            plan.execute(bufs[k % 2])
+        torch.cuda.synchronize()
+        stages, _ = plan.stage_times(reset=True)
+        plan.set_option(OPT_TIMING, 0)
+        plan.execute(xa)
+        recs, counts = plan.detect()
+        hits = tgt = fa = outside = 0
+        starts = np.searchsorted(recs["frame"], np.arange(nframes + 1))
+        for f, m in enumerate(metas):
+            sel = recs[starts[f]:starts[f + 1]]
+            D = len(m["shape"])
+            cells = np.ravel_multi_index(tuple(sel["idx"][:, d].astype(np.int64) for d in range(D)),
+                                         m["shape"]) if len(sel) else []
+            h, k, a, o = scoring.pd_pfa(cells, m["freqs"], m["shape"])
+            hits, tgt, fa, outside = hits + h, tgt + k, fa + a, outside + o
+        # records per compaction chunk (2^15 cells), the estimate's unit of work
+        D = len(metas[0]["shape"])
+        shapes = np.array([m["shape"] for m in metas], dtype=np.int64)
+        strides = np.cumprod(shapes[:, ::-1], axis=1)[:, ::-1]
+        strides = np.concatenate([strides[:, 1:], np.ones((nframes, 1), np.int64)], axis=1)
+        fr = recs["frame"].astype(np.int64)
+        flat = (recs["idx"][:, :D].astype(np.int64) * strides[fr]).sum(axis=1)
+        _, per_chunk = np.unique(fr * (1 << 40) + (flat >> 15), return_counts=True)
+        med = float(np.median(replay))
+        fold_gbs = (in_bytes + part_bytes) / (stages["fold"] * 1e-3) / 1e9
+        out[name] = {
+            "frames": nframes, "input_bytes": in_bytes,
+            "fold_launch": plan.info()["fold"],
+            "graph_replay_ms": {"p10": float(np.percentile(replay, 10)), "median": med,
+                                "p90": float(np.percentile(replay, 90))},
+            "frames_per_s": nframes / (med * 1e-3),
+            "input_gbs": in_bytes / (med * 1e-3) / 1e9,
+            "stage_ms": stages,
+            "fold_algorithmic_bytes": in_bytes + part_bytes,
+            "fold_gbs": fold_gbs, "fold_frac_of_peak": fold_gbs / HBM_PEAK_GBS,
+            "detections": int(counts.sum()),
+            "records_per_chunk": {"chunks": int(per_chunk.size), "max": int(per_chunk.max(initial=0)),
+                                  "mean": float(per_chunk.mean()) if per_chunk.size else 0.0,
+                                  "over_2048": int((per_chunk > 2048).sum())},
+            "pd": hits / max(tgt, 1), "pfa": fa / max(outside, 1),
+        }
+        log(f"  {med:.3f} ms per batch ({nframes / (med * 1e-3):.0f} frames/s), fold "
+            f"{stages['fold']:.3f} ms = {fold_gbs:.0f} GB/s, stages {stages}")
+        plan.close()
+        del xa, xb, bufs
+        torch.cuda.empty_cache()
+    return out
+
+
 def radar_section(dev, cpis=8, reps=10):
     """3-D RSFT on SRUR cubes (Table III: 32 RIs x 64 elements x 2048 range
     samples; Table IV targets, different-SNR setting), T = 4 bursts per CPI in
@@ -340,6 +466,9 @@ def main():
     ap.add_argument("--skip-comparators", action="store_true")
     ap.add_argument("--skip-refine", action="store_true")
     ap.add_argument("--skip-radar", action="store_true")
+    ap.add_argument("--workloads", nargs="?", const="all", default=None,
+                    help="also measure the other batched workloads (all, or a comma-separated "
+                         "list of names; adds about a minute)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the fold HBM-traffic summary from two rocprofv3 --pmc "
                          "CSV output folders (FETCH_SIZE, WRITE_SIZE) and exit; no GPU")
@@ -511,6 +640,9 @@ def main():
         out["refine"] = refine_section(dev)
     if not args.skip_radar:
         out["radar"] = radar_section(dev)
+    if args.workloads:
+        names = None if args.workloads == "all" else args.workloads.split(",")
+        out["workloads"] = workloads_section(dev, min(args.steps, 20), args.warmup, names)
 
     if not args.skip_cpu and args.cpu_sample > 0:
         n = min(args.cpu_sample, FRAMES)

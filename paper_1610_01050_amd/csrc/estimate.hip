@@ -132,7 +132,7 @@ __device__ __forceinline__ float neighbour_power(const EstFrame<D, M>& e, const 
   return median_of<M>(v);
 }
 
-// The same for D >= 3, from the permuted index u0[q][d] = [sigma c]_N of the
+// The same for D = 4, from the permuted index u0[q][d] = [sigma c]_N of the
 // cell itself (no array indexed at run time).
 template <int D, int M>
 __device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, const uint32_t (&u0)[M][D],
@@ -157,15 +157,15 @@ __device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, co
   return median_of<M>(v);
 }
 
-// One record. D <= 2: the 3^D neighbourhood lives in registers (loops
-// unrolled); D >= 3: its 27 or 81 values are kept in this thread's LDS
-// column `pcol` (stride kEstThreads) and visited by ordinary loops.
+// One record. D <= 3: the 3^D neighbourhood lives in registers (loops
+// unrolled); D = 4: its 81 values are kept in this thread's LDS column
+// `pcol` (stride kEstThreads) and visited by ordinary loops.
 template <int D, int M>
 __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int64_t f,
                                              unsigned long long flat, rsft_detection* out,
                                              float* pcol) {
   constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
-  constexpr bool kRegs = D <= 2;
+  constexpr bool kRegs = D <= 3;
   constexpr int kCentre = (kNb - 1) / 2;
   uint32_t cell[D];
 #pragma unroll
@@ -306,8 +306,12 @@ __device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc&
   }
 }
 
+// Waves per SIMD the register allocation aims at: five where the record's
+// registers fit in 96 VGPRs, fewer for the larger neighbourhoods.
+constexpr int est_waves(int D, int M) { return D <= 1 || (D == 2 && M <= 3) ? 5 : D == 2 ? 4 : 2; }
+
 template <int D, int M>
-__global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(5))) void compact_estimate_kernel(DevPtrs p, int T,
+__global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est_waves(D, M)))) void compact_estimate_kernel(DevPtrs p, int T,
                                                                        int64_t nframes,
                                                                        int max_cchunks,
                                                                        int xcd_groups) {
@@ -315,7 +319,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(5))
   __shared__ uint32_t list[kListMax];
   __shared__ uint32_t wsum[kEstThreads / 64];
   __shared__ rsft_detection stage[kEstThreads];
-  __shared__ float pbuf[D >= 3 ? kNb * kEstThreads : 1];
+  __shared__ float pbuf[D >= 4 ? kNb * kEstThreads : 1];
   int64_t f;
   int c;
   const int64_t b = blockIdx.x;
