@@ -157,6 +157,14 @@ __device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, co
   return median_of<M>(v);
 }
 
+// True when neighbour `code` differs from the cell in at most one dimension
+// (base-3 digits: 1 is offset 0).
+constexpr bool on_axis(int code, int D) {
+  int off = 0;
+  for (int dd = 0; dd < D; ++dd, code /= 3) off += code % 3 != 1;
+  return off <= 1;
+}
+
 // One record. D <= 3: the 3^D neighbourhood lives in registers (loops
 // unrolled); D = 4: its 81 values are kept in this thread's LDS column
 // `pcol` (stride kEstThreads) and visited by ordinary loops.
@@ -190,7 +198,27 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
 #pragma unroll
     for (int k = 0; k < 4; ++k) votes += int((wd[k] >> sh[k]) & 1u);
   }
+  // neighbour `code` against the cell: it must lie strictly below the cell's
+  // magnitude when its row-major index is lower, at most equal when higher
+  auto visit = [&](int code, float p0, float pc, bool& peak) {
+    unsigned long long nflat = 0ull;
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      const uint32_t nb = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
+      nflat |= (unsigned long long)nb << e.ns[dd];
+    }
+    if (nflat == flat) return;       // a dimension of length <= 2 wraps onto the cell
+    if (nflat < flat) {
+      if (!(p0 > pc)) peak = false;
+    } else {
+      if (!(p0 >= pc)) peak = false;
+    }
+  };
   float preg[kRegs ? kNb : 1];
+  bool peak = true;
   if constexpr (kRegs) {
     // Per round and dimension the three offsets o_d = -1, 0, 1 share one
     // permuted index, [sigma (c + o)]_N = [sigma c + sigma o]_N, so their
@@ -212,8 +240,21 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
         }
       }
     }
+    // The cell and its 2D axis neighbours first: they give the vertex, and
+    // most cells that are not peaks already lose to one of them. Only the
+    // lanes still in the running visit the other neighbours (the test is an
+    // AND over all of them, so the order does not change it).
 #pragma unroll
-    for (int code = 0; code < kNb; ++code) preg[code] = neighbour_power<D, M>(e, g, jb, code);
+    for (int code = 0; code < kNb; ++code)
+      if (on_axis(code, D)) preg[code] = neighbour_power<D, M>(e, g, jb, code);
+#pragma unroll
+    for (int code = 0; code < kNb; ++code)
+      if (code != kCentre && on_axis(code, D)) visit(code, preg[kCentre], preg[code], peak);
+    if (peak) {
+#pragma unroll
+      for (int code = 0; code < kNb; ++code)
+        if (!on_axis(code, D)) visit(code, preg[kCentre], neighbour_power<D, M>(e, g, jb, code), peak);
+    }
   } else {
     uint32_t u0[M][D];
 #pragma unroll
@@ -223,39 +264,16 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
     }
 #pragma unroll 1
     for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_dyn<D, M>(e, u0, code);
+    const float pc0 = pcol[kCentre * kEstThreads];
+#pragma unroll 1
+    for (int code = 0; code < kNb; ++code)
+      if (code != kCentre) visit(code, pc0, pcol[code * kEstThreads], peak);
   }
   auto P = [&](int code) -> float {
     if constexpr (kRegs) return preg[code];
     else return pcol[code * kEstThreads];
   };
   const float p0 = P(kCentre);
-  bool peak = true;
-  auto visit = [&](int code) {
-    if (code == kCentre) return;
-    unsigned long long nflat = 0ull;
-    int c = code;
-#pragma unroll
-    for (int dd = D - 1; dd >= 0; --dd) {
-      const int o = c % 3 - 1;
-      c /= 3;
-      const uint32_t nb = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
-      nflat |= (unsigned long long)nb << e.ns[dd];
-    }
-    if (nflat == flat) return;       // a dimension of length <= 2 wraps onto the cell
-    const float pc = P(code);
-    if (nflat < flat) {
-      if (!(p0 > pc)) peak = false;
-    } else {
-      if (!(p0 >= pc)) peak = false;
-    }
-  };
-  if constexpr (kRegs) {
-#pragma unroll
-    for (int code = 0; code < kNb; ++code) visit(code);
-  } else {
-#pragma unroll 1
-    for (int code = 0; code < kNb; ++code) visit(code);
-  }
   rsft_detection rec;
   rec.frame = f;
 #pragma unroll
@@ -310,6 +328,21 @@ __device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc&
 // registers fit in 96 VGPRs, fewer for the larger neighbourhoods.
 constexpr int est_waves(int D, int M) { return D <= 1 || (D == 2 && M <= 3) ? 5 : D == 2 ? 4 : 2; }
 
+// estimate_list for a frame of `ne` estimation rounds, 1 <= ne <= MMAX.
+template <int D, int MMAX>
+__device__ __forceinline__ void estimate_list_n(int ne, const DevPtrs& p, const FrameDesc& d, int64_t f,
+                                                int64_t rel, int T, const uint32_t* list, int n,
+                                                unsigned long long cell0, rsft_detection* out,
+                                                int64_t room, float* pcol, rsft_detection* stage) {
+  switch (ne) {
+    case 1: if constexpr (MMAX >= 1) estimate_list<D, 1>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
+    case 2: if constexpr (MMAX >= 2) estimate_list<D, 2>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
+    case 3: if constexpr (MMAX >= 3) estimate_list<D, 3>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
+    case 4: if constexpr (MMAX >= 4) estimate_list<D, 4>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
+    default: if constexpr (MMAX >= 5) estimate_list<D, 5>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
+  }
+}
+
 template <int D, int M>
 __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est_waves(D, M)))) void compact_estimate_kernel(DevPtrs p, int T,
                                                                        int64_t nframes,
@@ -337,7 +370,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
   // each loaded together before they are tested (no chain of dependent
   // loads behind early exits).
   const int cch = d.cchunks, nd = d.ndim, ne = d.n_est;
-  if ((c >= cch) | (nd != D) | (ne != M)) return;
+  if ((c >= cch) | (nd != D) | (ne < 1) | (ne > M)) return;
   const int64_t rel = rel_of(p, f);
   const int64_t ck = d.chunk_off + rel * d.chunk_stride + c;
   const int64_t cap = d.cap;
@@ -395,7 +428,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
       }
     }
     __syncthreads();
-    estimate_list<D, M>(p, d, f, rel, T, list, min(total, kListMax), cell0, out, room0, pcol, stage);
+    estimate_list_n<D, M>(ne, p, d, f, rel, T, list, min(total, kListMax), cell0, out, room0, pcol, stage);
     return;
   }
   // dense chunk: passes of kListMax / 32 words (at most kListMax cells each)
@@ -426,7 +459,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
       list[k++] = (uint32_t(w - w0) << 5) | uint32_t(bit);
     }
     __syncthreads();
-    estimate_list<D, M>(p, d, f, rel, T, list, total, cell0, out + running, room0 - running, pcol,
+    estimate_list_n<D, M>(ne, p, d, f, rel, T, list, total, cell0, out + running, room0 - running, pcol,
                         stage);
     running += total;
     if (running >= room0) return;   // uniform: the frame's capacity is used up
@@ -434,14 +467,17 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
   }
 }
 
+// One launch per dimension count, built for the most estimation rounds any
+// frame of the plan uses: uneven plans mix frames of 1..M rounds (sigma per
+// frame), and one grid serves them all.
 template <int D>
 static void launch_estimate_d(const DevPtrs& p, dim3 grid, hipStream_t st, int T, int64_t nframes,
                               int max_cchunks, int xcd, int est_mask) {
-  if (est_mask & 2) hipLaunchKernelGGL((compact_estimate_kernel<D, 1>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
-  if (est_mask & 4) hipLaunchKernelGGL((compact_estimate_kernel<D, 2>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
-  if (est_mask & 8) hipLaunchKernelGGL((compact_estimate_kernel<D, 3>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
-  if (est_mask & 16) hipLaunchKernelGGL((compact_estimate_kernel<D, 4>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
-  if (est_mask & 32) hipLaunchKernelGGL((compact_estimate_kernel<D, 5>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  if (est_mask >= 32) hipLaunchKernelGGL((compact_estimate_kernel<D, 5>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  else if (est_mask >= 16) hipLaunchKernelGGL((compact_estimate_kernel<D, 4>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  else if (est_mask >= 8) hipLaunchKernelGGL((compact_estimate_kernel<D, 3>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  else if (est_mask >= 4) hipLaunchKernelGGL((compact_estimate_kernel<D, 2>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+  else if (est_mask >= 2) hipLaunchKernelGGL((compact_estimate_kernel<D, 1>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
 }
 
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
