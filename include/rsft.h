@@ -173,11 +173,11 @@ typedef struct {
   double max_sparsity;       /* B / eta_m: by Remark 2 (Sec. IV-C) RSFT fails for
                                 K >= this many tones, whatever their SNR */
   uint64_t estimation_rounds; /* bit s set: round s feeds magnitude estimates */
-  /* plan-wide launch shape of the fold stage (see rsft_autotune) */
-  int32_t fold_threads;      /* work-group size */
-  int32_t fold_vec;          /* complex samples per thread per row */
-  int32_t fold_nontemporal;  /* 1: non-temporal input loads */
-  int32_t reserved2;
+  /* plan-wide launch shapes (see rsft_autotune) */
+  int32_t fold_threads;      /* fold: work-group size */
+  int32_t fold_vec;          /* fold: complex samples per thread per row */
+  int32_t fold_nontemporal;  /* fold: 1 = non-temporal input loads */
+  int32_t estimate_workers;  /* compact/estimate: 1 = overflow workers */
 } rsft_plan_info_t;
 
 typedef struct rsft_plan_s* rsft_plan_t;
@@ -212,13 +212,18 @@ rsft_status rsft_execute(rsft_plan_t plan, const void* d_input, int64_t batch,
                          void* stream);
 
 /*
- * Choose the launch shape of the fold stage (the HBM-bound stage) by timing:
- * work-group size (256 / 512 threads), samples per thread (4 / 2) and
- * ordinary vs non-temporal input loads are each run `repeats` times
- * (<= 0: 5) on d_input (same contract as rsft_execute) with
- * hipEvents on `stream`; the fastest becomes the plan's shape (reported by
- * rsft_plan_info) and *best_ms (may be NULL) its average duration.
- * Synchronizes the stream; the plan's detection results are unaffected.
+ * Choose the plan's launch shapes by timing them on d_input (same contract
+ * as rsft_execute) with hipEvents on `stream`, `repeats` runs each (<= 0: 5):
+ * - fold stage (the HBM-bound stage): work-group size (256 / 512 threads),
+ *   samples per thread (4 / 2), ordinary vs non-temporal input loads; the
+ *   fastest is kept and *best_ms (may be NULL) gets its average duration;
+ * - compact/estimate: without or with overflow workers (the records of
+ *   chunks holding more than 1024 detections shared among extra work-
+ *   groups); the workers are kept when at least 3% faster. How dense the
+ *   detections are depends on the data, hence timing on the caller's input.
+ * Both choices are reported by rsft_plan_info and leave the results
+ * unchanged (bit for bit for the estimate layout). Synchronizes the stream;
+ * afterwards the plan holds the results of an execute of d_input.
  * Errors: as rsft_execute.
  */
 rsft_status rsft_autotune(rsft_plan_t plan, const void* d_input, int64_t batch, void* stream,
@@ -346,7 +351,11 @@ enum {
      input loads 0 | 1 */
   RSFT_OPT_FOLD_THREADS = 2,
   RSFT_OPT_FOLD_VEC = 3,
-  RSFT_OPT_FOLD_NONTEMPORAL = 4
+  RSFT_OPT_FOLD_NONTEMPORAL = 4,
+  /* compact/estimate layout (what rsft_autotune chooses): 0 = one work-group
+     per compaction chunk builds all of its records; 1 = it builds the first
+     1024 and overflow workers the rest. Same records either way. Default 0. */
+  RSFT_OPT_ESTIMATE_WORKERS = 5
 };
 rsft_status rsft_set_option(rsft_plan_t plan, int32_t option, int64_t value);
 

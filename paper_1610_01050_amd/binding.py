@@ -31,6 +31,7 @@ C64, C128 = 0, 1
 NOISE_KNOWN, NOISE_ESTIMATED = 0, 1
 OPT_GRAPH, OPT_TIMING = 0, 1
 OPT_FOLD_THREADS, OPT_FOLD_VEC, OPT_FOLD_NONTEMPORAL = 2, 3, 4
+OPT_ESTIMATE_WORKERS = 5
 STAGES = ("fold", "dft", "vote", "estimate")
 
 # Every symbol include/rsft.h declares.
@@ -114,7 +115,7 @@ class PlanInfo(ctypes.Structure):
         ("max_sparsity", ctypes.c_double),
         ("estimation_rounds", ctypes.c_uint64),
         ("fold_threads", ctypes.c_int32), ("fold_vec", ctypes.c_int32),
-        ("fold_nontemporal", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+        ("fold_nontemporal", ctypes.c_int32), ("estimate_workers", ctypes.c_int32),
     ]
 
 
@@ -367,8 +368,10 @@ class Plan:
         self.last_batch = int(batch)
 
     def autotune(self, x, batch=None, repeats=5, stream=None):
-        """Time the fold stage's launch shapes on `x` and keep the fastest;
-        returns its average duration in ms."""
+        """Time the fold stage's launch shapes and the two compact/estimate
+        layouts on `x` and keep the fastest (rsft_autotune); returns the
+        fold's average duration in ms. The plan then holds the results of an
+        execute of `x`."""
         if batch is None:
             batch = x.shape[0] if self.uniform else len(self.descs)
         self._check_input(x, batch)
@@ -465,6 +468,7 @@ class Plan:
             "estimation_rounds": [s for s in range(T) if (out.estimation_rounds >> s) & 1],
             "fold": {"threads": out.fold_threads, "vec": out.fold_vec,
                      "nontemporal": out.fold_nontemporal},
+            "estimate_workers": out.estimate_workers,
         }
 
     # -- bucketized forward model of complex tones (off-grid refinement) --

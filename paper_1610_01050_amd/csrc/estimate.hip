@@ -6,9 +6,15 @@ namespace rsft {
 
 // ---------------------------------------------------------------------------
 // compact + estimate: one work-group per (frame, compaction chunk of 2^15
-// cells). It reads the chunk's bitmap words in row-major order, lists the
-// detected cells in LDS (popcount + block prefix sum) and gives each cell its
-// rank in the frame's record range; then every listed cell gets its record:
+// cells) builds all of the chunk's records. Where dense chunks would keep
+// single work-groups busy for long, the plan can add overflow workers
+// instead (split_estimate_kernel): a chunk's work-group builds its first
+// kChunkRecords records and the workers the rest, in items of 2^kItemShift
+// records listed by the scan. (The workers' code, compiled into a kernel,
+// slows its chunk path, so the plan picks the layout that is faster on its
+// data; see rsft_autotune.) A work-group reads the chunk's bitmap words in
+// row-major order, lists the detected cells of its rank range in LDS
+// (popcount + block prefix sum), and every listed cell gets its record:
 // votes recounted from the flags, gain-corrected magnitude (median over the
 // estimation rounds of |fhat_s[M(i, sigma_s)]| times the inverse flat-window
 // response at the cell's offset inside its bucket), a peak test against the
@@ -23,13 +29,12 @@ namespace rsft {
 // which is taken on the square roots. FP32 magnitudes, FP64 vertex and
 // frequency.
 //
-// With at least 16 frames, block b serves frames congruent to b mod 8: work-
-// groups are dealt to the eight XCDs round-robin, so each XCD's L2 holds the
-// buckets and flags of only its own frames.
+// With at least 16 frames, chunk work-group b serves frames congruent to b
+// mod 8: work-groups are dealt to the eight XCDs round-robin, so each XCD's
+// L2 holds the buckets and flags of only its own frames.
 // ---------------------------------------------------------------------------
 
 constexpr int kEstThreads = 256;
-constexpr int kListMax = 2048;   // cells listed at once: a chunk's, else one pass's
 
 // Per-frame constants of the estimate, uniform across the work-group.
 template <int D, int M>
@@ -325,8 +330,11 @@ __device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc&
 }
 
 // Waves per SIMD the register allocation aims at: five where the record's
-// registers fit in 96 VGPRs, fewer for the larger neighbourhoods.
-constexpr int est_waves(int D, int M) { return D <= 1 || (D == 2 && M <= 3) ? 5 : D == 2 ? 4 : 2; }
+// registers fit in 96 VGPRs, fewer for the larger neighbourhoods (D = 4 keeps
+// its neighbourhood in 81 KB of LDS: one work-group per compute unit).
+constexpr int est_waves(int D, int M) {
+  return D <= 1 || (D == 2 && M <= 3) ? 5 : D == 2 ? 4 : D == 3 ? 2 : 1;
+}
 
 // estimate_list for a frame of `ne` estimation rounds, 1 <= ne <= MMAX.
 template <int D, int MMAX>
@@ -342,6 +350,92 @@ __device__ __forceinline__ void estimate_list_n(int ne, const DevPtrs& p, const 
     default: if constexpr (MMAX >= 5) estimate_list<D, 5>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
   }
 }
+
+// The largest index i in [0, n) with a[i] <= t, for a non-decreasing array
+// with a[0] <= t: a 64-way search by one wave (each step loads 64 entries
+// and narrows the range 64-fold). Every wave of the work-group runs it and
+// gets the same answer.
+__device__ __forceinline__ int64_t wave_search(const int64_t* __restrict__ a, int64_t n, int64_t t) {
+  const int lane = threadIdx.x & 63;
+  int64_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + 63) >> 6;
+    const int64_t i = lo + int64_t(lane) * step;
+    const bool ok = i < hi && a[i] <= t;
+    const unsigned long long m = __ballot(ok);        // lanes 0..k (lane 0 holds a[lo] <= t)
+    if (m == 0ull) break;                              // only if a[lo] > t: keep lo
+    const int k = 63 - __clzll(m);
+    lo += int64_t(k) * step;
+    hi = min(lo + step, hi);
+  }
+  return lo;
+}
+
+// Records of ranks r_lo .. r_lo + n - 1 of chunk c of frame f: the work-group
+// lists those detected cells from the chunk's bitmap words wv (kWpt per
+// thread; popcounts and a block prefix sum) and builds their records.
+template <int D, int M, int kWpt>
+__device__ __forceinline__ void build_range(const DevPtrs& p, int T, const FrameDesc& d, int64_t f, int c,
+                                            const uint32_t (&wv)[kWpt], int r_lo, int n, int64_t rank0,
+                                            uint32_t* list, uint32_t* wsum, rsft_detection* stage,
+                                            float* pcol) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int pc = 0;
+#pragma unroll
+  for (int q = 0; q < kWpt; ++q) pc += __popc(wv[q]);
+  int incl = pc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wave] = uint32_t(incl);
+  __syncthreads();
+  int r = incl - pc;                                 // chunk rank of this thread's first cell
+#pragma unroll
+  for (int q = 0; q < kEstThreads / 64; ++q)
+    if (q < wave) r += int(wsum[q]);
+  if (r < r_lo + n && r + pc > r_lo) {
+#pragma unroll
+    for (int q = 0; q < kWpt; ++q) {
+      uint32_t word = wv[q];
+      const uint32_t wrel = uint32_t(tid * kWpt + q) << 5;
+      while (word) {
+        const int bit = __ffs(word) - 1;
+        word &= word - 1u;
+        if (r >= r_lo && r < r_lo + n) list[r - r_lo] = wrel | uint32_t(bit);
+        ++r;
+      }
+    }
+  }
+  __syncthreads();
+  estimate_list_n<D, M>(d.n_est, p, d, f, rel_of(p, f), T, list, n, (unsigned long long)c << kCompactShift,
+                        p.records + p.offsets[f] + rank0 + r_lo, n, pcol, stage);
+}
+
+constexpr int kWordsPerThread = (1 << (kCompactShift - 5)) / kEstThreads;   // a chunk's bitmap words
+
+// Chunk (frame f, chunk c) of work-group b of the chunk grid; false when b
+// lies past the batch.
+__device__ __forceinline__ bool chunk_of(int64_t b, int64_t nframes, int max_cchunks, int xcd_groups,
+                                         int64_t& f, int& c) {
+  if (xcd_groups) {
+    const int64_t k = b >> 3;
+    f = (k / max_cchunks) * 8 + (b & 7);
+    c = int(k % max_cchunks);
+  } else {
+    f = b / max_cchunks;
+    c = int(b % max_cchunks);
+  }
+  return f < nframes;
+}
+
+// Without overflow workers: one work-group per (frame, chunk) builds all of
+// the chunk's records; a chunk of up to kListMax detections is listed in one
+// pass, a denser one in passes of kListMax cells.
+constexpr int kListMax = 2048;   // cells listed at once: a chunk's, else one pass's
 
 template <int D, int M>
 __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est_waves(D, M)))) void compact_estimate_kernel(DevPtrs p, int T,
@@ -467,32 +561,143 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
   }
 }
 
-// One launch per dimension count, built for the most estimation rounds any
-// frame of the plan uses: uneven plans mix frames of 1..M rounds (sigma per
-// frame), and one grid serves them all.
+// With overflow workers: work-group b of the first `og` (dispatched first)
+// takes a contiguous range of the overflow items the scan listed
+// (consecutive ranges on one XCD); item i of a frame lies in the chunk whose
+// running item sum is the largest not above i, and covers the chunk's ranks
+// kChunkRecords + 2^kItemShift k ... for the chunk's k-th item. Every other
+// work-group owns one chunk and its ranks 0 .. kChunkRecords - 1. One record
+// builder serves both.
+template <int D, int M>
+__global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est_waves(D, M)))) void split_estimate_kernel(DevPtrs p, int T,
+                                                                     int64_t nframes,
+                                                                     int max_cchunks,
+                                                                     int xcd_groups,
+                                                                     int og) {
+  constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
+  constexpr int kItem = 1 << kItemShift;
+  constexpr int kWpt = kWordsPerThread;
+  __shared__ uint32_t list[kChunkRecords];
+  __shared__ uint32_t wsum[kEstThreads / 64];
+  __shared__ rsft_detection stage[kEstThreads];
+  __shared__ float pbuf[D >= 4 ? kNb * kEstThreads : 1];
+  const int tid = threadIdx.x;
+  const bool worker = int64_t(blockIdx.x) < og;
+  int64_t f = 0, i = 0, hi = 0, fbeg = 0, fend = 0;
+  int c = 0;
+  if (worker) {
+    const int64_t total = p.item_offsets[nframes];
+    const int64_t b = blockIdx.x;
+    const int64_t v = (og & 7) == 0 ? (b & 7) * (og >> 3) + (b >> 3) : b;
+    i = total * v / og;
+    hi = total * (v + 1) / og;
+  } else if (!chunk_of(int64_t(blockIdx.x) - og, nframes, max_cchunks, xcd_groups, f, c)) {
+    return;
+  }
+  for (;;) {
+    // the next record range: frame f, chunk c, ranks r_lo .. r_lo + n - 1
+    const FrameDesc* dp;
+    uint32_t wv[kWpt];
+    int r_lo, n;
+    int64_t rank0;
+    if (worker) {
+      if (i >= hi) return;
+      if (i >= fend) {
+        f = wave_search(p.item_offsets, nframes + 1, i);
+        if (f >= nframes) return;                      // i < total keeps f < nframes
+        fbeg = p.item_offsets[f];
+        fend = p.item_offsets[f + 1];
+        if (fend <= i) return;                         // item_offsets is non-decreasing
+        const FrameDesc& d = desc_of(p, f);
+        if ((d.ndim != D) | (d.n_est < 1) | (d.n_est > M)) {   // another launch's frame
+          i = fend;
+          continue;
+        }
+      }
+      dp = &desc_of(p, f);
+      const int64_t rel = rel_of(p, f);
+      const int64_t ck0 = dp->chunk_off + rel * dp->chunk_stride;
+      const int64_t* ci = p.chunk_items + ck0;
+      const int64_t j = i - fbeg;
+      c = int(wave_search(ci, dp->cchunks, j));
+      r_lo = kChunkRecords + int((j - ci[c]) << kItemShift);
+      const uint32_t count = p.chunk_counts[ck0 + c];
+      rank0 = p.chunk_offsets[ck0 + c];
+      const uint32_t* bm = p.bitmap + dp->bitmap_off + rel * dp->bitmap_stride;
+      const int w0 = c << (kCompactShift - 5);
+      const int bw = dp->bitmap_words;
+#pragma unroll
+      for (int q = 0; q < kWpt; ++q) {
+        const int w = w0 + tid * kWpt + q;
+        wv[q] = w < bw ? bm[w] : 0u;
+      }
+      n = int(min(min(int64_t(count) - r_lo, int64_t(dp->cap) - rank0 - r_lo), int64_t(kItem)));
+      ++i;
+    } else {
+      dp = &desc_of(p, f);
+      const int cch = dp->cchunks, nd = dp->ndim, ne = dp->n_est;
+      if ((c >= cch) | (nd != D) | (ne < 1) | (ne > M)) return;
+      const int64_t rel = rel_of(p, f);
+      const int64_t ck = dp->chunk_off + rel * dp->chunk_stride + c;
+      const uint32_t* bm = p.bitmap + dp->bitmap_off + rel * dp->bitmap_stride;
+      const int w0 = c << (kCompactShift - 5);
+      const int bw = dp->bitmap_words;
+#pragma unroll
+      for (int q = 0; q < kWpt; ++q) {
+        const int w = w0 + tid * kWpt + q;
+        wv[q] = w < bw ? bm[w] : 0u;
+      }
+      const uint32_t count = p.chunk_counts[ck];
+      rank0 = p.chunk_offsets[ck];
+      const int64_t cap = dp->cap;
+      if ((count == 0u) | (rank0 >= cap)) return;
+      r_lo = 0;
+      n = int(min(min(int64_t(count), cap - rank0), int64_t(kChunkRecords)));
+    }
+    build_range<D, M, kWpt>(p, T, *dp, f, c, wv, r_lo, n, rank0, list, wsum, stage, pbuf + tid);
+    if (!worker) return;
+  }
+}
+
+// Per dimension count, one kernel built for the most estimation rounds any
+// frame of the plan uses (uneven plans mix frames of 1..M rounds, sigma per
+// frame).
 template <int D>
-static void launch_estimate_d(const DevPtrs& p, dim3 grid, hipStream_t st, int T, int64_t nframes,
+static void launch_estimate_d(const DevPtrs& p, dim3 grid, int og, hipStream_t st, int T, int64_t nframes,
                               int max_cchunks, int xcd, int est_mask) {
-  if (est_mask >= 32) hipLaunchKernelGGL((compact_estimate_kernel<D, 5>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
-  else if (est_mask >= 16) hipLaunchKernelGGL((compact_estimate_kernel<D, 4>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
-  else if (est_mask >= 8) hipLaunchKernelGGL((compact_estimate_kernel<D, 3>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
-  else if (est_mask >= 4) hipLaunchKernelGGL((compact_estimate_kernel<D, 2>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
-  else if (est_mask >= 2) hipLaunchKernelGGL((compact_estimate_kernel<D, 1>), grid, dim3(kEstThreads), 0, st, p, T, nframes, max_cchunks, xcd);
+#define RSFT_EST(M)                                                                                      \
+  do {                                                                                                   \
+    if (og > 0)                                                                                          \
+      hipLaunchKernelGGL((split_estimate_kernel<D, M>), grid, dim3(kEstThreads), 0, st, p, T, nframes,    \
+                         max_cchunks, xcd, og);                                                          \
+    else                                                                                                 \
+      hipLaunchKernelGGL((compact_estimate_kernel<D, M>), grid, dim3(kEstThreads), 0, st, p, T, nframes,  \
+                         max_cchunks, xcd);                                                              \
+  } while (0)
+  if (est_mask >= 32) RSFT_EST(5);
+  else if (est_mask >= 16) RSFT_EST(4);
+  else if (est_mask >= 8) RSFT_EST(3);
+  else if (est_mask >= 4) RSFT_EST(2);
+  else if (est_mask >= 2) RSFT_EST(1);
+#undef RSFT_EST
 }
 
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
-                    int est_mask, void* stream) {
+                    int est_mask, int workers, int num_cus, void* stream) {
   if (nframes <= 0) return hipSuccess;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int xcd = nframes >= 16 ? 1 : 0;
   const int64_t rows = xcd ? ((nframes + 7) / 8) * 8 : nframes;
-  const int64_t blocks = rows * int64_t(max_cchunks);
+  // overflow workers: two per compute unit, a multiple of 8 so that the
+  // chunk work-groups after them keep their XCD assignment
+  const int og = workers ? ((2 * (num_cus > 0 ? num_cus : 256)) + 7) / 8 * 8 : 0;
+  const int64_t blocks = og + rows * int64_t(max_cchunks);
   if (blocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
   const dim3 grid{unsigned(blocks), 1u, 1u};
-  if (dims_mask & 1) launch_estimate_d<1>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
-  if (dims_mask & 2) launch_estimate_d<2>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
-  if (dims_mask & 4) launch_estimate_d<3>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
-  if (dims_mask & 8) launch_estimate_d<4>(p, grid, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 1) launch_estimate_d<1>(p, grid, og, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 2) launch_estimate_d<2>(p, grid, og, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 4) launch_estimate_d<3>(p, grid, og, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 8) launch_estimate_d<4>(p, grid, og, st, T, nframes, max_cchunks, xcd, est_mask);
   return hipGetLastError();
 }
 

@@ -79,13 +79,15 @@ struct rsft_plan_s {
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles;
   DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
-      d_offsets, d_records, d_scan_done;
+      d_offsets, d_records, d_scan_done, d_chunk_items, d_item_counts, d_item_offsets;
   rsft::DevPtrs ptrs{};
   // state of the last execute
   int64_t last_batch = -1;
   // graph replay
   bool use_graph = true;
   hipStream_t capture_stream = nullptr;
+  // estimate layout: 1 adds overflow workers for dense chunks (rsft_autotune)
+  int est_workers = 0;
   std::map<std::pair<const void*, int64_t>, hipGraphExec_t> graphs;
   std::vector<std::pair<const void*, int64_t>> graph_order;
   // stage timing
@@ -417,7 +419,7 @@ void free_plan(rsft_plan_s* pl) {
                           &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_part,
                           &pl->d_buckets, &pl->d_powers, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
-                          &pl->d_scan_done};
+                          &pl->d_scan_done, &pl->d_chunk_items, &pl->d_item_counts, &pl->d_item_offsets};
   for (auto* b : bufs) release(*b);
   delete pl;
 }
@@ -549,6 +551,9 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = alloc(pl->d_chunk_offsets, size_t(chunk_off) * sizeof(int64_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_counts, size_t(pl->max_frames) * sizeof(int64_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_offsets, size_t(pl->max_frames + 1) * sizeof(int64_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_chunk_items, size_t(chunk_off) * sizeof(int64_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_item_counts, size_t(pl->max_frames) * sizeof(int64_t))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_item_offsets, size_t(pl->max_frames + 1) * sizeof(int64_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_records, size_t(rec_total) * sizeof(rsft_detection))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_scan_done, sizeof(uint32_t))) != RSFT_OK) return st;
   HIP_TRY(hipMemset(pl->d_scan_done.ptr, 0, sizeof(uint32_t)));   // the scan keeps it 0 between launches
@@ -573,6 +578,9 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.chunk_offsets = static_cast<int64_t*>(pl->d_chunk_offsets.ptr);
   q.counts = static_cast<int64_t*>(pl->d_counts.ptr);
   q.offsets = static_cast<int64_t*>(pl->d_offsets.ptr);
+  q.chunk_items = static_cast<int64_t*>(pl->d_chunk_items.ptr);
+  q.item_counts = static_cast<int64_t*>(pl->d_item_counts.ptr);
+  q.item_offsets = static_cast<int64_t*>(pl->d_item_offsets.ptr);
   q.records = static_cast<rsft_detection*>(pl->d_records.ptr);
   q.scan_done = static_cast<uint32_t*>(pl->d_scan_done.ptr);
   q.tiles = static_cast<const int32_t*>(pl->d_tiles.ptr);
@@ -619,6 +627,15 @@ void drop_graphs(rsft_plan_s* pl) {
   pl->graph_order.clear();
 }
 
+// scan + compact/estimate, in the plan's estimate layout
+rsft_status estimate_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
+  const auto& q = pl->ptrs;
+  LAUNCH_TRY(rsft::launch_scan(q, batch, pl->est_workers, st));
+  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask,
+                                   pl->est_workers, pl->num_cus, st));
+  return RSFT_OK;
+}
+
 // The hot path, stage by stage; `ev` (optional) brackets the stages.
 rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStream_t st,
                     hipEvent_t* ev) {
@@ -633,8 +650,10 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, st));
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
-  LAUNCH_TRY(rsft::launch_scan(q, batch, st));
-  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask, st));
+  {
+    const rsft_status es = estimate_stage(pl, batch, st);
+    if (es != RSFT_OK) return es;
+  }
   if (ev) HIP_TRY(hipEventRecord(ev[4], st));
   return RSFT_OK;
 }
@@ -783,6 +802,24 @@ rsft_status rsft_autotune(rsft_plan_t pl, const void* d_input, int64_t batch, vo
       }
   if (st != RSFT_OK) return st;
   pl->fold = best;
+  // estimate layout: one execute of d_input leaves its flags and detected-
+  // cell bitmap; scan + compact/estimate (which only read those) are then
+  // timed without and with overflow workers. Dense chunks favour the
+  // workers; the workers are kept only when clearly faster.
+  if ((st = enqueue(pl, d_input, batch, s, nullptr)) != RSFT_OK) return st;
+  pl->last_batch = batch;
+  float est_ms[2] = {0.f, 0.f};
+  for (int w = 0; w < 2; ++w) {
+    pl->est_workers = w;
+    if ((st = estimate_stage(pl, batch, s)) != RSFT_OK) return st;
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < repeats && st == RSFT_OK; ++r) st = estimate_stage(pl, batch, s);
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    if (st != RSFT_OK) return st;
+    HIP_TRY(hipEventElapsedTime(&est_ms[w], e0, e1));
+  }
+  pl->est_workers = est_ms[1] < 0.97f * est_ms[0] ? 1 : 0;
   drop_graphs(pl);   // captured graphs hold the previous launch shape
   if (best_ms) *best_ms = double(best_t);
   return RSFT_OK;
@@ -802,8 +839,8 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
     LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, int(f), s));
   }
   if (batch > 0) {
-    LAUNCH_TRY(rsft::launch_scan(q, batch, s));
-    LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask, s));
+    const rsft_status es = estimate_stage(pl, batch, s);
+    if (es != RSFT_OK) return es;
   }
   return RSFT_OK;
 }
@@ -882,9 +919,7 @@ rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* strea
   HIP_TRY(hipMemcpyAsync(pl->d_flags.ptr, d_flags, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   const auto& q = pl->ptrs;
   LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, s));
-  LAUNCH_TRY(rsft::launch_scan(q, batch, s));
-  LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask, s));
-  return RSFT_OK;
+  return estimate_stage(pl, batch, s);
 }
 
 rsft_status rsft_detection_count(rsft_plan_t pl, void* stream, int64_t* total) {
@@ -957,6 +992,7 @@ rsft_status rsft_plan_info(rsft_plan_t pl, int64_t frame, rsft_plan_info_t* out)
   out->fold_threads = pl->fold.threads;
   out->fold_vec = pl->fold.vec;
   out->fold_nontemporal = pl->fold.nontemporal;
+  out->estimate_workers = pl->est_workers;
   return RSFT_OK;
 }
 
@@ -978,6 +1014,10 @@ rsft_status rsft_set_option(rsft_plan_t pl, int32_t option, int64_t value) {
       return RSFT_OK;
     case RSFT_OPT_FOLD_NONTEMPORAL:
       pl->fold.nontemporal = value != 0 ? 1 : 0;
+      drop_graphs(pl);
+      return RSFT_OK;
+    case RSFT_OPT_ESTIMATE_WORKERS:
+      pl->est_workers = value != 0 ? 1 : 0;
       drop_graphs(pl);
       return RSFT_OK;
     default: return fail(RSFT_ERROR_INVALID_ARGUMENT, "unknown option");

@@ -14,6 +14,9 @@ constexpr int kMaxLastBuckets = 4096;     // B_{D-1} (fold stage residue slots p
 constexpr int kMaxDetectionsPerFrame = 1 << 24;
 constexpr int kDefaultDetections = 16384;
 constexpr int kCompactShift = 15;         // cells per compaction chunk = 2^15
+constexpr int kChunkRecords = 1024;       // records a chunk's work-group builds at a time (and,
+                                          // with overflow workers, in all)
+constexpr int kItemShift = 8;             // records per overflow item = 2^8
 constexpr int kMaxEstRounds = 5;          // rounds feeding a magnitude estimate
 constexpr int kFoldRoundGroup = 4;        // rounds folded per pass over the input
 
@@ -87,6 +90,12 @@ struct DevPtrs {
   int64_t* chunk_offsets;      // rank of a chunk's first detection within its frame
   int64_t* counts;             // [frames] exact detections per frame
   int64_t* offsets;            // [frames + 1] first record of each frame
+  // overflow work list of the estimate: the records of a chunk beyond its
+  // first kChunkRecords (and within the frame's capacity) form items of up to
+  // 2^kItemShift consecutive records
+  int64_t* chunk_items;        // items of a frame before a chunk (chunk layout)
+  int64_t* item_counts;        // [frames] items per frame
+  int64_t* item_offsets;       // [frames + 1] first item of each frame
   uint32_t* scan_done;         // frames finished by the scan (0 between launches)
   rsft_detection* records;
   const int32_t* tiles;        // uneven plans: [ntiles][3] (frame, class, chunk)
@@ -108,10 +117,12 @@ int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int
                int identity_relabel, int nchunks_override, void* stream);
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
                 int max_words, int dims_mask, int rows_ok, int frame0, void* stream);
-int launch_scan(const DevPtrs& p, int64_t nframes, void* stream);
+// items: 1 also lists the estimate's overflow items (plans with overflow workers)
+int launch_scan(const DevPtrs& p, int64_t nframes, int items, void* stream);
 // est_mask: bit m set when some frame uses m estimation rounds (1..5)
+// workers: 1 adds overflow workers (two per compute unit of the num_cus)
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
-                    int est_mask, void* stream);
+                    int est_mask, int workers, int num_cus, void* stream);
 // Per-frame comparator path.
 int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t frame,
                       int round, int B, void* stream);

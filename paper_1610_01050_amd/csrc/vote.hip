@@ -281,10 +281,16 @@ int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunk
 // ---------------------------------------------------------------------------
 // scan: one work-group per frame turns the frame's chunk counters into
 // chunk_offsets (rank of each compaction chunk's first detection in its
-// frame, a running sum in row-major cell order) and counts[f]. The last
-// work-group to finish (a device-scope counter, released and acquired with
-// fences) computes offsets[f] = sum_{g<f} min(count_g, cap_g),
-// offsets[nframes] = total, and resets the counter for the next launch.
+// frame, a running sum in row-major cell order) and counts[f]. For plans
+// with overflow workers it also lists their work: the records of a chunk
+// beyond its first
+// kChunkRecords that fit the frame's capacity form ceil(over / 2^kItemShift)
+// items; chunk_items holds the running sum of items over the frame's chunks,
+// item_counts[f] the frame's total. The last work-group to finish (a
+// device-scope counter, released and acquired with fences) computes
+// offsets[f] = sum_{g<f} min(count_g, cap_g) and item_offsets[f] =
+// sum_{g<f} item_counts[g] (entry nframes holds the totals), and resets the
+// counter for the next launch.
 // ---------------------------------------------------------------------------
 
 constexpr int kScanThreads = 256;
@@ -312,7 +318,7 @@ __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wtot
   return pre + incl;
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t nframes) {
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t nframes, int items) {
   __shared__ int64_t wtot[kScanThreads / 64];
   __shared__ int is_last;
   const int tid = threadIdx.x;
@@ -320,17 +326,30 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t n
   const FrameDesc& d = desc_of(p, f);
   const int64_t rel = rel_of(p, f);
   const int64_t base = d.chunk_off + rel * d.chunk_stride;
-  int64_t run = 0;
+  const int64_t cap = d.cap;
+  int64_t run = 0, irun = 0;
   for (int c0 = 0; c0 < d.cchunks; c0 += kScanThreads) {
     const int c = c0 + tid;
     const int64_t v = c < d.cchunks ? int64_t(p.chunk_counts[base + c]) : 0;
     int64_t total;
     const int64_t incl = block_inclusive_scan(v, wtot, total);
-    if (c < d.cchunks) p.chunk_offsets[base + c] = run + incl - v;
+    const int64_t off = run + incl - v;
+    int64_t fit = cap - off;                     // the chunk's records that get a record slot
+    fit = fit < 0 ? 0 : (fit > v ? v : fit);
+    if (c < d.cchunks) p.chunk_offsets[base + c] = off;
     run += total;
+    if (items) {                                 // uniform
+      const int64_t over = fit > kChunkRecords ? fit - kChunkRecords : 0;
+      const int64_t it = (over + (int64_t(1) << kItemShift) - 1) >> kItemShift;
+      int64_t itotal;
+      const int64_t iincl = block_inclusive_scan(it, wtot, itotal);
+      if (c < d.cchunks) p.chunk_items[base + c] = irun + iincl - it;
+      irun += itotal;
+    }
   }
   if (tid == 0) {
     p.counts[f] = run;
+    p.item_counts[f] = irun;
     __threadfence();
     const unsigned prev = atomicAdd(p.scan_done, 1u);
     is_last = prev == unsigned(nframes - 1) ? 1 : 0;
@@ -338,31 +357,39 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t n
   __syncthreads();
   if (!is_last) return;
   __threadfence();
-  int64_t carry = 0;
+  int64_t carry = 0, icarry = 0;
   for (int64_t g0 = 0; g0 < nframes; g0 += kScanThreads) {
     const int64_t g = g0 + tid;
-    int64_t v = 0;
+    int64_t v = 0, iv = 0;
     if (g < nframes) {
       const int64_t cnt = __atomic_load_n(p.counts + g, __ATOMIC_RELAXED);
-      const int64_t cap = desc_of(p, g).cap;
-      v = cnt < cap ? cnt : cap;
+      const int64_t gcap = desc_of(p, g).cap;
+      v = cnt < gcap ? cnt : gcap;
+      if (items) iv = __atomic_load_n(p.item_counts + g, __ATOMIC_RELAXED);
     }
     int64_t total;
     const int64_t incl = block_inclusive_scan(v, wtot, total);
     if (g < nframes) p.offsets[g + 1] = carry + incl;
     carry += total;
+    if (items) {
+      int64_t itotal;
+      const int64_t iincl = block_inclusive_scan(iv, wtot, itotal);
+      if (g < nframes) p.item_offsets[g + 1] = icarry + iincl;
+      icarry += itotal;
+    }
   }
   if (tid == 0) {
     p.offsets[0] = 0;
+    p.item_offsets[0] = 0;
     atomicExch(p.scan_done, 0u);
   }
 }
 
-int launch_scan(const DevPtrs& p, int64_t nframes, void* stream) {
+int launch_scan(const DevPtrs& p, int64_t nframes, int items, void* stream) {
   if (nframes <= 0) return hipSuccess;
   if (nframes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(scan_kernel, dim3(unsigned(nframes)), dim3(kScanThreads), 0,
-                     static_cast<hipStream_t>(stream), p, nframes);
+                     static_cast<hipStream_t>(stream), p, nframes, items);
   return hipGetLastError();
 }
 

@@ -264,6 +264,58 @@ def test_dense_chunk_every_cell_detected():
     cut.close()
 
 
+DENSE = {
+    # name: (shape, buckets): at Pfa 0.3 (p1 = 0.67 per round) about 45% of
+    # the cells are detected, ~15000 per compaction chunk of 2^15 cells
+    "dense_256x256": ((256, 256), (16, 16)),
+    "dense_64x32x32": ((64, 32, 32), (8, 8, 8)),
+}
+
+
+@pytest.mark.parametrize("cap", [None, 20000])
+@pytest.mark.parametrize("name", sorted(DENSE))
+def test_estimate_layouts_on_dense_chunks(name, cap):
+    """Chunks far beyond 1024 detections: the estimate without and with
+    overflow workers gives the same records bit for bit, and they match the
+    oracle; a frame capacity that cuts the list keeps its first records."""
+    from paper_1610_01050_amd import OPT_ESTIMATE_WORKERS
+    shape, buckets = DENSE[name]
+    print(f"dense case {name} cap={cap}", flush=True)
+    xs = [make_input(shape, 6, seed=901 + f)[0] for f in range(2)]
+    xd = torch.from_numpy(np.stack(xs)).to("cuda")
+    sigma = synth.draw_sigma(np.random.default_rng(5), 3, shape)
+
+    def run(max_det, workers):
+        plan = _plan(shape=shape, buckets=buckets, rounds=3, sigma=sigma, pfa=0.3, max_batch=2,
+                     max_detections=max_det)
+        plan.set_option(OPT_ESTIMATE_WORKERS, workers)
+        assert plan.info()["estimate_workers"] == workers
+        plan.execute(xd)
+        recs, counts = plan.detect(allow_truncation=True)
+        gbk = [b.cpu().numpy() for b in plan.buckets()]
+        gfl = [w.cpu().numpy().view(np.uint32) for w in plan.flags()]
+        plan.close()
+        return recs, counts, gbk, gfl
+
+    full = 1 << 16
+    r0, c0, _, _ = run(cap or full, 0)
+    r1, c1, gbk, gfl = run(cap or full, 1)
+    assert np.array_equal(c0, c1)
+    assert np.array_equal(r0, r1)
+    oplan = oracle_plan(shape, buckets, sigma, pfa=0.3)
+    if cap is None:
+        assert int(c1.max()) > 2 * 1024          # overflow items exist
+        ref = OR.rsft(xs[0], oplan)
+        _check_frame(0, oplan, ref, r1, gbk[0], gfl[0])
+    else:
+        assert int(c1.min()) > cap               # every frame is cut
+        ru, _, _, _ = run(full, 0)
+        for f in range(2):
+            got = r1[r1["frame"] == f]
+            assert len(got) == cap
+            assert np.array_equal(got, ru[ru["frame"] == f][:cap])
+
+
 def test_autotuned_fold_keeps_parity():
     """Whatever launch shape the tuner picks, the results stay within the
     parity contract."""
