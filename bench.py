@@ -354,6 +354,7 @@ def workloads_section(dev, steps, warmup, names=None):
         out[name] = {
             "frames": nframes, "input_bytes": in_bytes,
             "fold_launch": plan.info()["fold"],
+            "estimate_workers": plan.info()["estimate_workers"],
             "graph_replay_ms": {"p10": float(np.percentile(replay, 10)), "median": med,
                                 "p90": float(np.percentile(replay, 90))},
             "frames_per_s": nframes / (med * 1e-3),
@@ -509,7 +510,8 @@ def main():
     torch.cuda.synchronize()
     tuned_ms = plan.autotune(xa, repeats=5)          # fold launch shape, untimed
     fold_cfg = plan.info()["fold"]
-    log(f"autotuned fold: {fold_cfg} ({tuned_ms:.4f} ms)")
+    log(f"autotuned fold: {fold_cfg} ({tuned_ms:.4f} ms), estimate workers "
+        f"{plan.info()['estimate_workers']}")
 
     # graph replay (production launch mode)
     plan.set_option(OPT_TIMING, 0)
@@ -580,6 +582,7 @@ def main():
                      "avg_launch_ms": fold_ms},
         "stage_ms": stages,
         "fold_launch": fold_cfg,
+        "estimate_workers": plan.info()["estimate_workers"],
         "graph_ms_per_step": graph_s / args.steps * 1e3,
         "graph_replay_ms": graph_pct,
         "detections": {"total": int(counts.sum()), **fused_score},
