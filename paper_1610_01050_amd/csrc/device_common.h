@@ -33,4 +33,14 @@ __device__ __forceinline__ int64_t rel_of(const DevPtrs& p, int64_t f) {
   return p.uniform ? f : 0;
 }
 
+// Chunk (frame f, chunk c) of work-group b: from the chunk list when the
+// launch uses it, else from the (chunk, frame) or XCD-grouped grid the caller
+// decodes; false for list padding.
+__device__ __forceinline__ bool listed_chunk(const DevPtrs& p, int64_t b, int64_t& f, int& c) {
+  const int32_t* e = p.chunk_list + 2 * b;
+  f = e[0];
+  c = e[1];
+  return f >= 0;
+}
+
 }  // namespace rsft

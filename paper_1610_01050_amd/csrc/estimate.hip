@@ -417,10 +417,12 @@ __device__ __forceinline__ void build_range(const DevPtrs& p, int T, const Frame
 
 constexpr int kWordsPerThread = (1 << (kCompactShift - 5)) / kEstThreads;   // a chunk's bitmap words
 
-// Chunk (frame f, chunk c) of work-group b of the chunk grid; false when b
-// lies past the batch.
-__device__ __forceinline__ bool chunk_of(int64_t b, int64_t nframes, int max_cchunks, int xcd_groups,
-                                         int64_t& f, int& c) {
+// Chunk (frame f, chunk c) of work-group b of the chunk grid: the chunk
+// list's entry b, else from the (XCD-grouped) frame-by-chunk grid; false
+// when b lies past the batch or on list padding.
+__device__ __forceinline__ bool chunk_of(const DevPtrs& p, int64_t b, int64_t nframes, int max_cchunks,
+                                         int xcd_groups, int use_list, int64_t& f, int& c) {
+  if (use_list) return listed_chunk(p, b, f, c);
   if (xcd_groups) {
     const int64_t k = b >> 3;
     f = (k / max_cchunks) * 8 + (b & 7);
@@ -441,7 +443,8 @@ template <int D, int M>
 __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est_waves(D, M)))) void compact_estimate_kernel(DevPtrs p, int T,
                                                                        int64_t nframes,
                                                                        int max_cchunks,
-                                                                       int xcd_groups) {
+                                                                       int xcd_groups,
+                                                                       int use_list) {
   constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
   __shared__ uint32_t list[kListMax];
   __shared__ uint32_t wsum[kEstThreads / 64];
@@ -449,16 +452,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
   __shared__ float pbuf[D >= 4 ? kNb * kEstThreads : 1];
   int64_t f;
   int c;
-  const int64_t b = blockIdx.x;
-  if (xcd_groups) {
-    const int64_t k = b >> 3;
-    f = (k / max_cchunks) * 8 + (b & 7);
-    c = int(k % max_cchunks);
-  } else {
-    f = b / max_cchunks;
-    c = int(b % max_cchunks);
-  }
-  if (f >= nframes) return;
+  if (!chunk_of(p, blockIdx.x, nframes, max_cchunks, xcd_groups, use_list, f, c)) return;
   const FrameDesc& d = desc_of(p, f);
   // The descriptor fields, then the chunk's counters and bitmap words, are
   // each loaded together before they are tested (no chain of dependent
@@ -573,6 +567,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
                                                                      int64_t nframes,
                                                                      int max_cchunks,
                                                                      int xcd_groups,
+                                                                     int use_list,
                                                                      int og) {
   constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
   constexpr int kItem = 1 << kItemShift;
@@ -591,7 +586,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
     const int64_t v = (og & 7) == 0 ? (b & 7) * (og >> 3) + (b >> 3) : b;
     i = total * v / og;
     hi = total * (v + 1) / og;
-  } else if (!chunk_of(int64_t(blockIdx.x) - og, nframes, max_cchunks, xcd_groups, f, c)) {
+  } else if (!chunk_of(p, int64_t(blockIdx.x) - og, nframes, max_cchunks, xcd_groups, use_list, f, c)) {
     return;
   }
   for (;;) {
@@ -664,15 +659,15 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
 // frame).
 template <int D>
 static void launch_estimate_d(const DevPtrs& p, dim3 grid, int og, hipStream_t st, int T, int64_t nframes,
-                              int max_cchunks, int xcd, int est_mask) {
+                              int max_cchunks, int xcd, int use_list, int est_mask) {
 #define RSFT_EST(M)                                                                                      \
   do {                                                                                                   \
     if (og > 0)                                                                                          \
       hipLaunchKernelGGL((split_estimate_kernel<D, M>), grid, dim3(kEstThreads), 0, st, p, T, nframes,    \
-                         max_cchunks, xcd, og);                                                          \
+                         max_cchunks, xcd, use_list, og);                                                \
     else                                                                                                 \
       hipLaunchKernelGGL((compact_estimate_kernel<D, M>), grid, dim3(kEstThreads), 0, st, p, T, nframes,  \
-                         max_cchunks, xcd);                                                              \
+                         max_cchunks, xcd, use_list);                                                    \
   } while (0)
   if (est_mask >= 32) RSFT_EST(5);
   else if (est_mask >= 16) RSFT_EST(4);
@@ -683,21 +678,22 @@ static void launch_estimate_d(const DevPtrs& p, dim3 grid, int og, hipStream_t s
 }
 
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
-                    int est_mask, int workers, int num_cus, void* stream) {
+                    int est_mask, int workers, int num_cus, int64_t nlist, void* stream) {
   if (nframes <= 0) return hipSuccess;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int xcd = nframes >= 16 ? 1 : 0;
+  const int use_list = nlist > 0 ? 1 : 0;
   const int64_t rows = xcd ? ((nframes + 7) / 8) * 8 : nframes;
   // overflow workers: two per compute unit, a multiple of 8 so that the
   // chunk work-groups after them keep their XCD assignment
   const int og = workers ? ((2 * (num_cus > 0 ? num_cus : 256)) + 7) / 8 * 8 : 0;
-  const int64_t blocks = og + rows * int64_t(max_cchunks);
+  const int64_t blocks = og + (use_list ? nlist : rows * int64_t(max_cchunks));
   if (blocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
   const dim3 grid{unsigned(blocks), 1u, 1u};
-  if (dims_mask & 1) launch_estimate_d<1>(p, grid, og, st, T, nframes, max_cchunks, xcd, est_mask);
-  if (dims_mask & 2) launch_estimate_d<2>(p, grid, og, st, T, nframes, max_cchunks, xcd, est_mask);
-  if (dims_mask & 4) launch_estimate_d<3>(p, grid, og, st, T, nframes, max_cchunks, xcd, est_mask);
-  if (dims_mask & 8) launch_estimate_d<4>(p, grid, og, st, T, nframes, max_cchunks, xcd, est_mask);
+  if (dims_mask & 1) launch_estimate_d<1>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);
+  if (dims_mask & 2) launch_estimate_d<2>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);
+  if (dims_mask & 4) launch_estimate_d<3>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);
+  if (dims_mask & 8) launch_estimate_d<4>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);
   return hipGetLastError();
 }
 

@@ -71,13 +71,16 @@ struct rsft_plan_s {
   rsft::FoldConfig fold{256, 4, 0};
   int num_cus = 256;
   int64_t min_nl = 0;
-  int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, rows_ok = 1, est_nmask = 0;
+  int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, est_nmask = 0;
+  int rows_ok = 1, masks_ok = 1;   // every frame suits the row vote / the 32-cell mask vote
+  int vote_path = rsft::kVoteCells;
   int dft_plane = 0;   // floats per LDS plane of the DFT: B plus one pad per last-dimension row
   int dft_pad = 0;     // 1 when those pads are used
   int64_t tiles_per_frame = 0;   // uniform plans
   int64_t ntiles_uneven = 0;     // uneven plans
+  int64_t nchunk_list = 0;       // uneven plans with frames of different chunk counts
   // device arrays
-  DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles;
+  DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles, d_chunk_list;
   DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
       d_offsets, d_records, d_scan_done, d_chunk_items, d_item_counts, d_item_offsets;
   rsft::DevPtrs ptrs{};
@@ -416,7 +419,7 @@ void free_plan(rsft_plan_s* pl) {
       if (e) (void)hipEventDestroy(e);
   if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
   DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
-                          &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_part,
+                          &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_chunk_list, &pl->d_part,
                           &pl->d_buckets, &pl->d_powers, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
                           &pl->d_scan_done, &pl->d_chunk_items, &pl->d_item_counts, &pl->d_item_offsets};
@@ -490,10 +493,12 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     pl->dims_mask |= 1 << (d.ndim - 1);
     pl->est_nmask |= 1 << d.n_est;
     if (d.n_last < 64 || d.n_last > 4096) pl->rows_ok = 0;
+    if (d.n_last != 32) pl->masks_ok = 0;
     int sum_tw = 0;
     for (int k = 0; k < d.ndim; ++k) sum_tw += d.b[k];
     pl->sum_tw_max = std::max(pl->sum_tw_max, sum_tw);
   }
+  pl->vote_path = pl->rows_ok ? rsft::kVoteRows : pl->masks_ok ? rsft::kVoteMasks32 : rsft::kVoteCells;
   // the DFT stage keeps two planes of B floats plus the twiddles in LDS;
   // padding of the last dimension's rows (against bank conflicts) is used
   // when it fits
@@ -530,6 +535,31 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     }
     pl->ntiles_uneven = int64_t(tl.size());
   }
+  // compaction chunks of an uneven batch: when frames differ in chunk count,
+  // the vote and estimate launches take one work-group per listed chunk
+  // instead of a frames x max-chunks grid that is mostly empty. Position p
+  // holds a frame congruent to p mod 8 when the estimate groups frames by
+  // XCD (16 frames or more), as its grid does.
+  std::vector<int32_t> chunk_list;
+  if (!pl->uniform) {
+    int64_t total = 0;
+    for (const auto& d : pl->descs) total += d.cchunks;
+    if (total < int64_t(pl->max_cchunks) * nframes) {
+      const int groups = nframes >= 16 ? 8 : 1;
+      std::vector<std::vector<std::pair<int32_t, int32_t>>> q(static_cast<size_t>(groups));
+      for (int64_t i = 0; i < nframes; ++i)
+        for (int32_t c = 0; c < pl->descs[size_t(i)].cchunks; ++c)
+          q[size_t(i % groups)].push_back({int32_t(i), c});
+      size_t len = 0;
+      for (const auto& v : q) len = std::max(len, v.size());
+      for (size_t k = 0; k < len; ++k)
+        for (const auto& v : q) {
+          chunk_list.push_back(k < v.size() ? v[k].first : -1);
+          chunk_list.push_back(k < v.size() ? v[k].second : -1);
+        }
+      pl->nchunk_list = int64_t(chunk_list.size() / 2);
+    }
+  }
 
   rsft_status st;
   if ((st = upload(pl->d_descs, pl->descs)) != RSFT_OK) return st;
@@ -541,6 +571,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = upload(pl->d_win, ht.win)) != RSFT_OK) return st;
   if ((st = upload(pl->d_flat, ht.flat)) != RSFT_OK) return st;
   if ((st = upload(pl->d_tiles, tiles)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_chunk_list, chunk_list)) != RSFT_OK) return st;
   if ((st = alloc(pl->d_part, size_t(part_off) * sizeof(float2))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_buckets, size_t(bucket_off) * sizeof(float2))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_powers, size_t(bucket_off) * sizeof(float))) != RSFT_OK) return st;
@@ -584,6 +615,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.records = static_cast<rsft_detection*>(pl->d_records.ptr);
   q.scan_done = static_cast<uint32_t*>(pl->d_scan_done.ptr);
   q.tiles = static_cast<const int32_t*>(pl->d_tiles.ptr);
+  q.chunk_list = static_cast<const int32_t*>(pl->d_chunk_list.ptr);
   return RSFT_OK;
 }
 
@@ -632,7 +664,7 @@ rsft_status estimate_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   const auto& q = pl->ptrs;
   LAUNCH_TRY(rsft::launch_scan(q, batch, pl->est_workers, st));
   LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask,
-                                   pl->est_workers, pl->num_cus, st));
+                                   pl->est_workers, pl->num_cus, pl->nchunk_list, st));
   return RSFT_OK;
 }
 
@@ -648,7 +680,7 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0, st));
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, st));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, st));
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   {
     const rsft_status es = estimate_stage(pl, batch, st);
@@ -836,7 +868,7 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
     const auto& d = pl->descs[size_t(pl->uniform ? 0 : f)];
     for (int r = 0; r < pl->T; ++r) LAUNCH_TRY(rsft::launch_plain_fold(q, d_input, pl->dtype, f, r, d.B, s));
     LAUNCH_TRY(rsft::launch_plain_dft(q, f, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, s));
-    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, int(f), s));
+    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, int(f), 0, s));
   }
   if (batch > 0) {
     const rsft_status es = estimate_stage(pl, batch, s);
@@ -918,7 +950,7 @@ rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* strea
   for (int64_t f = 0; f < batch; ++f) words += size_t(pl->descs[size_t(pl->uniform ? 0 : f)].flag_stride);
   HIP_TRY(hipMemcpyAsync(pl->d_flags.ptr, d_flags, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   const auto& q = pl->ptrs;
-  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->rows_ok, 0, s));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, s));
   return estimate_stage(pl, batch, s);
 }
 

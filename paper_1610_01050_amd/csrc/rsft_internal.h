@@ -99,6 +99,10 @@ struct DevPtrs {
   uint32_t* scan_done;         // frames finished by the scan (0 between launches)
   rsft_detection* records;
   const int32_t* tiles;        // uneven plans: [ntiles][3] (frame, class, chunk)
+  // uneven plans whose frames differ in chunk count: [n][2] (frame, chunk) of
+  // every compaction chunk, position p holding a frame congruent to p mod 8
+  // (work-groups are dealt to the eight XCDs round-robin); (-1, -1) pads
+  const int32_t* chunk_list;
 };
 
 // Launch configuration of the fold stage, chosen per plan.
@@ -115,14 +119,18 @@ int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
                 int T, const FoldConfig& cfg, void* stream);
 int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw,
                int identity_relabel, int nchunks_override, void* stream);
+// vote paths: per cell (any shape), rows of 64..4096 cells (T <= 4), rows of
+// exactly 32 cells (bit-parallel masks)
+constexpr int kVoteCells = 0, kVoteRows = 1, kVoteMasks32 = 2;
+// nlist > 0: one work-group per chunk_list entry (whole batch, frame0 = 0)
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
-                int max_words, int dims_mask, int rows_ok, int frame0, void* stream);
+                int max_words, int dims_mask, int vote_path, int frame0, int64_t nlist, void* stream);
 // items: 1 also lists the estimate's overflow items (plans with overflow workers)
 int launch_scan(const DevPtrs& p, int64_t nframes, int items, void* stream);
 // est_mask: bit m set when some frame uses m estimation rounds (1..5)
 // workers: 1 adds overflow workers (two per compute unit of the num_cus)
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
-                    int est_mask, int workers, int num_cus, void* stream);
+                    int est_mask, int workers, int num_cus, int64_t nlist, void* stream);
 // Per-frame comparator path.
 int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t frame,
                       int round, int B, void* stream);

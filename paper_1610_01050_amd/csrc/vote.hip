@@ -51,12 +51,13 @@ __device__ __forceinline__ void stage_flags(uint32_t* __restrict__ dst, const ui
 }
 
 template <int D>
-__global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, int mu, int frame0) {
+__global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, int mu, int frame0, int use_list) {
   extern __shared__ uint32_t sflags[];
   __shared__ uint32_t wcount[kVoteThreads / 64];
   __shared__ uint32_t ssig[kMaxRounds * kMaxDims];
-  const int c = blockIdx.x;
-  const int64_t f = frame0 + int64_t(blockIdx.y);
+  int64_t f = frame0 + int64_t(blockIdx.y);
+  int c = blockIdx.x;
+  if (use_list && !listed_chunk(p, blockIdx.x, f, c)) return;
   const FrameDesc& d = desc_of(p, f);
   const int cch = d.cchunks, nd = d.ndim;   // loaded together, then tested
   if ((c >= cch) | (nd != D)) return;
@@ -115,20 +116,128 @@ __global__ __launch_bounds__(kVoteThreads) void vote_kernel(DevPtrs p, int T, in
   }
 }
 
+// vote_mask_kernel (rows of exactly 32 cells, any T): a row's 32 cells
+// share their bucket in every dimension but the last, so in round s the
+// bucket of cell x of the row is rowpart_s | b_s(x) with b_s(x) =
+// [sigma_{s,last} x]_32 >> log2 L_last (Def. 3). With M_s[b] the 32-bit mask
+// of the cells x whose b_s(x) = b, the round's votes for the whole row are
+// the OR of M_s[b] over the flagged buckets b of the row's B_last-bit flag
+// window (B_last <= 16, so the window never straddles a word). A bit-sliced
+// counter of NB bits adds the T masks and a bit-sliced comparison with mu
+// gives the row's bitmap word: the same bits as the per-cell sum of eq. a_i,
+// at a few instructions per cell. One thread per row.
+template <int D, int NB>
+__global__ __launch_bounds__(kVoteThreads) void vote_mask_kernel(DevPtrs p, int T, int mu, int frame0,
+                                                                int use_list) {
+  extern __shared__ uint32_t sflags[];
+  __shared__ uint32_t wcount[kVoteThreads / 64];
+  __shared__ uint32_t smask[kMaxRounds * 16];   // M_s[b], b < B_last <= 16
+  __shared__ uint32_t ssig[kMaxRounds * kMaxDims];
+  int64_t f = frame0 + int64_t(blockIdx.y);
+  int c = blockIdx.x;
+  if (use_list && !listed_chunk(p, blockIdx.x, f, c)) return;
+  const FrameDesc& d = desc_of(p, f);
+  const int cch = d.cchunks, nd = d.ndim;   // loaded together, then tested
+  if ((c >= cch) | (nd != D)) return;
+  const int64_t rel = rel_of(p, f);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int words = d.words;
+  const uint32_t bl = uint32_t(d.b_last);
+  const uint32_t lsl = uint32_t(d.lshift[D - 1]);
+  stage_flags(sflags, p.flags + d.flag_off + rel * d.flag_stride, T * words);
+  if (tid < T * D) ssig[tid] = uint32_t(d.sigma[tid / D][tid % D]);
+  for (int k = tid; k < T * 16; k += kVoteThreads) {
+    const int s = k >> 4;
+    const uint32_t b = uint32_t(k & 15);
+    const uint32_t sg = uint32_t(d.sigma[s][D - 1]);
+    uint32_t m = 0u;
+    for (uint32_t x = 0; x < 32u; ++x) m |= uint32_t((((sg * x) & 31u) >> lsl) == b) << x;
+    smask[k] = m;
+  }
+  uint32_t nm[D], ls[D], bs[D], ns[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    nm[dd] = uint32_t(d.n[dd] - 1);
+    ls[dd] = uint32_t(d.lshift[dd]);
+    bs[dd] = uint32_t(d.bshift[dd]);
+    ns[dd] = uint32_t(d.nshift[dd]);
+  }
+  const int64_t cell0 = int64_t(c) << kCompactShift;
+  const int64_t rem = d.N - cell0;
+  const int nrows = int(rem < (int64_t(1) << kCompactShift) ? rem : (int64_t(1) << kCompactShift)) >> 5;
+  uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride + (cell0 >> 5);
+  const uint32_t wmask = bl >= 32u ? ~0u : (1u << bl) - 1u;
+  __syncthreads();
+
+  uint32_t cnt = 0u;
+  for (int r = tid; r < nrows; r += kVoteThreads) {
+    const int64_t iw = cell0 + (int64_t(r) << 5);   // first cell of the row
+    uint32_t acc[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc[k] = 0u;
+    for (int s = 0; s < T; ++s) {
+      uint32_t rowpart = 0u;
+#pragma unroll
+      for (int dd = 0; dd < D - 1; ++dd) {
+        const uint32_t cd = uint32_t(iw >> ns[dd]) & nm[dd];
+        rowpart |= (((ssig[s * D + dd] * cd) & nm[dd]) >> ls[dd]) << bs[dd];
+      }
+      uint32_t win = (sflags[s * words + int(rowpart >> 5)] >> (rowpart & 31u)) & wmask;
+      uint32_t m = 0u;
+      while (win) {
+        const int b = __ffs(win) - 1;
+        win &= win - 1u;
+        m |= smask[s * 16 + b];
+      }
+      // acc += m, bit-sliced
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const uint32_t t = acc[k] & m;
+        acc[k] ^= m;
+        m = t;
+      }
+    }
+    // acc >= mu, bit-sliced, most significant bit first
+    uint32_t ge = 0u, eq = ~0u;
+#pragma unroll
+    for (int k = NB - 1; k >= 0; --k) {
+      const uint32_t mk = ((uint32_t(mu) >> k) & 1u) ? ~0u : 0u;
+      ge |= eq & acc[k] & ~mk;
+      eq &= ~(acc[k] ^ mk);
+    }
+    const uint32_t hit = ge | eq;
+    bm[r] = hit;
+    cnt += uint32_t(__popc(hit));
+  }
+  // work-group total of the chunk
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (lane == 0) wcount[wave] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t total = 0u;
+    for (int w = 0; w < kVoteThreads / 64; ++w) total += wcount[w];
+    p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c] = total;
+  }
+}
+
 // bit j (< 128) of a 128-bit row held as four words
 __device__ __forceinline__ uint32_t row_bit(const uint32_t* w, uint32_t j) {
   return __builtin_amdgcn_ubfe(w[j >> 5], j & 31u, 1u);
 }
 
 template <int D, int TT>
-__global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int mu, int frame0) {
+__global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int mu, int frame0, int use_list) {
   extern __shared__ uint32_t sflags[];
   __shared__ uint32_t wcount[kVoteThreads / 64];
   __shared__ uint32_t rowbm[kVoteThreads / 64][kRowWordsMax];
   __shared__ uint32_t blist[kVoteThreads / 64][128];
   __shared__ uint32_t rowflags[kVoteThreads / 64][TT * 4];
-  const int c = blockIdx.x;
-  const int64_t f = frame0 + int64_t(blockIdx.y);
+  int64_t f = frame0 + int64_t(blockIdx.y);
+  int c = blockIdx.x;
+  if (use_list && !listed_chunk(p, blockIdx.x, f, c)) return;
   const FrameDesc& d = desc_of(p, f);
   const int cch = d.cchunks, nd = d.ndim;   // loaded together, then tested
   if ((c >= cch) | (nd != D)) return;
@@ -251,30 +360,39 @@ __global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int 
 
 template <int D>
 static void launch_vote_d(const DevPtrs& p, dim3 grid, size_t shmem, hipStream_t st, int T, int mu,
-                          int frame0, bool rows) {
+                          int frame0, int use_list, bool rows, bool masks) {
+  if (masks) {   // counters of NB bits hold counts up to T
+    if (T <= 3) hipLaunchKernelGGL((vote_mask_kernel<D, 2>), grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0, use_list);
+    else if (T <= 7) hipLaunchKernelGGL((vote_mask_kernel<D, 3>), grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0, use_list);
+    else hipLaunchKernelGGL((vote_mask_kernel<D, 7>), grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0, use_list);
+    return;
+  }
   if (rows) {
     switch (T) {
-      case 1: hipLaunchKernelGGL((vote_rows_kernel<D, 1>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
-      case 2: hipLaunchKernelGGL((vote_rows_kernel<D, 2>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
-      case 3: hipLaunchKernelGGL((vote_rows_kernel<D, 3>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
-      case 4: hipLaunchKernelGGL((vote_rows_kernel<D, 4>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0); return;
+      case 1: hipLaunchKernelGGL((vote_rows_kernel<D, 1>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0, use_list); return;
+      case 2: hipLaunchKernelGGL((vote_rows_kernel<D, 2>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0, use_list); return;
+      case 3: hipLaunchKernelGGL((vote_rows_kernel<D, 3>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0, use_list); return;
+      case 4: hipLaunchKernelGGL((vote_rows_kernel<D, 4>), grid, dim3(kVoteThreads), shmem, st, p, mu, frame0, use_list); return;
       default: break;
     }
   }
-  hipLaunchKernelGGL(vote_kernel<D>, grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0);
+  hipLaunchKernelGGL(vote_kernel<D>, grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0, use_list);
 }
 
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks, int max_words,
-                int dims_mask, int rows_ok, int frame0, void* stream) {
+                int dims_mask, int vote_path, int frame0, int64_t nlist, void* stream) {
   if (nframes <= 0) return hipSuccess;
   const size_t shmem = size_t(T) * size_t(max_words) * sizeof(uint32_t);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const dim3 grid{unsigned(max_cchunks), unsigned(nframes), 1u};
-  const bool rows = rows_ok != 0 && T <= 4;
-  if (dims_mask & 1) launch_vote_d<1>(p, grid, shmem, st, T, mu, frame0, rows);
-  if (dims_mask & 2) launch_vote_d<2>(p, grid, shmem, st, T, mu, frame0, rows);
-  if (dims_mask & 4) launch_vote_d<3>(p, grid, shmem, st, T, mu, frame0, rows);
-  if (dims_mask & 8) launch_vote_d<4>(p, grid, shmem, st, T, mu, frame0, rows);
+  const int use_list = nlist > 0 ? 1 : 0;
+  if (use_list && (frame0 != 0 || nlist >= (int64_t(1) << 31))) return hipErrorInvalidValue;
+  const dim3 grid = use_list ? dim3{unsigned(nlist), 1u, 1u} : dim3{unsigned(max_cchunks), unsigned(nframes), 1u};
+  const bool rows = vote_path == kVoteRows && T <= 4;
+  const bool masks = vote_path == kVoteMasks32;
+  if (dims_mask & 1) launch_vote_d<1>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks);
+  if (dims_mask & 2) launch_vote_d<2>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks);
+  if (dims_mask & 4) launch_vote_d<3>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks);
+  if (dims_mask & 8) launch_vote_d<4>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks);
   return hipGetLastError();
 }
 

@@ -53,6 +53,10 @@ CASES = {
     "rectangular_windows": ((256, 256), (16, 16), 3, 0, "c64", 2, 5, 1e-3, 0.0),
     "forty_db": ((1024, 256), (32, 16), 3, 0, "c64", 2, 8, 1e-3, 40.0),
     "max_rounds_64": ((512, 256), (16, 16), 64, 40, "c64", 1, 4, 1e-3, 60.0),
+    # rows of 32 cells take the bit-parallel vote; T = 5 and 9 need 3- and
+    # 7-bit vote counters
+    "rows_of_32_T5_mu3": ((256, 32), (16, 8), 5, 3, "c64", 2, 4, 1e-3, 60.0),
+    "rows_of_32_T9_mu5": ((128, 32), (8, 4), 9, 5, "c64", 1, 3, 1e-3, 60.0),
 }
 
 
@@ -110,7 +114,8 @@ def test_estimated_noise_floor_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["ongrid_256x256_c128", "cube_256x128x32", "four_dim",
-                                  "five_rounds_mu3", "one_dim_4096"])
+                                  "five_rounds_mu3", "one_dim_4096", "rows_of_32_T5_mu3",
+                                  "rows_of_32_T9_mu5"])
 def test_votes_bit_exact_from_oracle_flags(name):
     """Voting, second stage and ordering are integer work: given the oracle's
     flags, the detections and their votes must match exactly."""
