@@ -79,6 +79,7 @@ struct rsft_plan_s {
   int64_t tiles_per_frame = 0;   // uniform plans
   int64_t ntiles_uneven = 0;     // uneven plans
   int64_t nchunk_list = 0;       // uneven plans with frames of different chunk counts
+  int scan_fpb = 1;              // frames per scan work-group
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles, d_chunk_list;
   DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
@@ -499,6 +500,9 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     pl->sum_tw_max = std::max(pl->sum_tw_max, sum_tw);
   }
   pl->vote_path = pl->rows_ok ? rsft::kVoteRows : pl->masks_ok ? rsft::kVoteMasks32 : rsft::kVoteCells;
+  // chunks per frame are a power of two (N is); few of them: several frames
+  // per scan work-group
+  if (pl->uniform && pl->descs[0].cchunks <= 128) pl->scan_fpb = 256 / pl->descs[0].cchunks;
   // the DFT stage keeps two planes of B floats plus the twiddles in LDS;
   // padding of the last dimension's rows (against bank conflicts) is used
   // when it fits
@@ -662,7 +666,7 @@ void drop_graphs(rsft_plan_s* pl) {
 // scan + compact/estimate, in the plan's estimate layout
 rsft_status estimate_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   const auto& q = pl->ptrs;
-  LAUNCH_TRY(rsft::launch_scan(q, batch, pl->est_workers, st));
+  LAUNCH_TRY(rsft::launch_scan(q, batch, pl->est_workers, pl->scan_fpb, st));
   LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask,
                                    pl->est_workers, pl->num_cus, pl->nchunk_list, st));
   return RSFT_OK;

@@ -125,8 +125,10 @@ constexpr int kVoteCells = 0, kVoteRows = 1, kVoteMasks32 = 2;
 // nlist > 0: one work-group per chunk_list entry (whole batch, frame0 = 0)
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
                 int max_words, int dims_mask, int vote_path, int frame0, int64_t nlist, void* stream);
-// items: 1 also lists the estimate's overflow items (plans with overflow workers)
-int launch_scan(const DevPtrs& p, int64_t nframes, int items, void* stream);
+// items: 1 also lists the estimate's overflow items (plans with overflow
+// workers); fpb: frames per work-group (1, or 256 / chunks per frame in a
+// uniform plan of at most 128 chunks per frame)
+int launch_scan(const DevPtrs& p, int64_t nframes, int items, int fpb, void* stream);
 // est_mask: bit m set when some frame uses m estimation rounds (1..5)
 // workers: 1 adds overflow workers (two per compute unit of the num_cus)
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,

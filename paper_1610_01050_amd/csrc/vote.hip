@@ -397,7 +397,9 @@ int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunk
 }
 
 // ---------------------------------------------------------------------------
-// scan: one work-group per frame turns the frame's chunk counters into
+// scan: one work-group per frame (or, in uniform plans of at most 128 chunks
+// per frame, per kScanThreads / chunks frames in one segmented block scan)
+// turns the frame's chunk counters into
 // chunk_offsets (rank of each compaction chunk's first detection in its
 // frame, a running sum in row-major cell order) and counts[f]. For plans
 // with overflow workers it also lists their work: the records of a chunk
@@ -436,41 +438,91 @@ __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wtot
   return pre + incl;
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t nframes, int items) {
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t nframes, int items, int fpb) {
   __shared__ int64_t wtot[kScanThreads / 64];
+  __shared__ int64_t sinc[kScanThreads];     // block-wide inclusive sums (fpb > 1)
+  __shared__ int64_t ftot[kScanThreads];     // records of each of the block's frames
+  __shared__ int64_t fitm[kScanThreads];     // overflow items of each of the block's frames
   __shared__ int is_last;
   const int tid = threadIdx.x;
-  const int64_t f = blockIdx.x;
-  const FrameDesc& d = desc_of(p, f);
-  const int64_t rel = rel_of(p, f);
-  const int64_t base = d.chunk_off + rel * d.chunk_stride;
-  const int64_t cap = d.cap;
-  int64_t run = 0, irun = 0;
-  for (int c0 = 0; c0 < d.cchunks; c0 += kScanThreads) {
-    const int c = c0 + tid;
-    const int64_t v = c < d.cchunks ? int64_t(p.chunk_counts[base + c]) : 0;
+  const int64_t f0 = int64_t(blockIdx.x) * fpb;
+  if (fpb == 1) {
+    // one frame, its chunks kScanThreads at a time
+    const int64_t f = f0;
+    const FrameDesc& d = desc_of(p, f);
+    const int64_t rel = rel_of(p, f);
+    const int64_t base = d.chunk_off + rel * d.chunk_stride;
+    const int64_t cap = d.cap;
+    int64_t run = 0, irun = 0;
+    for (int c0 = 0; c0 < d.cchunks; c0 += kScanThreads) {
+      const int c = c0 + tid;
+      const int64_t v = c < d.cchunks ? int64_t(p.chunk_counts[base + c]) : 0;
+      int64_t total;
+      const int64_t incl = block_inclusive_scan(v, wtot, total);
+      const int64_t off = run + incl - v;
+      int64_t fit = cap - off;                   // the chunk's records that get a record slot
+      fit = fit < 0 ? 0 : (fit > v ? v : fit);
+      if (c < d.cchunks) p.chunk_offsets[base + c] = off;
+      run += total;
+      if (items) {                               // uniform
+        const int64_t over = fit > kChunkRecords ? fit - kChunkRecords : 0;
+        const int64_t it = (over + (int64_t(1) << kItemShift) - 1) >> kItemShift;
+        int64_t itotal;
+        const int64_t iincl = block_inclusive_scan(it, wtot, itotal);
+        if (c < d.cchunks) p.chunk_items[base + c] = irun + iincl - it;
+        irun += itotal;
+      }
+    }
+    if (tid == 0) {
+      ftot[0] = run;
+      fitm[0] = irun;
+    }
+  } else {
+    // a uniform plan of cch = kScanThreads / fpb chunks per frame: fpb frames
+    // in one segmented scan (thread t: frame t / cch, chunk t mod cch)
+    const FrameDesc& d = p.descs[0];
+    const int cch = kScanThreads / fpb;
+    const int fi = tid / cch;
+    const int c = tid - fi * cch;
+    const int64_t f = f0 + fi;
+    const bool valid = f < nframes;
+    const int64_t base = d.chunk_off + f * d.chunk_stride;
+    const int64_t cap = d.cap;
+    const int s0 = fi * cch;                     // the frame's first thread
+    const int64_t v = valid ? int64_t(p.chunk_counts[base + c]) : 0;
     int64_t total;
     const int64_t incl = block_inclusive_scan(v, wtot, total);
-    const int64_t off = run + incl - v;
-    int64_t fit = cap - off;                     // the chunk's records that get a record slot
+    sinc[tid] = incl;
+    __syncthreads();
+    const int64_t segb = s0 == 0 ? 0 : sinc[s0 - 1];
+    const int64_t off = incl - v - segb;
+    int64_t fit = cap - off;
     fit = fit < 0 ? 0 : (fit > v ? v : fit);
-    if (c < d.cchunks) p.chunk_offsets[base + c] = off;
-    run += total;
+    if (valid) p.chunk_offsets[base + c] = off;
+    if (c == cch - 1) ftot[fi] = incl - segb;
     if (items) {                                 // uniform
       const int64_t over = fit > kChunkRecords ? fit - kChunkRecords : 0;
       const int64_t it = (over + (int64_t(1) << kItemShift) - 1) >> kItemShift;
       int64_t itotal;
-      const int64_t iincl = block_inclusive_scan(it, wtot, itotal);
-      if (c < d.cchunks) p.chunk_items[base + c] = irun + iincl - it;
-      irun += itotal;
+      const int64_t iincl = block_inclusive_scan(it, wtot, itotal);   // its barriers end the reads of sinc
+      sinc[tid] = iincl;
+      __syncthreads();
+      const int64_t isegb = s0 == 0 ? 0 : sinc[s0 - 1];
+      if (valid) p.chunk_items[base + c] = iincl - it - isegb;
+      if (c == cch - 1) fitm[fi] = iincl - isegb;
+    } else if (c == cch - 1) {
+      fitm[fi] = 0;
     }
   }
+  __syncthreads();
   if (tid == 0) {
-    p.counts[f] = run;
-    p.item_counts[f] = irun;
+    for (int k = 0; k < fpb && f0 + k < nframes; ++k) {
+      p.counts[f0 + k] = ftot[k];
+      p.item_counts[f0 + k] = fitm[k];
+    }
     __threadfence();
     const unsigned prev = atomicAdd(p.scan_done, 1u);
-    is_last = prev == unsigned(nframes - 1) ? 1 : 0;
+    is_last = prev == gridDim.x - 1u ? 1 : 0;
   }
   __syncthreads();
   if (!is_last) return;
@@ -503,11 +555,13 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t n
   }
 }
 
-int launch_scan(const DevPtrs& p, int64_t nframes, int items, void* stream) {
+int launch_scan(const DevPtrs& p, int64_t nframes, int items, int fpb, void* stream) {
   if (nframes <= 0) return hipSuccess;
   if (nframes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scan_kernel, dim3(unsigned(nframes)), dim3(kScanThreads), 0,
-                     static_cast<hipStream_t>(stream), p, nframes, items);
+  if (fpb < 1 || fpb > kScanThreads || kScanThreads % fpb != 0) return hipErrorInvalidValue;
+  const int64_t blocks = (nframes + fpb - 1) / fpb;
+  hipLaunchKernelGGL(scan_kernel, dim3(unsigned(blocks)), dim3(kScanThreads), 0,
+                     static_cast<hipStream_t>(stream), p, nframes, items, fpb);
   return hipGetLastError();
 }
 
