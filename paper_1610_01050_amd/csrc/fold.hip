@@ -91,7 +91,7 @@ __device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restr
   chunk = __builtin_amdgcn_readfirstlane(chunk);
   const FrameDesc& d = p.descs[p.uniform ? 0 : f];
   const int64_t rel = p.uniform ? f : 0;
-  const int nl = d.n_last, bl = d.b_last, R = d.rows_per_class, rows_total = d.rows_total;
+  const int nl = d.fold_nl, bl = d.fold_bl, R = d.rows_per_class, rows_total = d.rows_total;
   const float2* __restrict__ wrow = p.wrow + d.wrow_off;
   const float2* __restrict__ wcol = p.wcol + d.wcol_off;
   const int32_t* __restrict__ rl = p.rowlist + d.rowlist_off + int64_t(cls) * R;
@@ -182,20 +182,42 @@ __device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restr
     for (int v = 0; v < V; ++v) red[s * P + tid * V + v] = make_float2(ar[s][v], ai[s][v]);
   __syncthreads();
 
-  // slot q holds residue q mod B_{D-1}; sum the P / B_{D-1} slots of each
-  // residue in a fixed order
+  // Sum the P / fold_bl slots of each residue in a fixed order. One
+  // dimension: slot q holds residue q mod B_{D-1}. Two flattened: slot q =
+  // i * N_{D-1} + j (mod the pass) holds residue (i mod B_{D-2}) B_{D-1} +
+  // (j mod B_{D-1}), and residue (r1, r2) owns the slots r2 + B_{D-1} a +
+  // (r1 + B_{D-2} m) N_{D-1}.
   const int nslots = P / bl;
   float2* part = p.part + d.part_off + rel * d.part_stride;
-  for (int o = tid; o < TG * bl; o += THREADS) {
-    const int s = o / bl;
-    const int rho = o - s * bl;
-    float sr = 0.f, si = 0.f;
-    for (int k = 0; k < nslots; ++k) {
-      const float2 v = red[s * P + rho + k * bl];
-      sr += v.x;
-      si += v.y;
+  if (bl == d.fold_bin) {
+    for (int o = tid; o < TG * bl; o += THREADS) {
+      const int s = o / bl;
+      const int rho = o - s * bl;
+      float sr = 0.f, si = 0.f;
+      for (int k = 0; k < nslots; ++k) {
+        const float2 v = red[s * P + rho + k * bl];
+        sr += v.x;
+        si += v.y;
+      }
+      part[(int64_t(chunk) * T + round0 + s) * d.B + int64_t(cls) * bl + rho] = make_float2(sr, si);
     }
-    part[(int64_t(chunk) * T + round0 + s) * d.B + int64_t(cls) * bl + rho] = make_float2(sr, si);
+  } else {
+    const int bin = d.fold_bin, lw = d.fold_lw;
+    const int na = (1 << lw) / bin;              // slots of a residue within one N_{D-1} row
+    const int period = (bl / bin) << lw;         // B_{D-2} N_{D-1}
+    for (int o = tid; o < TG * bl; o += THREADS) {
+      const int s = o / bl;
+      const int rho = o - s * bl;
+      const int r1 = rho / bin, r2 = rho - r1 * bin;
+      float sr = 0.f, si = 0.f;
+      for (int m = 0; m < P / period; ++m)
+        for (int a = 0; a < na; ++a) {
+          const float2 v = red[s * P + m * period + (r1 << lw) + r2 + a * bin];
+          sr += v.x;
+          si += v.y;
+        }
+      part[(int64_t(chunk) * T + round0 + s) * d.B + int64_t(cls) * bl + rho] = make_float2(sr, si);
+    }
   }
 }
 

@@ -313,13 +313,23 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
     d.renyi_h = double(H);
   }
 
-  // fold view: rows = leading dims flattened, columns = last dim
-  const int64_t nl = p.n[D - 1], bl = p.b[D - 1];
+  // fold view: rows = leading dims flattened, columns = the last dim, or
+  // the last two flattened when rows would be short (< 64 cells, D >= 3)
+  // and the flattened residue period B_{D-2} N_{D-1} and residue count
+  // B_{D-2} B_{D-1} stay within the smallest fold pass (512 slots)
+  const int F = (D >= 3 && p.n[D - 1] < 64 && p.b[D - 2] * p.n[D - 1] <= 512 &&
+                 p.b[D - 2] * p.b[D - 1] <= 512) ? 2 : 1;
+  const int64_t nl = F == 2 ? p.n[D - 2] * p.n[D - 1] : p.n[D - 1];
+  const int64_t bl = F == 2 ? p.b[D - 2] * p.b[D - 1] : p.b[D - 1];
   const int64_t rows_total = N / nl;
   const int64_t classes = B / bl;
   const int64_t R = rows_total / classes;
-  d.n_last = int32_t(nl);
-  d.b_last = int32_t(bl);
+  d.n_last = int32_t(p.n[D - 1]);
+  d.b_last = int32_t(p.b[D - 1]);
+  d.fold_nl = int32_t(nl);
+  d.fold_bl = int32_t(bl);
+  d.fold_bin = int32_t(p.b[D - 1]);
+  d.fold_lw = F == 2 ? ilog2(int32_t(p.n[D - 1])) : 24;
   d.rows_total = int32_t(rows_total);
   d.classes = int32_t(classes);
   d.rows_per_class = int32_t(R);
@@ -338,7 +348,7 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
     for (int64_t r = 0; r < rows_total; ++r) {
       std::complex<double> v(1.0, 0.0);
       int64_t rem = r;
-      for (int k = D - 2; k >= 0; --k) {
+      for (int k = D - 1 - F; k >= 0; --k) {
         const int64_t m = rem % p.n[k];
         rem /= p.n[k];
         v *= W[size_t(s * D + k)][size_t(m)];
@@ -348,27 +358,28 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
   d.wcol_off = int64_t(ht.wcol.size());
   for (int s = 0; s < T; ++s)
     for (int64_t c = 0; c < nl; ++c) {
-      const auto v = W[size_t(s * D + D - 1)][size_t(c)];
+      std::complex<double> v = W[size_t(s * D + D - 1)][size_t(c % p.n[D - 1])];
+      if (F == 2) v *= W[size_t(s * D + D - 2)][size_t(c / p.n[D - 1])];
       ht.wcol.push_back(make_float2(float(v.real()), float(v.imag())));
     }
   d.rowlist_off = int64_t(ht.rowlist.size());
   for (int64_t cls = 0; cls < classes; ++cls) {
-    // class = row-major (c_0, ..., c_{D-2}) over B_0 x ... x B_{D-2}
+    // class = row-major (c_0, ..., c_{D-1-F}) over B_0 x ... x B_{D-1-F}
     int64_t c[RSFT_MAX_DIMS] = {0, 0, 0, 0};
     int64_t rem = cls;
-    for (int k = D - 2; k >= 0; --k) {
+    for (int k = D - 1 - F; k >= 0; --k) {
       c[k] = rem % p.b[k];
       rem /= p.b[k];
     }
     for (int64_t li = 0; li < R; ++li) {
       int64_t lrem = li, row = 0, stride = 1;
       int64_t m[RSFT_MAX_DIMS] = {0, 0, 0, 0};
-      for (int k = D - 2; k >= 0; --k) {
+      for (int k = D - 1 - F; k >= 0; --k) {
         const int64_t L = p.n[k] / p.b[k];
         m[k] = c[k] + p.b[k] * (lrem % L);
         lrem /= L;
       }
-      for (int k = D - 2; k >= 0; --k) {
+      for (int k = D - 1 - F; k >= 0; --k) {
         row += m[k] * stride;
         stride *= p.n[k];
       }
@@ -526,7 +537,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     std::vector<Tile> tl;
     for (int64_t i = 0; i < nframes; ++i) {
       const auto& d = pl->descs[size_t(i)];
-      const int64_t bytes = int64_t(d.rows_per_class) * std::min<int64_t>(d.chunk_cols, d.n_last);
+      const int64_t bytes = int64_t(d.rows_per_class) * std::min<int64_t>(d.chunk_cols, d.fold_nl);
       for (int c = 0; c < d.classes; ++c)
         for (int k = 0; k < d.nchunks; ++k) tl.push_back({bytes, int32_t(i), c, k});
     }

@@ -37,6 +37,12 @@ struct FrameDesc {
   // fold view: rows = flattened leading dims, columns = last dim
   int32_t n_last, b_last, rows_total, classes, rows_per_class;
   int32_t chunk_cols, nchunks;
+  // fold row: the last dimension, or for short-row 3-D+ frames the last two
+  // flattened (fold_nl cells, fold_bl residue classes). Residue of slot q of
+  // a row: ((q >> fold_lw) mod (fold_bl / fold_bin)) * fold_bin + q mod
+  // fold_bin, with fold_bin = B_{D-1} and fold_lw = log2 N_{D-1} (fold_bl =
+  // fold_bin for one dimension: q mod B_{D-1})
+  int32_t fold_nl, fold_bl, fold_bin, fold_lw;
   int32_t words;              // flag words per round = ceil(B / 32)
   int32_t cap;                // detection capacity of a frame
   int32_t n_est;              // rounds used for magnitude estimates (<= kMaxEstRounds)
