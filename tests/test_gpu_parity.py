@@ -161,6 +161,41 @@ def test_uneven_batch_matches_oracle():
     plan.close()
 
 
+def test_uneven_3d_mixed_fold_views_matches_oracle():
+    """Frames whose fold rows are the last dimension (N_last = 64) or the last
+    two flattened (N_last = 32 or 16), of one or two compaction chunks (so
+    the vote and estimate take the chunk list), in one launch; both estimate
+    layouts give the same records."""
+    from paper_1610_01050_amd import OPT_ESTIMATE_WORKERS, Plan
+    cases = [((64, 32, 32), (8, 8, 8)), ((32, 16, 64), (4, 4, 8)),
+             ((16, 128, 32), (4, 16, 4)), ((8, 64, 16), (4, 8, 4))]
+    descs, frames, sigmas = [], [], []
+    for i, (sh, bk) in enumerate(cases):
+        sg = synth.draw_sigma(np.random.default_rng(450 + i), 3, sh)
+        descs.append(dict(shape=sh, buckets=bk, rounds=3, sigma=sg, pfa=1e-3, max_detections=1 << 15))
+        x, _ = make_input(sh, 5, seed=550 + i)
+        frames.append(x)
+        sigmas.append(sg)
+    xd = torch.from_numpy(np.concatenate([x.ravel() for x in frames])).to("cuda")
+    out = []
+    for workers in (0, 1):
+        plan = Plan.uneven(descs)
+        plan.set_option(OPT_ESTIMATE_WORKERS, workers)
+        plan.execute(xd)
+        recs, counts = plan.detect()
+        gbk = [b.cpu().numpy() for b in plan.buckets()]
+        gfl = [w.cpu().numpy().view(np.uint32) for w in plan.flags()]
+        plan.close()
+        out.append((recs, counts, gbk, gfl))
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
+    recs, counts, gbk, gfl = out[0]
+    for f, (sh, bk) in enumerate(cases):
+        oplan = oracle_plan(sh, bk, sigmas[f], pfa=1e-3)
+        ref = OR.rsft(frames[f], oplan)
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
+
+
 def test_graph_replay_equals_eager():
     """The captured launch sequence gives the same results on every replay as
     the eager launches, with eager work in between."""
