@@ -527,6 +527,50 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(DevPtrs p, int64_t n
   __syncthreads();
   if (!is_last) return;
   __threadfence();
+  constexpr int kPer = 8;
+  if (nframes <= int64_t(kPer) * kScanThreads) {
+    // thread t owns frames t * per .. t * per + per - 1: their totals are
+    // loaded together, summed, and one block scan places them
+    const int per = int((nframes + kScanThreads - 1) / kScanThreads);
+    const int64_t g0 = int64_t(tid) * per;
+    int64_t v[kPer], iv[kPer];
+    int64_t sum = 0, isum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t g = g0 + k;
+      v[k] = iv[k] = 0;
+      if (k < per && g < nframes) {
+        const int64_t cnt = __atomic_load_n(p.counts + g, __ATOMIC_RELAXED);
+        const int64_t gcap = desc_of(p, g).cap;
+        v[k] = cnt < gcap ? cnt : gcap;
+        if (items) iv[k] = __atomic_load_n(p.item_counts + g, __ATOMIC_RELAXED);
+      }
+      sum += v[k];
+      isum += iv[k];
+    }
+    int64_t total;
+    int64_t run = block_inclusive_scan(sum, wtot, total) - sum;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      run += v[k];
+      if (k < per && g0 + k < nframes) p.offsets[g0 + k + 1] = run;
+    }
+    if (items) {
+      int64_t itotal;
+      int64_t irun = block_inclusive_scan(isum, wtot, itotal) - isum;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        irun += iv[k];
+        if (k < per && g0 + k < nframes) p.item_offsets[g0 + k + 1] = irun;
+      }
+    }
+    if (tid == 0) {
+      p.offsets[0] = 0;
+      p.item_offsets[0] = 0;
+      atomicExch(p.scan_done, 0u);
+    }
+    return;
+  }
   int64_t carry = 0, icarry = 0;
   for (int64_t g0 = 0; g0 < nframes; g0 += kScanThreads) {
     const int64_t g = g0 + tid;
