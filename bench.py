@@ -15,6 +15,11 @@ end in device memory. Inputs are resident in HBM before timing starts; two
 1 GiB input buffers alternate so the 256 MB last-level cache cannot serve
 repeated reads.
 
+The same JSON line also reports the other batched workloads (1024 x 256x256
+complex128, 64 radar cubes of 256x128x32, 512 frames of uneven shapes,
+16 x 2048x2048; --skip-workloads leaves them out), a refinement run, the
+SRUR radar cubes, the same-GPU comparators and the CPU oracle on a sample.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 
@@ -467,9 +472,10 @@ def main():
     ap.add_argument("--skip-comparators", action="store_true")
     ap.add_argument("--skip-refine", action="store_true")
     ap.add_argument("--skip-radar", action="store_true")
-    ap.add_argument("--workloads", nargs="?", const="all", default=None,
-                    help="also measure the other batched workloads (all, or a comma-separated "
-                         "list of names; adds about a minute)")
+    ap.add_argument("--workloads", nargs="?", const="all", default="all",
+                    help="the other batched workloads to measure as well: all (default) or a "
+                         "comma-separated list of names (about a minute in all)")
+    ap.add_argument("--skip-workloads", action="store_true")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the fold HBM-traffic summary from two rocprofv3 --pmc "
                          "CSV output folders (FETCH_SIZE, WRITE_SIZE) and exit; no GPU")
@@ -643,7 +649,7 @@ def main():
         out["refine"] = refine_section(dev)
     if not args.skip_radar:
         out["radar"] = radar_section(dev)
-    if args.workloads:
+    if args.workloads and not args.skip_workloads:
         names = None if args.workloads == "all" else args.workloads.split(",")
         out["workloads"] = workloads_section(dev, min(args.steps, 20), args.warmup, names)
 
