@@ -204,7 +204,8 @@ __device__ __forceinline__ void mode_product_r16(float* __restrict__ re, float* 
 
 __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int plane, int pad,
                                                           int frame0, int identity,
-                                                          int nchunks_override) {
+                                                          int nchunks_override,
+                                                          const int32_t* __restrict__ order) {
   extern __shared__ float smem[];
   float* re = smem;
   float* im = smem + plane;
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   __shared__ uint32_t hist[256];
 
   const int s = blockIdx.x;
-  const int64_t f = frame0 + int64_t(blockIdx.y);
+  const int64_t f = order ? int64_t(order[blockIdx.y]) : frame0 + int64_t(blockIdx.y);
   const FrameDesc& d = desc_of(p, f);
   const int64_t rel = rel_of(p, f);
   const int B = d.B;
@@ -386,11 +387,12 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
 }
 
 int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw, int identity,
-               int nchunks_override, void* stream) {
+               int nchunks_override, const int32_t* order, void* stream) {
   if (nframes <= 0) return hipSuccess;
   const size_t shmem = size_t(2 * plane) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
   hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), unsigned(nframes)), dim3(kDftThreads), shmem,
-                     static_cast<hipStream_t>(stream), p, T, plane, pad, 0, identity, nchunks_override);
+                     static_cast<hipStream_t>(stream), p, T, plane, pad, 0, identity, nchunks_override,
+                     order);
   return hipGetLastError();
 }
 
@@ -398,7 +400,7 @@ static int launch_dft_frame(const DevPtrs& p, int64_t frame, int T, int plane, i
                             hipStream_t st) {
   const size_t shmem = size_t(2 * plane) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
   hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), 1u), dim3(kDftThreads), shmem, st, p, T, plane,
-                     pad, int(frame), 1, 1);
+                     pad, int(frame), 1, 1, static_cast<const int32_t*>(nullptr));
   return hipGetLastError();
 }
 

@@ -81,7 +81,8 @@ struct rsft_plan_s {
   int64_t nchunk_list = 0;       // uneven plans with frames of different chunk counts
   int scan_fpb = 1;              // frames per scan work-group
   // device arrays
-  DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles, d_chunk_list;
+  DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles, d_chunk_list,
+      d_dft_order;
   DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
       d_offsets, d_records, d_scan_done, d_chunk_items, d_item_counts, d_item_offsets;
   rsft::DevPtrs ptrs{};
@@ -431,7 +432,8 @@ void free_plan(rsft_plan_s* pl) {
       if (e) (void)hipEventDestroy(e);
   if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
   DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
-                          &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_chunk_list, &pl->d_part,
+                          &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_chunk_list,
+                          &pl->d_dft_order, &pl->d_part,
                           &pl->d_buckets, &pl->d_powers, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
                           &pl->d_scan_done, &pl->d_chunk_items, &pl->d_item_counts, &pl->d_item_offsets};
@@ -550,6 +552,15 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     }
     pl->ntiles_uneven = int64_t(tl.size());
   }
+  // DFT order of an uneven batch: frames by decreasing bucket count (stable),
+  // so that the largest transforms, one work-group each, start first
+  std::vector<int32_t> dft_order;
+  if (!pl->uniform) {
+    for (int64_t i = 0; i < nframes; ++i) dft_order.push_back(int32_t(i));
+    std::stable_sort(dft_order.begin(), dft_order.end(), [&](int32_t a, int32_t b) {
+      return pl->descs[size_t(a)].B > pl->descs[size_t(b)].B;
+    });
+  }
   // compaction chunks of an uneven batch: when frames differ in chunk count,
   // the vote and estimate launches take one work-group per listed chunk
   // instead of a frames x max-chunks grid that is mostly empty. Position p
@@ -587,6 +598,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = upload(pl->d_flat, ht.flat)) != RSFT_OK) return st;
   if ((st = upload(pl->d_tiles, tiles)) != RSFT_OK) return st;
   if ((st = upload(pl->d_chunk_list, chunk_list)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_dft_order, dft_order)) != RSFT_OK) return st;
   if ((st = alloc(pl->d_part, size_t(part_off) * sizeof(float2))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_buckets, size_t(bucket_off) * sizeof(float2))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_powers, size_t(bucket_off) * sizeof(float))) != RSFT_OK) return st;
@@ -693,7 +705,8 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
     if (fs != RSFT_OK) return fs;
   }
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-  LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0, st));
+  LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0,
+                              pl->uniform ? nullptr : static_cast<const int32_t*>(pl->d_dft_order.ptr), st));
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, st));
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));

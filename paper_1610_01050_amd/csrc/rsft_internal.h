@@ -123,8 +123,10 @@ constexpr int kFoldMaxP = 2048;   // largest threads * vec a plan may be tuned t
 int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
                 int64_t tiles_per_frame, int64_t ntiles, int round0, int rounds,
                 int T, const FoldConfig& cfg, void* stream);
+// order (may be NULL): frame of each grid row, e.g. the frames of an uneven
+// batch by decreasing bucket count so that the largest transforms start first
 int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw,
-               int identity_relabel, int nchunks_override, void* stream);
+               int identity_relabel, int nchunks_override, const int32_t* order, void* stream);
 // vote paths: per cell (any shape), rows of 64..4096 cells (T <= 4), rows of
 // exactly 32 cells (bit-parallel masks)
 constexpr int kVoteCells = 0, kVoteRows = 1, kVoteMasks32 = 2;
