@@ -216,9 +216,10 @@ def estimation_rounds(plan):
     L_d + 2 permuted bins of 0 (circularly) for some dimension d and k in
     {1, 2}, neighbouring main-lobe bins of one tone share a bucket (or its
     transition band) and the bucket no longer measures a single cell. A round
-    is clean when that happens for no d and k. The first five clean rounds are
-    used; if none is clean, the single round whose smallest such distance
-    (minus L_d + 2) is largest, the first on ties."""
+    is clean when that happens for no d and k. Every clean round is used
+    (each is an independent measurement of the cell); if none is clean, the
+    single round whose smallest such distance (minus L_d + 2) is largest, the
+    first on ties."""
     scores = []
     for s in range(plan.T):
         worst = None
@@ -230,7 +231,7 @@ def estimation_rounds(plan):
         scores.append(worst)
     clean = [s for s in range(plan.T) if scores[s] >= 0]
     if clean:
-        return clean[:5]
+        return clean
     best = max(scores)
     return [scores.index(best)]
 

@@ -29,23 +29,34 @@ namespace rsft {
 // which is taken on the square roots. FP32 magnitudes, FP64 vertex and
 // frequency.
 //
+// Frames of 1..kMaxEstRounds estimation rounds take kernels specialised on
+// that count (per-round tables in registers, a sorting network for the
+// median). Frames with more (every clean round is used, up to T = 64) take
+// the kEstAny variant, which walks the round mask and sorts each cell's
+// values by insertion into a per-thread array.
+//
 // With at least 16 frames, chunk work-group b serves frames congruent to b
 // mod 8: work-groups are dealt to the eight XCDs round-robin, so each XCD's
 // L2 holds the buckets and flags of only its own frames.
 // ---------------------------------------------------------------------------
 
 constexpr int kEstThreads = 256;
+constexpr int kEstAny = 0;   // template round count of the loop variant (any number of rounds)
 
 // Per-frame constants of the estimate, uniform across the work-group.
 template <int D, int M>
 struct EstFrame {
+  static constexpr int kM = M > 0 ? M : 1;
   uint32_t nm[D], lm[D], ls[D], bs[D], ns[D];
   const float* ig[D];              // inverse flat-window gains per dimension
-  uint32_t sig_est[M][D];
-  const float* pw_est[M];          // squared magnitudes |fhat_s|^2 of the estimation rounds
+  uint32_t sig_est[kM][D];
+  const float* pw_est[kM];         // squared magnitudes |fhat_s|^2 of the estimation rounds
   const uint32_t* fl;              // flags [T][words]
   const int32_t* sig;              // sigma [kMaxRounds][kMaxDims] of the descriptor
   int words;
+  const float* pw;                 // round 0 of the squared magnitudes (kEstAny)
+  uint64_t est_mask;               // the estimation rounds (kEstAny)
+  int B;
 };
 
 template <int D, int M>
@@ -71,6 +82,9 @@ __device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d,
   e.fl = p.flags + d.flag_off + rel * d.flag_stride;
   e.sig = &d.sigma[0][0];
   e.words = d.words;
+  e.pw = pw;
+  e.est_mask = d.est_mask;
+  e.B = d.B;
 }
 
 // Median of M values (an odd-even transposition network on fixed indices);
@@ -162,6 +176,45 @@ __device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, co
   return median_of<M>(v);
 }
 
+// The same for any number of estimation rounds (kEstAny): the rounds of the
+// mask in increasing order, each value inserted into a sorted per-thread
+// array, then the median as in median_of.
+template <int D, int M>
+__device__ __forceinline__ float neighbour_power_any(const EstFrame<D, M>& e, const uint32_t (&cell)[D],
+                                                     int code) {
+  float v[kMaxRounds];
+  int n = 0;
+  uint64_t rest = e.est_mask;
+  while (rest) {
+    const int s = __builtin_ctzll(rest);
+    rest &= rest - 1ull;
+    uint32_t jf = 0u;
+    float gg = 1.f;
+    int c = code;
+#pragma unroll
+    for (int dd = D - 1; dd >= 0; --dd) {
+      const int o = c % 3 - 1;
+      c /= 3;
+      const uint32_t sg = uint32_t(e.sig[s * kMaxDims + dd]);
+      const uint32_t u = (sg * cell[dd] + sg * uint32_t(o)) & e.nm[dd];
+      const float ig = e.ig[dd][u & e.lm[dd]];
+      gg *= ig * ig;
+      jf |= (u >> e.ls[dd]) << e.bs[dd];
+    }
+    const float x = e.pw[int64_t(s) * e.B + jf] * gg;
+    int k = n;
+    while (k > 0 && v[k - 1] > x) {
+      v[k] = v[k - 1];
+      --k;
+    }
+    v[k] = x;
+    ++n;
+  }
+  if (n & 1) return v[n / 2];
+  const float a = 0.5f * (sqrtf(v[n / 2 - 1]) + sqrtf(v[n / 2]));
+  return a * a;
+}
+
 // True when neighbour `code` differs from the cell in at most one dimension
 // (base-3 digits: 1 is offset 0).
 constexpr bool on_axis(int code, int D) {
@@ -224,7 +277,19 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
   };
   float preg[kRegs ? kNb : 1];
   bool peak = true;
-  if constexpr (kRegs) {
+  if constexpr (kRegs && M == kEstAny) {
+#pragma unroll
+    for (int code = 0; code < kNb; ++code)
+      if (on_axis(code, D)) preg[code] = neighbour_power_any<D, M>(e, cell, code);
+#pragma unroll
+    for (int code = 0; code < kNb; ++code)
+      if (code != kCentre && on_axis(code, D)) visit(code, preg[kCentre], preg[code], peak);
+    if (peak) {
+#pragma unroll
+      for (int code = 0; code < kNb; ++code)
+        if (!on_axis(code, D)) visit(code, preg[kCentre], neighbour_power_any<D, M>(e, cell, code), peak);
+    }
+  } else if constexpr (kRegs) {
     // Per round and dimension the three offsets o_d = -1, 0, 1 share one
     // permuted index, [sigma (c + o)]_N = [sigma c + sigma o]_N, so their
     // squared inverse gains and bucket offsets are formed once.
@@ -261,14 +326,19 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
         if (!on_axis(code, D)) visit(code, preg[kCentre], neighbour_power<D, M>(e, g, jb, code), peak);
     }
   } else {
-    uint32_t u0[M][D];
-#pragma unroll
-    for (int q = 0; q < M; ++q) {
-#pragma unroll
-      for (int dd = 0; dd < D; ++dd) u0[q][dd] = e.sig_est[q][dd] * cell[dd];
-    }
+    if constexpr (M == kEstAny) {
 #pragma unroll 1
-    for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_dyn<D, M>(e, u0, code);
+      for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_any<D, M>(e, cell, code);
+    } else {
+      uint32_t u0[M][D];
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) u0[q][dd] = e.sig_est[q][dd] * cell[dd];
+      }
+#pragma unroll 1
+      for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_dyn<D, M>(e, u0, code);
+    }
     const float pc0 = pcol[kCentre * kEstThreads];
 #pragma unroll 1
     for (int code = 0; code < kNb; ++code)
@@ -333,15 +403,20 @@ __device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc&
 // registers fit in 96 VGPRs, fewer for the larger neighbourhoods (D = 4 keeps
 // its neighbourhood in 81 KB of LDS: one work-group per compute unit).
 constexpr int est_waves(int D, int M) {
-  return D <= 1 || (D == 2 && M <= 3) ? 5 : D == 2 ? 4 : D == 3 ? 2 : 1;
+  return M == kEstAny ? (D >= 4 ? 1 : 2) : D <= 1 || (D == 2 && M <= 3) ? 5 : D == 2 ? 4 : D == 3 ? 2 : 1;
 }
 
-// estimate_list for a frame of `ne` estimation rounds, 1 <= ne <= MMAX.
+// estimate_list for a frame of `ne` estimation rounds, 1 <= ne <= MMAX
+// (MMAX = kEstAny: any count, by the loop variant).
 template <int D, int MMAX>
 __device__ __forceinline__ void estimate_list_n(int ne, const DevPtrs& p, const FrameDesc& d, int64_t f,
                                                 int64_t rel, int T, const uint32_t* list, int n,
                                                 unsigned long long cell0, rsft_detection* out,
                                                 int64_t room, float* pcol, rsft_detection* stage) {
+  if constexpr (MMAX == kEstAny) {
+    estimate_list<D, kEstAny>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage);
+    return;
+  }
   switch (ne) {
     case 1: if constexpr (MMAX >= 1) estimate_list<D, 1>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
     case 2: if constexpr (MMAX >= 2) estimate_list<D, 2>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
@@ -434,6 +509,14 @@ __device__ __forceinline__ bool chunk_of(const DevPtrs& p, int64_t b, int64_t nf
   return f < nframes;
 }
 
+// Whether the kernel built for M rounds serves a frame of ne estimation
+// rounds: the specialised kernels take 1..M (one launch per plan, built for
+// the plan's largest count up to kMaxEstRounds), the kEstAny kernel the
+// frames beyond kMaxEstRounds.
+__host__ __device__ constexpr bool serves(int M, int ne) {
+  return M == kEstAny ? ne > kMaxEstRounds : (ne >= 1) & (ne <= M);
+}
+
 // Without overflow workers: one work-group per (frame, chunk) builds all of
 // the chunk's records; a chunk of up to kListMax detections is listed in one
 // pass, a denser one in passes of kListMax cells.
@@ -458,7 +541,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
   // each loaded together before they are tested (no chain of dependent
   // loads behind early exits).
   const int cch = d.cchunks, nd = d.ndim, ne = d.n_est;
-  if ((c >= cch) | (nd != D) | (ne < 1) | (ne > M)) return;
+  if ((c >= cch) | (nd != D) | !serves(M, ne)) return;
   const int64_t rel = rel_of(p, f);
   const int64_t ck = d.chunk_off + rel * d.chunk_stride + c;
   const int64_t cap = d.cap;
@@ -604,7 +687,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
         fend = p.item_offsets[f + 1];
         if (fend <= i) return;                         // item_offsets is non-decreasing
         const FrameDesc& d = desc_of(p, f);
-        if ((d.ndim != D) | (d.n_est < 1) | (d.n_est > M)) {   // another launch's frame
+        if ((d.ndim != D) | !serves(M, d.n_est)) {   // another launch's frame
           i = fend;
           continue;
         }
@@ -631,7 +714,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
     } else {
       dp = &desc_of(p, f);
       const int cch = dp->cchunks, nd = dp->ndim, ne = dp->n_est;
-      if ((c >= cch) | (nd != D) | (ne < 1) | (ne > M)) return;
+      if ((c >= cch) | (nd != D) | !serves(M, ne)) return;
       const int64_t rel = rel_of(p, f);
       const int64_t ck = dp->chunk_off + rel * dp->chunk_stride + c;
       const uint32_t* bm = p.bitmap + dp->bitmap_off + rel * dp->bitmap_stride;
@@ -669,11 +752,13 @@ static void launch_estimate_d(const DevPtrs& p, dim3 grid, int og, hipStream_t s
       hipLaunchKernelGGL((compact_estimate_kernel<D, M>), grid, dim3(kEstThreads), 0, st, p, T, nframes,  \
                          max_cchunks, xcd, use_list);                                                    \
   } while (0)
-  if (est_mask >= 32) RSFT_EST(5);
-  else if (est_mask >= 16) RSFT_EST(4);
-  else if (est_mask >= 8) RSFT_EST(3);
-  else if (est_mask >= 4) RSFT_EST(2);
-  else if (est_mask >= 2) RSFT_EST(1);
+  const int small = est_mask & ((2 << kMaxEstRounds) - 1);
+  if (small >= 32) RSFT_EST(5);
+  else if (small >= 16) RSFT_EST(4);
+  else if (small >= 8) RSFT_EST(3);
+  else if (small >= 4) RSFT_EST(2);
+  else if (small >= 2) RSFT_EST(1);
+  if (est_mask >> (kMaxEstRounds + 1)) RSFT_EST(kEstAny);
 #undef RSFT_EST
 }
 

@@ -183,9 +183,8 @@ struct HostTables {
 
 // Rounds feeding magnitude estimates: a round is clean when no dimension d
 // and k in {1, 2} has |[sigma_{s,d} k]_{N_d}| (circular) < L_d + 2, i.e. the
-// main-lobe bins of one tone never share a bucket; the first (up to
-// kMaxEstRounds) clean rounds are used, else the one whose worst distance is
-// largest (first on ties).
+// main-lobe bins of one tone never share a bucket; every clean round is
+// used, else the one whose worst distance is largest (first on ties).
 uint64_t estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma) {
   std::vector<int64_t> score(static_cast<size_t>(p.rounds));
   uint64_t mask = 0;
@@ -200,7 +199,7 @@ uint64_t estimation_mask(const rsft_params& p, const std::vector<int64_t>& sigma
       }
     }
     score[size_t(s)] = worst;
-    if (worst >= 0 && __builtin_popcountll(mask) < rsft::kMaxEstRounds) mask |= uint64_t(1) << s;
+    if (worst >= 0) mask |= uint64_t(1) << s;
   }
   if (mask) return mask;
   int best = 0;
@@ -266,7 +265,10 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
   d.est_mask = estimation_mask(p, sigma);
   d.n_est = 0;
   for (int s = 0; s < T; ++s)
-    if ((d.est_mask >> s) & 1u) d.est_rounds[d.n_est++] = s;
+    if ((d.est_mask >> s) & 1u) {
+      if (d.n_est < rsft::kMaxEstRounds) d.est_rounds[d.n_est] = s;
+      ++d.n_est;
+    }
 
   // windows (Sec. III-C.1, Sec. IV-B) per dimension, FP64
   const double flat_db = p.flat_atten_db < 0.0 ? p.window_atten_db : p.flat_atten_db;
@@ -505,7 +507,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     pl->max_words = std::max(pl->max_words, d.words);
     pl->max_cchunks = std::max(pl->max_cchunks, d.cchunks);
     pl->dims_mask |= 1 << (d.ndim - 1);
-    pl->est_nmask |= 1 << d.n_est;
+    pl->est_nmask |= 1 << std::min(d.n_est, rsft::kMaxEstRounds + 1);
     if (d.n_last < 64 || d.n_last > 4096) pl->rows_ok = 0;
     if (d.n_last != 32) pl->masks_ok = 0;
     int sum_tw = 0;

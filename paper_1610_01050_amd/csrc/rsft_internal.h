@@ -17,7 +17,7 @@ constexpr int kCompactShift = 15;         // cells per compaction chunk = 2^15
 constexpr int kChunkRecords = 1024;       // records a chunk's work-group builds at a time (and,
                                           // with overflow workers, in all)
 constexpr int kItemShift = 8;             // records per overflow item = 2^8
-constexpr int kMaxEstRounds = 5;          // rounds feeding a magnitude estimate
+constexpr int kMaxEstRounds = 5;          // estimation rounds of the specialised estimate kernels
 constexpr int kFoldRoundGroup = 4;        // rounds folded per pass over the input
 
 // Everything a kernel needs to know about one frame descriptor. Lives in
@@ -45,8 +45,8 @@ struct FrameDesc {
   int32_t fold_nl, fold_bl, fold_bin, fold_lw;
   int32_t words;              // flag words per round = ceil(B / 32)
   int32_t cap;                // detection capacity of a frame
-  int32_t n_est;              // rounds used for magnitude estimates (<= kMaxEstRounds)
-  int32_t est_rounds[kMaxEstRounds];  // their indices
+  int32_t n_est;              // rounds used for magnitude estimates (1..T)
+  int32_t est_rounds[kMaxEstRounds];  // the first min(n_est, kMaxEstRounds) of them
   uint64_t est_mask;                   // the same rounds as a bit mask
   int32_t sigma[kMaxRounds][kMaxDims];
   int32_t sigma_inv[kMaxRounds][kMaxDims];
@@ -137,7 +137,8 @@ int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunk
 // workers); fpb: frames per work-group (1, or 256 / chunks per frame in a
 // uniform plan of at most 128 chunks per frame)
 int launch_scan(const DevPtrs& p, int64_t nframes, int items, int fpb, void* stream);
-// est_mask: bit m set when some frame uses m estimation rounds (1..5)
+// est_mask: bit m set when some frame uses m estimation rounds (1..5); bit 6
+// when some frame uses more (the loop variant)
 // workers: 1 adds overflow workers (two per compute unit of the num_cus)
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
                     int est_mask, int workers, int num_cus, int64_t nlist, void* stream);

@@ -107,6 +107,15 @@ def test_estimation_rounds_rule():
     # round 1 has [513*2]_1024 = 2 -> 2 - 18, round 2 has 1023 -> 1 - 18
     # (and 3 -> 3 - 18): the least contaminated is round 0
     assert R.estimation_rounds(plan) == [0]
+    # eight rounds, the odd-numbered ones clean (|[sigma k]| >= 18 for k = 1, 2)
+    # and the even-numbered ones not (sigma = 5 in dimension 0): every clean
+    # round is used, however many there are
+    sig = [[5, 301] if s % 2 == 0 else [101 + 2 * s, 301] for s in range(8)]
+    plan = R.OraclePlan(shape, b, sig, 60, None, 1e-3)
+    assert R.estimation_rounds(plan) == [1, 3, 5, 7]
+    sig = [[101 + 2 * s, 301 + 2 * s] for s in range(12)]
+    plan = R.OraclePlan(shape, b, sig, 60, None, 1e-3)
+    assert R.estimation_rounds(plan) == list(range(12))
 
 
 def test_noise_free_offgrid_estimate_matches_dense():
@@ -173,6 +182,72 @@ def test_bartlett_gamma_threshold_and_roc():
         pd_mc = np.mean(sig >= gamma_n)
         pd_cf = Dn.bartlett_roc_pd(pfa, T, snr, alpha_p, beta_p)
         assert abs(pd_mc - pd_cf) < 0.03
+
+
+def _erlang_survival(x, T):
+    """P[Gamma(T, 1) >= x] for integer T: exp(-x) sum_{k<T} x^k / k! (the
+    Poisson sum identity of the Erlang law, written out)."""
+    term = 1.0
+    acc = 1.0
+    for k in range(1, T):
+        term *= x / k
+        acc += term
+    return math.exp(-x) * acc
+
+
+def test_bartlett_detect_threshold_is_erlang_quantile():
+    """Alg. 2 over T segments (Appendix A): a noise-only bin of the summed
+    statistic is a sum of T independent exponentials of mean
+    sigma_n^2 ||w||^2, so the threshold bartlett_detect returns must sit where
+    the Erlang(T) survival function equals Pfa (closed form, no quantile
+    routine involved)."""
+    shape = (8, 8)
+    w = [W.dolph_chebyshev(8, 60)] * 2
+    zeta2 = 2.5 * Dn.window_energy(w)
+    for T in (2, 3, 5, 10):
+        for pfa in (1e-2, 1e-4, 1e-6):
+            segs = [np.zeros(shape, np.complex128)] * T
+            _, _, thr = Dn.bartlett_detect(segs, w, pfa, noise_var=2.5)
+            assert abs(_erlang_survival(thr / zeta2, T) - pfa) <= 1e-9 * pfa
+
+
+def test_bartlett_detect_two_segment_sum_by_hand():
+    """Two segments on a 4x4 grid with rectangular windows: segment 0 is a
+    unit impulse at the origin (flat spectrum 1 on every bin), segment 1 the
+    on-grid tone 3 exp(j 2 pi (m0 + 2 m1) / 4) (16 * 3 on bin (1, 2), zero
+    elsewhere). The summed statistic is 1 + 48^2 on bin (1, 2) and 1
+    elsewhere; with sigma_n^2 = 0.1 and ||w||^2 = 16 the Pfa = 1e-3 threshold
+    lies between, so exactly that bin is detected."""
+    shape = (4, 4)
+    w = [np.ones(4)] * 2
+    r0 = np.zeros(shape, np.complex128)
+    r0[0, 0] = 1.0
+    m0, m1 = np.meshgrid(np.arange(4), np.arange(4), indexing="ij")
+    r1 = 3.0 * np.exp(2j * np.pi * (m0 + 2 * m1) / 4)
+    det, x, thr = Dn.bartlett_detect([r0, r1], w, 1e-3, noise_var=0.1)
+    want = np.ones(shape)
+    want[1, 2] += 48.0 ** 2
+    assert np.allclose(x, want, rtol=0, atol=1e-9)
+    assert 1.0 < thr < want[1, 2]
+    assert list(det) == [int(np.ravel_multi_index((1, 2), shape))]
+
+
+def test_bartlett_detect_empirical_pfa_over_segments():
+    """Noise-only input split into T = 4 independent segments: the per-bin
+    false-alarm rate of bartlett_detect's summed statistic matches the design
+    Pfa = 1e-2. Bins of one frame are correlated by the window, so the
+    standard error is taken over frames."""
+    shape = (64, 64)
+    w = [W.dolph_chebyshev(64, 60)] * 2
+    pfa, T, frames = 1e-2, 4, 160
+    rates = []
+    for f in range(frames):
+        segs = [synth.noise_only(shape, 11 + s, f, dtype=np.complex128) for s in range(T)]
+        det, x, _ = Dn.bartlett_detect(segs, w, pfa)
+        rates.append(len(det) / x.size)
+    rates = np.array(rates)
+    se = rates.std(ddof=1) / math.sqrt(frames)
+    assert abs(rates.mean() - pfa) < 4 * se + 1e-4
 
 
 def test_pd_pfa_scoring():
