@@ -312,6 +312,25 @@ rsft_status rsft_model_forward(rsft_plan_t plan, const double* d_freqs, const vo
                                void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rsft_model_forward without a workspace. The per-dimension factors go to
+ * a static device array of the library instead, RSFT_STATIC_SCRATCH_BYTES
+ * bytes on each GPU the library runs on, held until the process ends. The
+ * call allocates nothing; the caller passes inputs and outputs as for
+ * rsft_model_forward (d_model receives the same values) and the plan's
+ * device must be the current device. Every call on a GPU shares that GPU's
+ * array and overwrites it (it holds the last call's factors, usable by no
+ * other call), so calls that overlap on one GPU race: issue them on one
+ * stream, or order them. Errors: as rsft_model_forward; UNSUPPORTED when
+ * the factors, 2 * batch * T * tones * (sum_d B_d) * 8 bytes, exceed the
+ * array; INVALID_ARGUMENT when the current device is not the plan's.
+ */
+#define RSFT_STATIC_SCRATCH_BYTES (8 << 20)
+rsft_status rsft_model_forward_noalloc(rsft_plan_t plan, const double* d_freqs, const void* d_amps,
+                                       int64_t batch, int32_t tones, void* d_model, void* stream);
+
+/*
  * Gradients of a real loss through the model, given the output gradient
  * d_grad_model = dL/dRe(model) + j dL/dIm(model) (layout of d_model):
  *   d_grad_amps[f][t]     = sum_{s,k} grad_s[k] conj(prod_d G_{s,d}(f_t)[k_d])

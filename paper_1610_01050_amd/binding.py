@@ -42,7 +42,8 @@ SYMBOLS = (
     "rsft_destroy", "rsft_status_string", "rsft_last_error",
     "rsft_chebyshev_window", "rsft_flat_window", "rsft_mod_inverse",
     "rsft_stage1_probability", "rsft_draw_sigma",
-    "rsft_model_workspace_size", "rsft_model_forward", "rsft_model_backward",
+    "rsft_model_workspace_size", "rsft_model_forward", "rsft_model_forward_noalloc",
+    "rsft_model_backward",
     "rsft_design_thresholds",
 )
 
@@ -170,6 +171,7 @@ def load_library(path=None):
                                             ctypes.POINTER(ctypes.c_double)]
     lib.rsft_model_workspace_size.argtypes = [vp, i64, ctypes.c_int32, ctypes.POINTER(i64)]
     lib.rsft_model_forward.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp]
+    lib.rsft_model_forward_noalloc.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp]
     lib.rsft_model_backward.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     lib.rsft_design_thresholds.argtypes = [ctypes.POINTER(DesignParams),
                                            ctypes.POINTER(DesignResult)]
@@ -509,6 +511,16 @@ class Plan:
             self._h, ctypes.c_void_p(freqs.data_ptr()), ctypes.c_void_p(amps.data_ptr()), batch, K,
             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
             _stream_handle(stream)))
+        return out
+
+    def model_forward_noalloc(self, freqs, amps, out, stream=None):
+        """model_forward into the caller's `out` with the factors in the
+        library's static scratch array (no allocation anywhere; the factors
+        are not kept for a backward call)."""
+        batch, K = self._model_args(freqs, amps)
+        _check(self._lib, self._lib.rsft_model_forward_noalloc(
+            self._h, ctypes.c_void_p(freqs.data_ptr()), ctypes.c_void_p(amps.data_ptr()), batch, K,
+            ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
     def model_backward(self, amps, grad_model, workspace, steps=False, stream=None):

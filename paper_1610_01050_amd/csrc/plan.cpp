@@ -950,6 +950,31 @@ rsft_status rsft_model_forward(rsft_plan_t pl, const double* d_freqs, const void
   return RSFT_OK;
 }
 
+rsft_status rsft_model_forward_noalloc(rsft_plan_t pl, const double* d_freqs, const void* d_amps,
+                                       int64_t batch, int32_t tones, void* d_model, void* stream) {
+  rsft_status st = check_model(pl, batch, tones);
+  if (st != RSFT_OK) return st;
+  if (!d_freqs || !d_amps || !d_model) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL pointer");
+  const int64_t need = 2 * model_factor_count(pl, batch, tones) * int64_t(sizeof(float) * 2);
+  if (need > int64_t(RSFT_STATIC_SCRATCH_BYTES))
+    return fail(RSFT_ERROR_UNSUPPORTED, "model factors need " + std::to_string(need) +
+                                            " bytes, more than the static scratch of " +
+                                            std::to_string(int64_t(RSFT_STATIC_SCRATCH_BYTES)) +
+                                            " bytes (2 * batch * T * tones * sum_d B_d * 8)");
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != pl->device) return fail(RSFT_ERROR_INVALID_ARGUMENT, "the current device is not the plan's device");
+  void* ws = nullptr;
+  LAUNCH_TRY(rsft::static_scratch(cur, &ws));
+  const int D = pl->descs[0].ndim;
+  float2* G = static_cast<float2*>(ws);
+  float2* dG = G + model_factor_count(pl, batch, tones);
+  LAUNCH_TRY(rsft::launch_model_forward(pl->ptrs, d_freqs, static_cast<const float2*>(d_amps), batch,
+                                        tones, D, pl->T, pl->maxB, pl->sum_tw_max, G, dG,
+                                        static_cast<float2*>(d_model), stream));
+  return RSFT_OK;
+}
+
 rsft_status rsft_model_backward(rsft_plan_t pl, const void* d_amps, int64_t batch, int32_t tones,
                                 const void* d_grad_model, double* d_grad_freqs, void* d_grad_amps,
                                 double* d_step_freqs, void* d_step_amps, const void* d_workspace,

@@ -30,9 +30,34 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "rsft_internal.h"
 
 namespace rsft {
+
+// Scratch of the model's factors for callers that cannot allocate
+// (rsft_model_forward_noalloc): a static device array, one copy per GPU,
+// held from module load until the process ends. Host code never uses its
+// name as an address: static_scratch() resolves the device address once per
+// device, with that device current, and every launch takes that pointer.
+static __device__ __align__(256) unsigned char scratch[RSFT_STATIC_SCRATCH_BYTES];
+
+int static_scratch(int device, void** out) {
+  constexpr int kMaxScratchDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxScratchDevices] = {};
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
 
 constexpr int kBasisThreads = 256;
 constexpr int kCombineThreads = 256;

@@ -152,6 +152,9 @@ int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int plane, int pad,
 int launch_model_forward(const DevPtrs& p, const double* freqs, const float2* amps, int64_t batch,
                          int K, int D, int T, int maxB, int sum_b, float2* G, float2* dG,
                          float2* model, void* stream);
+// Device address of the library's static scratch array on `device`, which
+// must be the current device (resolved once per device, then cached).
+int static_scratch(int device, void** out);
 int launch_model_backward(const DevPtrs& p, const float2* amps, int64_t batch, int K, int T,
                           int sum_b, const float2* G, const float2* dG, const float2* grad_model,
                           double* grad_freqs, float2* grad_amps, double* step_freqs,
