@@ -149,6 +149,68 @@ def summarize_counters(fetch_dir, write_dir, command_fetch, command_write):
     print(json.dumps(out, indent=1))
 
 
+def _short_kernel_name(name):
+    """A kernel's name without its argument list and namespace."""
+    n = name.split("(")[0]
+    return n.replace("rsft::", "").replace("void ", "").strip()
+
+
+def summarize_trace(directory, title, command):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run: per
+    kernel, calls, average / min / max duration (us) and share of the GPU
+    time, from the kernel_stats.csv files under `directory`."""
+    import csv
+    import glob
+    rows = {}
+    for path in glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True):
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                k = _short_kernel_name(r["Name"])
+                c = rows.setdefault(k, [0, 0.0, math.inf, 0.0])
+                calls = int(r["Calls"])
+                c[0] += calls
+                c[1] += float(r["TotalDurationNs"])
+                c[2] = min(c[2], float(r["MinNs"]))
+                c[3] = max(c[3], float(r["MaxNs"]))
+    if not rows:
+        raise SystemExit(f"no kernel_stats.csv under {directory}")
+    total = sum(v[1] for v in rows.values())
+    lines = [f"# {title}", "", "Command (from the repository root `R` on an MI355X, ROCm 7.2 rocprofv3):",
+             "", "```", command, "```", "",
+             "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for k, v in sorted(rows.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| `{k}` | {v[0]} | {v[1] / v[0] / 1e3:.1f} | {v[2] / 1e3:.1f} | {v[3] / 1e3:.1f} | "
+                     f"{100 * v[1] / total:.1f}% |")
+    print("\n".join(lines))
+
+
+def summarize_pmc(directories, title, commands, kernels):
+    """Markdown summary of rocprofv3 --pmc runs: for each kernel whose name
+    contains one of `kernels`, the number of dispatches and each counter's
+    average per dispatch, from the counter_collection.csv files under the
+    given directories (one run per counter pass)."""
+    per = {}
+    for directory in directories:
+        for name, counter, value in _counter_rows(directory):
+            k = _short_kernel_name(name)
+            if kernels and not any(q in k for q in kernels):
+                continue
+            per.setdefault(k, {}).setdefault(counter, []).append(value)
+    counters = sorted({c for v in per.values() for c in v})
+    lines = [f"# {title}", "", "Commands (from the repository root `R` on an MI355X, ROCm 7.2 rocprofv3):",
+             "", "```"] + list(commands) + ["```", "",
+             "Average per dispatch (SQ counters are summed over the chip; cycle counters of "
+             "the SQ are in quad-cycles where rocprofv3 documents them so).", "",
+             "| Kernel | Dispatches | " + " | ".join(counters) + " |",
+             "|---|---|" + "---|" * len(counters)]
+    for k, v in sorted(per.items()):
+        n = max(len(x) for x in v.values())
+        cells = [f"{np.mean(v[c]):,.0f}" if c in v else "" for c in counters]
+        lines.append(f"| `{k}` | {n} | " + " | ".join(cells) + " |")
+    print("\n".join(lines))
+
+
 def score(recs, counts, metas, shape, frames):
     hits = tgt = fa = outside = 0
     D = len(shape)
@@ -172,11 +234,13 @@ def cpu_baseline(frames_np, metas, shape, buckets, sigma, pfa, nsample):
     with threadpool_limits(limits=1):
         plan = oracle_rsft.OraclePlan(shape, buckets, sigma, 60.0, None, pfa)
         dets = []
+        outs = []
         t0 = time.perf_counter()
         for f in range(nsample):
             out = oracle_rsft.rsft(frames_np[f], plan)
-            oracle_rsft.estimate(out["detections"], out["buckets"], plan)
+            out["estimates"] = oracle_rsft.estimate(out["detections"], out["buckets"], plan)
             dets.append(out["detections"])
+            outs.append(out)
         dt = time.perf_counter() - t0
     hits = tgt = fa = outside = 0
     for f in range(nsample):
@@ -189,35 +253,133 @@ def cpu_baseline(frames_np, metas, shape, buckets, sigma, pfa, nsample):
             "sample": f"first {nsample} of the {FRAMES} frames of this workload: literal "
                       f"FP64 Algorithm 1 plus the estimate of every detection (numpy, "
                       f"one thread), {dt:.1f} s",
-            "pd": hits / max(tgt, 1), "pfa": fa / max(outside, 1)}, dets
+            "pd": hits / max(tgt, 1), "pfa": fa / max(outside, 1)}, dets, outs
 
 
-def refine_section(dev, steps=20):
-    """Gauss-Newton refinement through the bucketized forward model on 16
-    frames of 2048x2048 (K = 32 off-grid tones, B = 128x128): observed buckets
-    from the fused RSFT of the frames, start = truth perturbed by N(0, 0.1 bin)
-    in frequency and 10% in amplitude; `steps` steps timed with events."""
+def host_cpu():
+    """The host's CPU model (from /proc/cpuinfo), its logical CPU count
+    (os.cpu_count, what nproc reports without limits) and the CPUs this
+    process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "cpus_allowed": allowed}
+
+
+def dense_cpu_leg(frames_np, shape, atten_db, pfa, nsample, workers):
+    """The dense detector on the host: windowed 2-D FFT with
+    scipy.fft.fftn(workers=...), |X|^2 and the exact exponential threshold
+    sigma_n^2 ||w||^2 ln(1/Pfa) (Algorithm 2, one segment), on the first
+    `nsample` frames; frames/s."""
+    import scipy.fft
+    from oracle import windows as oracle_windows
+    w = np.multiply.outer(oracle_windows.dolph_chebyshev(shape[0], atten_db),
+                          oracle_windows.dolph_chebyshev(shape[1], atten_db))
+    thr = float(np.sum(w ** 2)) * math.log(1.0 / pfa)
+    t0 = time.perf_counter()
+    for f in range(nsample):
+        X = scipy.fft.fftn(frames_np[f].astype(np.complex128) * w, workers=workers)
+        np.flatnonzero((X.real ** 2 + X.imag ** 2) >= thr)
+    dt = time.perf_counter() - t0
+    return {"value": nsample / dt, "unit": "frames/s", "workers": workers,
+            "sample": f"first {nsample} frames: FP64 windowed fftn + |X|^2 + threshold, {dt:.1f} s"}
+
+
+def precision_report(gpu_buckets, gpu_flags, recs, outs, shape, buckets):
+    """The FP32 path against the FP64 oracle on the same frames, stage by
+    stage: bucket errors per round relative to the round's rms (max and
+    99th percentile), first-stage flags that differ and how close their
+    oracle power was to the threshold (|P - gamma| / gamma), detection-set
+    differences, and for the detections both report, the magnitude's
+    relative error and (cells both call peaks) the off-grid frequency's
+    error in bins."""
+    T = len(outs[0]["buckets"])
+    B = int(np.prod(buckets))
+    D = len(shape)
+    bmax, bp99 = [], []
+    flips, flip_band = 0, 0.0
+    sym, common = 0, 0
+    mag, frq = [], []
+    peak_diff = 0
+    for f, o in enumerate(outs):
+        g = gpu_buckets[f].reshape((T,) + tuple(buckets))
+        for r in range(T):
+            rms = np.sqrt(np.mean(np.abs(o["buckets"][r]) ** 2))
+            e = np.abs(g[r] - o["buckets"][r]).ravel() / rms
+            bmax.append(float(e.max()))
+            bp99.append(float(np.percentile(e, 99)))
+        words = gpu_flags[f].reshape(T, -1).astype(np.uint32)
+        j = np.arange(B)
+        gfl = ((words[:, j // 32] >> (j % 32).astype(np.uint32)) & 1).astype(bool)
+        ofl = o["flags"].reshape(T, -1)
+        diff = gfl != ofl
+        if diff.any():
+            pw = np.abs(o["buckets"].reshape(T, -1)) ** 2
+            band = np.abs(pw - o["gamma"][:, None]) / o["gamma"][:, None]
+            flips += int(diff.sum())
+            flip_band = max(flip_band, float(band[diff].max()))
+        sel = recs[recs["frame"] == f]
+        cells = np.ravel_multi_index(tuple(sel["idx"][:, d].astype(np.int64) for d in range(D)), shape)
+        gmap = {int(c): r for c, r in zip(cells, sel)}
+        est = {e["cell"]: e for e in o["estimates"]}
+        sym += len(set(gmap) ^ set(est))
+        for c in set(gmap) & set(est):
+            common += 1
+            r, e = gmap[c], est[c]
+            mag.append(abs(float(r["magnitude"]) / e["magnitude"] - 1))
+            if bool(r["is_peak"]) != e["is_peak"]:
+                peak_diff += 1
+            elif e["is_peak"]:
+                frq.append(max(abs(((float(r["freq"][d]) - e["freq"][d] + 0.5) % 1.0) - 0.5) * shape[d]
+                               for d in range(D)))
+    mag = np.array(mag) if mag else np.zeros(1)
+    frq = np.array(frq) if frq else np.zeros(1)
+    return {"frames": len(outs),
+            "bucket_rel_err": {"max": max(bmax), "p99_max_over_rounds": max(bp99)},
+            "flag_flips": flips, "flip_max_distance_to_threshold": flip_band,
+            "detections_common": common, "detections_differing": sym,
+            "magnitude_rel_err": {"median": float(np.median(mag)), "max": float(mag.max())},
+            "peak_flag_differences": peak_diff,
+            "peak_freq_err_bins": {"p99": float(np.percentile(frq, 99)), "max": float(frq.max())}}
+
+
+def refine_section(dev, steps=20, oracle_frames=1):
+    """Detect -> estimate -> refine on 16 frames of 2048x2048 (K = 32
+    off-grid tones, B = 128x128): the fused RSFT of the frames, the 32
+    strongest peaks of each frame as starting frequencies, their starting
+    amplitudes from the buckets (rsft_initial_amplitudes), then `steps`
+    refinement steps (rsft_refine) timed with events. Every true tone within
+    one bin of a starting peak is scored before and after; the FP64 oracle
+    refines the first `oracle_frames` frames from the same start and
+    observed buckets."""
     import torch
     from paper_1610_01050_amd import Plan
-    from paper_1610_01050_amd.refine import refine
+    from paper_1610_01050_amd.refine import refine, select_tones
     cfg = synth.WORKLOADS["offgrid_2048x2048"]
     F, K = 16, cfg["K"]
     shape = cfg["shape"]
+    D = len(shape)
     log(f"refinement: generating {F} frames {shape} ...")
     frames, metas = synth.make_batch("offgrid_2048x2048", F)
-    plan = Plan(shape, cfg["buckets"], rounds=cfg["rounds"], sigma=synth.shared_sigma("offgrid_2048x2048"),
-                pfa=cfg["pfa"], max_batch=F)
+    sigma = synth.shared_sigma("offgrid_2048x2048")
+    plan = Plan(shape, cfg["buckets"], rounds=cfg["rounds"], sigma=sigma, pfa=cfg["pfa"], max_batch=F,
+                max_detections=1 << 17)
     x = torch.from_numpy(frames).to(dev)
     plan.execute(x)
+    recs, _ = plan.detect()
     obs = torch.cat([b.reshape(-1) for b in plan.buckets()]).contiguous()
-    truth_f = np.stack([m["freqs"] for m in metas])
-    truth_a = np.stack([m["amps"] for m in metas])
-    rng = np.random.default_rng(1610)
-    start_f = truth_f + rng.normal(0.0, 0.1, truth_f.shape) / np.array(shape)
-    start_a = truth_a * (1 + 0.1 * (rng.standard_normal(truth_a.shape)
-                                    + 1j * rng.standard_normal(truth_a.shape)) / np.sqrt(2))
-    f0 = torch.tensor(start_f, dtype=torch.float64, device=dev)
-    a0 = torch.tensor(start_a.astype(np.complex64), device=dev)
+    f0, a0, passed = select_tones(plan, recs, K, observed=obs)
+    start = f0.cpu().numpy()
     refine(plan, obs, f0, a0, steps=2, record_loss=False)          # warm-up
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -228,30 +390,72 @@ def refine_section(dev, steps=20):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     _, _, losses = refine(plan, obs, f0, a0, steps=steps, record_loss=True)
-    losses = losses.cpu().numpy()
+    losses = losses.cpu().numpy().sum(axis=1)
+    end = fr.cpu().numpy()
+    amp0 = a0.cpu().numpy()
+    amp1 = ar.cpu().numpy()
 
-    def err(f):
-        e = (((f - truth_f + 0.5) % 1.0) - 0.5) * np.array(shape)
-        return float(np.sqrt(np.mean(e ** 2))), float(np.max(np.abs(e)))
+    def circ(a, b):
+        return (((a - b + 0.5) % 1.0) - 0.5) * np.array(shape)
 
-    # loss of the true parameters: a fit at or below it is noise-limited
-    ws = plan.model_workspace(F, K)
-    tm = plan.model_forward(torch.tensor(truth_f, dtype=torch.float64, device=dev),
-                            torch.tensor(truth_a.astype(np.complex64), device=dev), ws)
-    r = tm - obs
-    truth_loss = float((r.real.double() ** 2 + r.imag.double() ** 2).sum())
-    before, after = err(start_f), err(fr.cpu().numpy())
-    amp_err = float(np.median(np.abs(ar.cpu().numpy() / truth_a - 1)))
-    plan.close()
+    tones = []   # per true tone initialized by a peak: (frame, tone, |b|^2, err before, err after)
+    for f in range(F):
+        for t, ft in enumerate(metas[f]["freqs"]):
+            d = np.abs(circ(start[f], ft)).max(axis=1)
+            u = int(np.argmin(d))
+            if d[u] >= 1.0:
+                continue
+            tones.append((f, t, float(abs(metas[f]["amps"][t]) ** 2), float(d[u]),
+                          float(np.abs(circ(end[f, u], ft)).max()),
+                          float(abs(amp1[f, u] / metas[f]["amps"][t] - 1))))
+    ev = np.array([[v[3], v[4], v[5]] for v in tones]) if tones else np.zeros((0, 3))
+    worst = sorted(tones, key=lambda v: -v[4])[:5]
     out = {"workload": f"{F} frames of 2048x2048 complex64, K={K} off-grid tones, B=128x128, T=3",
-           "start": "truth + N(0, 0.1 bin) frequency, 10% amplitude error",
+           "start": f"per frame the {K} strongest detected peaks (off-grid estimates) among the "
+                    f"{4 * K} strongest whose per-round amplitudes agree (spread <= 0.5), "
+                    "amplitudes from rsft_initial_amplitudes",
            "steps": steps, "ms_per_step": ms / steps, "ms_total": ms,
-           "freq_err_rms_bins": [before[0], after[0]], "freq_err_max_bins": [before[1], after[1]],
-           "amp_rel_err_median_after": amp_err,
-           "loss_first_last": [float(losses[0]), float(losses[-1])],
-           "loss_at_truth": truth_loss}
-    log(f"refinement: {out['ms_per_step']:.3f} ms/step, freq rms {before[0]:.4f} -> {after[0]:.4f} bin")
-    return out
+           "true_tones": F * K, "tones_initialized": len(tones),
+           "consistent_peaks_per_frame_min": int(passed.min()),
+           "freq_err_rms_bins": [float(np.sqrt(np.mean(ev[:, 0] ** 2))), float(np.sqrt(np.mean(ev[:, 1] ** 2)))],
+           "freq_err_max_bins": [float(ev[:, 0].max()), float(ev[:, 1].max())],
+           "tones_worse_after": int(np.sum(ev[:, 1] > ev[:, 0])),
+           "amp_rel_err_median_after": float(np.median(ev[:, 2])),
+           "worst_tones_after": [{"frame": v[0], "tone": v[1], "amp_sq": v[2], "err_before_bins": v[3],
+                                  "err_after_bins": v[4]} for v in worst],
+           "loss_first_last": [float(losses[0]), float(losses[-1])]}
+    log(f"refinement: {out['ms_per_step']:.3f} ms/step, {len(tones)} tones, freq rms "
+        f"{out['freq_err_rms_bins'][0]:.4f} -> {out['freq_err_rms_bins'][1]:.4f} bin, max "
+        f"{out['freq_err_max_bins'][0]:.4f} -> {out['freq_err_max_bins'][1]:.4f}")
+    per = cfg["rounds"] * int(np.prod(cfg["buckets"]))
+    obs_np = obs.cpu().numpy()
+    handoff = {"sigma": sigma, "steps": steps,
+               "frames": [{"start_f": start[f], "start_a": amp0[f], "end_f": end[f], "end_a": amp1[f],
+                           "observed": obs_np[f * per:(f + 1) * per].reshape(
+                               (cfg["rounds"],) + tuple(cfg["buckets"]))}
+                          for f in range(oracle_frames)]}
+    plan.close()
+    return out, handoff
+
+
+def refine_vs_oracle(handoff):
+    """The FP64 oracle's refinement of the handed-over frames from the same
+    start (frequencies, amplitudes) and observed buckets as the GPU's: the
+    largest difference of the refined frequencies (bins) and amplitudes."""
+    from oracle import refine as oracle_refine
+    from oracle import rsft as oracle_rsft
+    cfg = synth.WORKLOADS["offgrid_2048x2048"]
+    shape = cfg["shape"]
+    oplan = oracle_rsft.OraclePlan(shape, cfg["buckets"], handoff["sigma"], 60.0, None, cfg["pfa"])
+    df, da = [], []
+    t0 = time.perf_counter()
+    for fr in handoff["frames"]:
+        wf, wa, _, _ = oracle_refine.refine(fr["start_f"], fr["start_a"].astype(np.complex128), oplan,
+                                            fr["observed"].astype(np.complex128), handoff["steps"])
+        df.append(np.abs((((fr["end_f"] - wf + 0.5) % 1.0) - 0.5) * np.array(shape)).max())
+        da.append(np.max(np.abs(fr["end_a"] / wa - 1)))
+    return {"frames": len(handoff["frames"]), "refined_freq_max_diff_bins": float(max(df)),
+            "refined_amp_max_rel_diff": float(max(da)), "oracle_seconds": time.perf_counter() - t0}
 
 
 # The other batched workloads, each at its full batch: (name, frames,
@@ -360,6 +564,7 @@ def workloads_section(dev, steps, warmup, names=None):
             "frames": nframes, "input_bytes": in_bytes,
             "fold_launch": plan.info()["fold"],
             "estimate_workers": plan.info()["estimate_workers"],
+            "vote_kernel": plan.info()["vote_kernel"],
             "graph_replay_ms": {"p10": float(np.percentile(replay, 10)), "median": med,
                                 "p90": float(np.percentile(replay, 90))},
             "frames_per_s": nframes / (med * 1e-3),
@@ -481,9 +686,24 @@ def main():
                          "CSV output folders (FETCH_SIZE, WRITE_SIZE) and exit; no GPU")
     ap.add_argument("--counter-commands", nargs=2, default=["", ""],
                     help="the two rocprofv3 commands, recorded in the summary")
+    ap.add_argument("--skip-headline", action="store_true",
+                    help="skip the headline workload (with --workloads NAME: profile one workload)")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "TITLE", "COMMAND"),
+                    help="print a markdown summary of a rocprofv3 --kernel-trace --stats run and "
+                         "exit; no GPU")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
+                    help="TITLE KERNELS(comma-separated) DIR COMMAND [DIR COMMAND ...]: print a "
+                         "markdown summary of rocprofv3 --pmc runs and exit; no GPU")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, *args.counter_commands)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_pmc:
+        a = args.summarize_pmc
+        summarize_pmc(a[2::2], a[0], a[3::2], [k for k in a[1].split(",") if k])
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -497,6 +717,12 @@ def main():
     load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.skip_headline:
+        # profiling runs: the named other workloads alone
+        names = None if args.workloads == "all" else args.workloads.split(",")
+        print(json.dumps({"workloads": workloads_section(dev, min(args.steps, 20), args.warmup, names)}),
+              flush=True)
+        return
     cfg = synth.WORKLOADS[WORKLOAD]
     shape, buckets, T, pfa = cfg["shape"], cfg["buckets"], cfg["rounds"], cfg["pfa"]
     N = int(np.prod(shape))
@@ -510,6 +736,17 @@ def main():
     xb = torch.neg(xa)   # second buffer: same statistics, other bytes; this kernel reads
                          # and writes exactly 1 GiB and calibrates the HBM counters
     bufs = [xa, xb]
+    # measured copy bandwidth: the same elementwise negation, 1 GiB read + 1 GiB written
+    copy_ms = []
+    for _ in range(6):
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        torch.neg(xa, out=xb)
+        c1.record()
+        torch.cuda.synchronize()
+        copy_ms.append(c0.elapsed_time(c1))
+    copy_gbs = 2 * xa.numel() * 8 / (float(np.median(copy_ms[1:])) * 1e-3) / 1e9
+    log(f"copy (negation, 2 GiB moved): {copy_gbs:.0f} GB/s")
     sigma = synth.shared_sigma(WORKLOAD)
     plan = Plan(shape, buckets, rounds=T, sigma=sigma, window_atten_db=cfg["atten_db"],
                 pfa=pfa, dtype="c64", max_batch=FRAMES, max_detections=1 << 16)
@@ -584,11 +821,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "fold",
+                     "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": fold_bytes,
                      "avg_launch_ms": fold_ms},
         "stage_ms": stages,
         "fold_launch": fold_cfg,
         "estimate_workers": plan.info()["estimate_workers"],
+        "vote_kernel": plan.info()["vote_kernel"],
         "graph_ms_per_step": graph_s / args.steps * 1e3,
         "graph_replay_ms": graph_pct,
         "detections": {"total": int(counts.sum()), **fused_score},
@@ -623,15 +862,20 @@ def main():
             X = torch.fft.fft2(x * wnd)
             return (X.real ** 2 + X.imag ** 2) >= thr
 
-        det = dense(xa)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(3):
-            det = dense(xa)
-            nz = torch.nonzero(det.view(FRAMES, -1))
-        torch.cuda.synchronize()
-        dn_s = (time.perf_counter() - t0) / 3
-        nz = nz.cpu().numpy()
+        def timed(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            d0.record()
+            for _ in range(reps):
+                r = fn()
+            d1.record()
+            torch.cuda.synchronize()
+            return d0.elapsed_time(d1) / reps * 1e-3, r
+
+        dn_s, det = timed(lambda: dense(xa))
+        fft_s, _ = timed(lambda: torch.fft.fft2(xa))
+        nz = torch.nonzero(det.view(FRAMES, -1)).cpu().numpy()
         hits = tgt = fa = outside = 0
         for f in range(FRAMES):
             cells = nz[nz[:, 0] == f, 1]
@@ -641,12 +885,17 @@ def main():
             fa += a
             outside += o
         out["dense_fft"] = {"frames_per_s": FRAMES / dn_s, "ms_per_batch": dn_s * 1e3,
+                            "what": "window multiply, rocFFT 2-D FFT (torch.fft.fft2), |X|^2 >= "
+                                    "threshold as a mask; the cell list is taken after timing",
+                            "fft_only_ms_per_batch": fft_s * 1e3,
                             "speedup_of_fused": value / (FRAMES / dn_s),
+                            "speedup_of_fused_vs_fft_only": value / (FRAMES / fft_s),
                             "pd": hits / max(tgt, 1), "pfa": fa / max(outside, 1)}
         log(f"dense: {dn_s * 1e3:.2f} ms/batch")
 
+    refine_handoff = None
     if not args.skip_refine:
-        out["refine"] = refine_section(dev)
+        out["refine"], refine_handoff = refine_section(dev)
     if not args.skip_radar:
         out["radar"] = radar_section(dev)
     if args.workloads and not args.skip_workloads:
@@ -656,7 +905,14 @@ def main():
     if not args.skip_cpu and args.cpu_sample > 0:
         n = min(args.cpu_sample, FRAMES)
         log(f"cpu baseline: oracle on {n} frames ...")
-        cb, odets = cpu_baseline(frames_np, metas, shape, buckets, sigma, pfa, n)
+        cb, odets, oouts = cpu_baseline(frames_np, metas, shape, buckets, sigma, pfa, n)
+        gb = [b.cpu().numpy() for b in plan.buckets()[:n]]
+        gw = [w.cpu().numpy().view(np.uint32) for w in plan.flags()[:n]]
+        out["precision"] = precision_report(gb, gw, recs, oouts, shape, buckets)
+        log(f"precision: {out['precision']}")
+        if refine_handoff is not None:
+            out["refine"]["vs_fp64_oracle"] = refine_vs_oracle(refine_handoff)
+            log(f"refinement vs FP64 oracle: {out['refine']['vs_fp64_oracle']}")
         gpu_sample = score(recs, counts, metas, shape, range(n))
         cb["gpu_pd_same_frames"] = gpu_sample["pd"]
         cb["gpu_pfa_same_frames"] = gpu_sample["pfa"]
@@ -670,6 +926,10 @@ def main():
             agree += len(g & o)
             total += len(g | o)
         cb["detection_jaccard_vs_gpu"] = agree / max(total, 1)
+        cb["host"] = host_cpu()
+        workers = max(1, min(16, cb["host"]["cpus_allowed"]))
+        cb["dense_leg"] = dense_cpu_leg(frames_np, shape, cfg["atten_db"], pfa, n, workers)
+        log(f"cpu dense leg: {cb['dense_leg']}")
         out["cpu_baseline"] = cb
         log(f"cpu: {cb['value']:.2f} frames/s")
 

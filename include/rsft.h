@@ -178,6 +178,8 @@ typedef struct {
   int32_t fold_vec;          /* fold: complex samples per thread per row */
   int32_t fold_nontemporal;  /* fold: 1 = non-temporal input loads */
   int32_t estimate_workers;  /* compact/estimate: 1 = overflow workers */
+  int32_t vote_kernel;       /* 0 per cell, 1 candidate rows, 2 32-cell masks, 3 word-parallel masks */
+  int32_t reserved;
 } rsft_plan_info_t;
 
 typedef struct rsft_plan_s* rsft_plan_t;
@@ -217,12 +219,14 @@ rsft_status rsft_execute(rsft_plan_t plan, const void* d_input, int64_t batch,
  * - fold stage (the HBM-bound stage): work-group size (256 / 512 threads),
  *   samples per thread (4 / 2), ordinary vs non-temporal input loads; the
  *   fastest is kept and *best_ms (may be NULL) gets its average duration;
+ * - vote, where both kernels apply (RSFT_OPT_VOTE_WORDS): word-parallel
+ *   masks or the enumeration of candidate cells, the faster kept;
  * - compact/estimate: without or with overflow workers (the records of
  *   chunks holding more than 1024 detections shared among extra work-
  *   groups); the workers are kept when at least 3% faster. How dense the
  *   detections are depends on the data, hence timing on the caller's input.
- * Both choices are reported by rsft_plan_info and leave the results
- * unchanged (bit for bit for the estimate layout). Synchronizes the stream;
+ * The choices are reported by rsft_plan_info and leave the results
+ * unchanged (bit for bit for the vote and the estimate layout). Synchronizes the stream;
  * afterwards the plan holds the results of an execute of d_input.
  * Errors: as rsft_execute.
  */
@@ -232,16 +236,21 @@ rsft_status rsft_autotune(rsft_plan_t plan, const void* d_input, int64_t batch, 
 /*
  * The same detections computed the plain way, as a comparator: for each
  * frame and each round separately, gather the permuted samples, window,
- * alias, DFT, threshold (Algorithm 1 literally, one launch chain per frame),
- * then vote over all N cells of the frame. Same arguments and results as
- * rsft_execute; much slower.
+ * alias and DFT, then threshold (Algorithm 1 literally: T passes over the
+ * frame, one launch chain per frame), then the frame's reverse mapping and
+ * second stage (Def. 3-4, eq. a_i; the plan's vote kernel, one launch per
+ * frame); the estimates of the whole batch follow as in rsft_execute. Same
+ * arguments and results as rsft_execute; much slower.
  */
 rsft_status rsft_execute_per_frame(rsft_plan_t plan, const void* d_input,
                                    int64_t batch, void* stream);
 
 /*
  * Synchronize `stream` and copy the detections of the last execute to the
- * host. h_out: host array of `capacity` records; receives the records sorted
+ * host: the output o of Algorithm 1, the cells whose accumulated votes pass
+ * the second-stage threshold (Sec. III-C.5), each with the off-grid estimate
+ * described at rsft_detection. h_out: host array of `capacity` records;
+ * receives the records sorted
  * by (frame, row-major cell index). h_counts: host array with one entry per
  * frame of the last execute (may be NULL); receives the exact number of
  * detections of each frame, including any beyond the per-frame
@@ -267,16 +276,20 @@ rsft_status rsft_get_buckets(rsft_plan_t plan, void* d_out, void* stream);
 
 /*
  * Copy the first-stage flags c_s of the last execute to d_out (device,
- * uint32): for each frame, [T][ceil(B/32)] words; bucket j (row-major
+ * uint32): c_s[j] = 1 when |fhat_s[j]|^2 >= gamma_s, the Neyman-Pearson test
+ * of each bucket with the per-round threshold of eq. tpd (first stage,
+ * Sec. IV-B). For each frame, [T][ceil(B/32)] words; bucket j (row-major
  * flattened) is bit (j % 32) of word j / 32. Async on `stream`.
  */
 rsft_status rsft_get_flags(rsft_plan_t plan, uint32_t* d_out, void* stream);
 
 /*
  * Replace the flags of the last execute by d_flags (device, layout of
- * rsft_get_flags) and redo the reverse mapping, second-stage detection and
- * estimates from them (buckets unchanged). Lets a caller check the voting
- * stage against known flags. Async on `stream`.
+ * rsft_get_flags) and redo the reverse mapping and accumulation
+ * abar_i = sum_s c_s[M(i, sigma_s)] (Def. 3-4, eq. a_i), the second-stage
+ * detection abar_i >= mu (Sec. III-C.5) and the estimates from them
+ * (buckets unchanged). Lets a caller check the voting stage against known
+ * flags. Async on `stream`.
  */
 rsft_status rsft_vote_flags(rsft_plan_t plan, const uint32_t* d_flags, void* stream);
 
@@ -354,6 +367,57 @@ rsft_status rsft_model_backward(rsft_plan_t plan, const void* d_amps, int64_t ba
                                 void* d_grad_amps, double* d_step_freqs, void* d_step_amps,
                                 const void* d_workspace, void* stream);
 
+/*
+ * Off-grid refinement of K tones per frame against observed buckets
+ * (Sec. I cites gradient refinement of sparse-FFT estimates; here the
+ * bucketized model of rsft_model_forward is fitted to the round buckets of
+ * eq. f by least squares, loss = sum_{s,k} |model_s[k] - observed_s[k]|^2).
+ *
+ * d_observed   device complex64 in the layout of rsft_get_buckets, or NULL
+ *              for the plan's own buckets of the last execute (which must
+ *              have processed `batch` frames; else NOT_READY).
+ * d_workspace  device buffer of rsft_refine_workspace_size bytes (both calls
+ *              below; contents are scratch).
+ *
+ * rsft_initial_amplitudes: the starting amplitude of each tone from the
+ * buckets its nearest cell falls in (cell_d = floor(f_d N_d + 1/2) mod N_d):
+ * in every estimation round (rsft_plan_info_t.estimation_rounds) the
+ * observed bucket y_s[M(cell, sigma_s)] (Def. 3) divided by the model of a
+ * unit tone at f in that bucket (the window, permutation, flat window,
+ * aliasing and DFT response; Sec. III-C divides bucket values by the window
+ * spectrum); of these ratios, the one whose magnitude is the median over the
+ * rounds (rank floor((n-1)/2) ascending, the earlier round on ties), so that
+ * a round where another tone shares the bucket is outvoted. d_freqs: double
+ * [batch][K][D] (e.g. the freq of detected peaks); d_amps: complex64
+ * [batch][K] (output); d_spread (may be NULL): float [batch][K], the
+ * largest deviation of a round's ratio from the chosen one relative to it,
+ * max_s |a_s - a| / |a| (infinity for a = 0): small for a single tone, of
+ * order one for a peak made of different tones' energy in different rounds
+ * (the ambiguity of Remark 1), which a caller can drop before refining.
+ *
+ * rsft_refine: `steps` steps in place on d_freqs / d_amps, all on the
+ * device. Each step, every tone against the same residual r = model -
+ * observed (tones decoupled): the tone's Gauss-Newton step over (Re b,
+ * Im b, f) (as rsft_model_backward), its frequency step clipped to the
+ * tone's trust radius (starting at trust_bins bins per dimension); then the
+ * amplitude re-solved for the new frequency f' by least squares against the
+ * residual without the tone; the step is kept when it lowers the tone's own
+ * loss (others fixed), and the radius doubles (at most trust_bins); else
+ * the frequency stays, the amplitude becomes the least-squares one at f and
+ * the radius halves. d_loss (may be NULL): double [steps + 1][batch], the
+ * loss of each frame before each step and after the last, in FP64.
+ * Frequencies are FP64 throughout; sums are FP32 with FP64 reductions.
+ * Errors: as rsft_model_forward; INVALID_ARGUMENT (steps outside 0..100000,
+ * trust_bins <= 0); NOT_READY. Async on `stream`.
+ */
+rsft_status rsft_refine_workspace_size(rsft_plan_t plan, int64_t batch, int32_t tones, int64_t* bytes);
+rsft_status rsft_initial_amplitudes(rsft_plan_t plan, const void* d_observed, const double* d_freqs,
+                                    int64_t batch, int32_t tones, void* d_amps, float* d_spread,
+                                    void* d_workspace, void* stream);
+rsft_status rsft_refine(rsft_plan_t plan, const void* d_observed, double* d_freqs, void* d_amps,
+                        int64_t batch, int32_t tones, int32_t steps, double trust_bins,
+                        void* d_workspace, double* d_loss, void* stream);
+
 /* Per-frame derived parameters; frame indexes the descriptors of rsft_plan. */
 rsft_status rsft_plan_info(rsft_plan_t plan, int64_t frame, rsft_plan_info_t* out);
 
@@ -374,7 +438,12 @@ enum {
   /* compact/estimate layout (what rsft_autotune chooses): 0 = one work-group
      per compaction chunk builds all of its records; 1 = it builds the first
      1024 and overflow workers the rest. Same records either way. Default 0. */
-  RSFT_OPT_ESTIMATE_WORKERS = 5
+  RSFT_OPT_ESTIMATE_WORKERS = 5,
+  /* vote kernel for plans whose frames all have rows (last dimension) of
+     128..4096 cells and B_last * N_last / 32 <= 16384: 1 = word-parallel
+     masks (default), 0 = enumeration of the candidate cells of flagged
+     buckets (T <= 4; larger T keeps the masks). Same detections either way. */
+  RSFT_OPT_VOTE_WORDS = 6
 };
 rsft_status rsft_set_option(rsft_plan_t plan, int32_t option, int64_t value);
 

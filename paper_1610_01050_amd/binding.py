@@ -32,6 +32,7 @@ NOISE_KNOWN, NOISE_ESTIMATED = 0, 1
 OPT_GRAPH, OPT_TIMING = 0, 1
 OPT_FOLD_THREADS, OPT_FOLD_VEC, OPT_FOLD_NONTEMPORAL = 2, 3, 4
 OPT_ESTIMATE_WORKERS = 5
+OPT_VOTE_WORDS = 6
 STAGES = ("fold", "dft", "vote", "estimate")
 
 # Every symbol include/rsft.h declares.
@@ -43,7 +44,7 @@ SYMBOLS = (
     "rsft_chebyshev_window", "rsft_flat_window", "rsft_mod_inverse",
     "rsft_stage1_probability", "rsft_draw_sigma",
     "rsft_model_workspace_size", "rsft_model_forward", "rsft_model_forward_noalloc",
-    "rsft_model_backward",
+    "rsft_model_backward", "rsft_refine_workspace_size", "rsft_initial_amplitudes", "rsft_refine",
     "rsft_design_thresholds",
 )
 
@@ -117,6 +118,7 @@ class PlanInfo(ctypes.Structure):
         ("estimation_rounds", ctypes.c_uint64),
         ("fold_threads", ctypes.c_int32), ("fold_vec", ctypes.c_int32),
         ("fold_nontemporal", ctypes.c_int32), ("estimate_workers", ctypes.c_int32),
+        ("vote_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -173,6 +175,10 @@ def load_library(path=None):
     lib.rsft_model_forward.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp]
     lib.rsft_model_forward_noalloc.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp]
     lib.rsft_model_backward.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    lib.rsft_refine_workspace_size.argtypes = [vp, i64, ctypes.c_int32, ctypes.POINTER(i64)]
+    lib.rsft_initial_amplitudes.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp]
+    lib.rsft_refine.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                vp, vp, vp]
     lib.rsft_design_thresholds.argtypes = [ctypes.POINTER(DesignParams),
                                            ctypes.POINTER(DesignResult)]
     lib.rsft_draw_sigma.argtypes = [ctypes.c_uint64, ctypes.c_int32,
@@ -471,6 +477,7 @@ class Plan:
             "fold": {"threads": out.fold_threads, "vec": out.fold_vec,
                      "nontemporal": out.fold_nontemporal},
             "estimate_workers": out.estimate_workers,
+            "vote_kernel": ("per_cell", "candidate_rows", "masks_32", "word_masks")[out.vote_kernel],
         }
 
     # -- bucketized forward model of complex tones (off-grid refinement) --
@@ -544,6 +551,46 @@ class Plan:
             ctypes.c_void_p(sa.data_ptr() if steps else 0), ctypes.c_void_p(workspace.data_ptr()),
             _stream_handle(stream)))
         return (gf, ga, sf, sa) if steps else (gf, ga)
+
+    def refine_workspace(self, batch, tones):
+        import torch
+        n = ctypes.c_int64()
+        _check(self._lib, self._lib.rsft_refine_workspace_size(self._h, int(batch), int(tones),
+                                                               ctypes.byref(n)))
+        return torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+
+    def initial_amplitudes(self, freqs, workspace, observed=None, with_spread=False, stream=None):
+        """Starting amplitudes (complex64 [batch, K]) of tones at `freqs`
+        (float64 [batch, K, D]) from the observed buckets (default: this
+        plan's buckets of the last execute); with_spread: also the per-round
+        spread (float32 [batch, K])."""
+        import torch
+        if not (isinstance(freqs, torch.Tensor) and freqs.is_cuda and freqs.dtype == torch.float64
+                and freqs.is_contiguous() and freqs.dim() == 3):
+            raise TypeError("freqs must be a contiguous CUDA float64 tensor [batch, K, D]")
+        batch, K = int(freqs.shape[0]), int(freqs.shape[1])
+        amps = torch.empty((batch, K), dtype=torch.complex64, device="cuda")
+        spread = torch.empty((batch, K), dtype=torch.float32, device="cuda") if with_spread else None
+        obs = 0 if observed is None else observed.contiguous().data_ptr()
+        _check(self._lib, self._lib.rsft_initial_amplitudes(
+            self._h, ctypes.c_void_p(obs), ctypes.c_void_p(freqs.data_ptr()), batch, K,
+            ctypes.c_void_p(amps.data_ptr()), ctypes.c_void_p(spread.data_ptr() if with_spread else 0),
+            ctypes.c_void_p(workspace.data_ptr()), _stream_handle(stream)))
+        return (amps, spread) if with_spread else amps
+
+    def refine(self, freqs, amps, steps, workspace, observed=None, trust_bins=0.25, loss=None,
+               stream=None):
+        """rsft_refine in place on freqs (float64 [batch, K, D]) and amps
+        (complex64 [batch, K]); loss: None or a float64 CUDA tensor of
+        (steps + 1) * batch elements."""
+        batch, K = self._model_args(freqs, amps)
+        obs = 0 if observed is None else observed.contiguous().data_ptr()
+        lp = 0 if loss is None else loss.data_ptr()
+        _check(self._lib, self._lib.rsft_refine(
+            self._h, ctypes.c_void_p(obs), ctypes.c_void_p(freqs.data_ptr()),
+            ctypes.c_void_p(amps.data_ptr()), batch, K, int(steps), float(trust_bins),
+            ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(lp), _stream_handle(stream)))
+        return freqs, amps
 
     def set_option(self, option, value):
         _check(self._lib, self._lib.rsft_set_option(self._h, int(option), int(value)))

@@ -73,16 +73,20 @@ struct rsft_plan_s {
   int64_t min_nl = 0;
   int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, est_nmask = 0;
   int rows_ok = 1, masks_ok = 1;   // every frame suits the row vote / the 32-cell mask vote
+  int words_ok = 1;                // every frame suits the word-parallel vote
+  int vote_words = 1;              // RSFT_OPT_VOTE_WORDS: prefer the word-parallel vote
+  int tab_words = 0;               // LDS words of its per-round table (largest frame)
   int vote_path = rsft::kVoteCells;
   int dft_plane = 0;   // floats per LDS plane of the DFT: B plus one pad per last-dimension row
   int dft_pad = 0;     // 1 when those pads are used
   int64_t tiles_per_frame = 0;   // uniform plans
   int64_t ntiles_uneven = 0;     // uneven plans
   int64_t nchunk_list = 0;       // uneven plans with frames of different chunk counts
+  int64_t nvote_list = 0;        // the same for the word-parallel vote's chunk groups
   int scan_fpb = 1;              // frames per scan work-group
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles, d_chunk_list,
-      d_dft_order;
+      d_dft_order, d_vote_tab, d_vote_list;
   DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
       d_offsets, d_records, d_scan_done, d_chunk_items, d_item_counts, d_item_offsets;
   rsft::DevPtrs ptrs{};
@@ -104,6 +108,17 @@ struct rsft_plan_s {
 };
 
 namespace {
+
+// Vote kernel of a plan: the word-parallel masks where every frame's rows
+// suit them (and RSFT_OPT_VOTE_WORDS is on), else the candidate rows, the
+// 32-cell masks, or the per-cell gather.
+void choose_vote_path(rsft_plan_s* pl) {
+  pl->vote_path = pl->words_ok && pl->vote_words ? rsft::kVoteWords
+                  : pl->rows_ok && pl->T <= 4    ? rsft::kVoteRows
+                  : pl->masks_ok                 ? rsft::kVoteMasks32
+                  : pl->words_ok                 ? rsft::kVoteWords
+                                                 : rsft::kVoteCells;
+}
 
 rsft_status validate(const rsft_params& p, int64_t idx) {
   const std::string at = "frame descriptor " + std::to_string(idx) + ": ";
@@ -435,7 +450,7 @@ void free_plan(rsft_plan_s* pl) {
   if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
   DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
                           &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_chunk_list,
-                          &pl->d_dft_order, &pl->d_part,
+                          &pl->d_dft_order, &pl->d_vote_tab, &pl->d_vote_list, &pl->d_part,
                           &pl->d_buckets, &pl->d_powers, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
                           &pl->d_scan_done, &pl->d_chunk_items, &pl->d_item_counts, &pl->d_item_offsets};
@@ -510,11 +525,17 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     pl->est_nmask |= 1 << std::min(d.n_est, rsft::kMaxEstRounds + 1);
     if (d.n_last < 64 || d.n_last > 4096) pl->rows_ok = 0;
     if (d.n_last != 32) pl->masks_ok = 0;
+    {
+      const int64_t nl = d.n[d.ndim - 1];
+      const int64_t tw = int64_t(d.b[d.ndim - 1]) * (nl / 32);
+      if (nl < 128 || nl > 4096 || tw > 16384) pl->words_ok = 0;
+      else pl->tab_words = std::max(pl->tab_words, int(tw));
+    }
     int sum_tw = 0;
     for (int k = 0; k < d.ndim; ++k) sum_tw += d.b[k];
     pl->sum_tw_max = std::max(pl->sum_tw_max, sum_tw);
   }
-  pl->vote_path = pl->rows_ok ? rsft::kVoteRows : pl->masks_ok ? rsft::kVoteMasks32 : rsft::kVoteCells;
+  choose_vote_path(pl);
   // chunks per frame are a power of two (N is); few of them: several frames
   // per scan work-group
   if (pl->uniform && pl->descs[0].cchunks <= 128) pl->scan_fpb = 256 / pl->descs[0].cchunks;
@@ -589,8 +610,46 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     }
   }
 
+  // word-parallel vote: per descriptor and round, M_s[b][w] with bit x of
+  // word w set when cell 32 w + x of a row lies in bucket column b, i.e.
+  // the preimages x = [sigma_inv u] of u in [b L, (b + 1) L) (Def. 4); and
+  // for uneven plans whose frames differ in chunk count, the list of
+  // (frame, first chunk) groups of kVoteCpw chunks
+  std::vector<uint32_t> vote_tab;
+  std::vector<int32_t> vote_list;
+  if (pl->words_ok) {
+    for (auto& d : pl->descs) {
+      const int D = d.ndim;
+      const uint32_t nl = uint32_t(d.n[D - 1]);
+      const uint32_t W = nl / 32;
+      const uint32_t bl = uint32_t(d.b[D - 1]);
+      const int lsl = d.lshift[D - 1];
+      d.vtab_off = int64_t(vote_tab.size());
+      vote_tab.resize(vote_tab.size() + size_t(d.T) * bl * W, 0u);
+      uint32_t* t0 = vote_tab.data() + d.vtab_off;
+      for (int r = 0; r < d.T; ++r) {
+        uint32_t* tr = t0 + size_t(r) * bl * W;
+        const uint64_t sinv = uint64_t(uint32_t(d.sigma_inv[r][D - 1]));
+        for (uint32_t u = 0; u < nl; ++u) {
+          const uint32_t x = uint32_t((sinv * u) % nl);
+          tr[(u >> lsl) * W + (x >> 5)] |= 1u << (x & 31u);
+        }
+      }
+    }
+    if (!pl->uniform && pl->nchunk_list > 0) {
+      for (int64_t i = 0; i < nframes; ++i)
+        for (int32_t c = 0; c < pl->descs[size_t(i)].cchunks; c += rsft::kVoteCpw) {
+          vote_list.push_back(int32_t(i));
+          vote_list.push_back(c);
+        }
+      pl->nvote_list = int64_t(vote_list.size() / 2);
+    }
+  }
+
   rsft_status st;
   if ((st = upload(pl->d_descs, pl->descs)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_vote_tab, vote_tab)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_vote_list, vote_list)) != RSFT_OK) return st;
   if ((st = upload(pl->d_wrow, ht.wrow)) != RSFT_OK) return st;
   if ((st = upload(pl->d_wcol, ht.wcol)) != RSFT_OK) return st;
   if ((st = upload(pl->d_rowlist, ht.rowlist)) != RSFT_OK) return st;
@@ -645,6 +704,8 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.scan_done = static_cast<uint32_t*>(pl->d_scan_done.ptr);
   q.tiles = static_cast<const int32_t*>(pl->d_tiles.ptr);
   q.chunk_list = static_cast<const int32_t*>(pl->d_chunk_list.ptr);
+  q.vote_tab = static_cast<const uint32_t*>(pl->d_vote_tab.ptr);
+  q.vote_list = static_cast<const int32_t*>(pl->d_vote_list.ptr);
   return RSFT_OK;
 }
 
@@ -697,6 +758,13 @@ rsft_status estimate_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   return RSFT_OK;
 }
 
+// Reverse mapping, accumulation and second stage for the whole batch.
+rsft_status vote_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
+  LAUNCH_TRY(rsft::launch_vote(pl->ptrs, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask,
+                               pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, st));
+  return RSFT_OK;
+}
+
 // The hot path, stage by stage; `ev` (optional) brackets the stages.
 rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStream_t st,
                     hipEvent_t* ev) {
@@ -710,7 +778,10 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
   LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0,
                               pl->uniform ? nullptr : static_cast<const int32_t*>(pl->d_dft_order.ptr), st));
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, st));
+  {
+    const rsft_status vs = vote_stage(pl, batch, st);
+    if (vs != RSFT_OK) return vs;
+  }
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   {
     const rsft_status es = estimate_stage(pl, batch, st);
@@ -870,6 +941,26 @@ rsft_status rsft_autotune(rsft_plan_t pl, const void* d_input, int64_t batch, vo
   // workers; the workers are kept only when clearly faster.
   if ((st = enqueue(pl, d_input, batch, s, nullptr)) != RSFT_OK) return st;
   pl->last_batch = batch;
+  // vote kernel, where both the word-parallel masks and the candidate
+  // enumeration apply: which is faster depends on B_last, L_last and how
+  // many buckets the data flag; the faster on d_input's flags is kept (the
+  // vote only reads the flags, and both write the same bitmap)
+  if (pl->words_ok && pl->rows_ok && pl->T <= 4) {
+    float vote_ms[2] = {0.f, 0.f};
+    for (int v = 0; v < 2; ++v) {
+      pl->vote_words = v;
+      choose_vote_path(pl);
+      if ((st = vote_stage(pl, batch, s)) != RSFT_OK) return st;
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < repeats && st == RSFT_OK; ++r) st = vote_stage(pl, batch, s);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      if (st != RSFT_OK) return st;
+      HIP_TRY(hipEventElapsedTime(&vote_ms[v], e0, e1));
+    }
+    pl->vote_words = vote_ms[1] <= vote_ms[0] ? 1 : 0;
+    choose_vote_path(pl);
+  }
   float est_ms[2] = {0.f, 0.f};
   for (int w = 0; w < 2; ++w) {
     pl->est_workers = w;
@@ -898,7 +989,7 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
     const auto& d = pl->descs[size_t(pl->uniform ? 0 : f)];
     for (int r = 0; r < pl->T; ++r) LAUNCH_TRY(rsft::launch_plain_fold(q, d_input, pl->dtype, f, r, d.B, s));
     LAUNCH_TRY(rsft::launch_plain_dft(q, f, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, s));
-    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, int(f), 0, s));
+    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, int(f), 0, 0, pl->tab_words, s));
   }
   if (batch > 0) {
     const rsft_status es = estimate_stage(pl, batch, s);
@@ -995,6 +1086,98 @@ rsft_status rsft_model_backward(rsft_plan_t pl, const void* d_amps, int64_t batc
   return RSFT_OK;
 }
 
+namespace {
+// Observed buckets of a refinement: the caller's, or the plan's own from the
+// last execute (which must have covered `batch` frames).
+rsft_status observed_buckets(rsft_plan_s* pl, const void* d_observed, int64_t batch, const float2** out) {
+  if (d_observed) {
+    *out = static_cast<const float2*>(d_observed);
+    return RSFT_OK;
+  }
+  if (pl->last_batch != batch)
+    return fail(RSFT_ERROR_NOT_READY, "no observed buckets given and the last execute was not of this batch");
+  *out = pl->ptrs.buckets;
+  return RSFT_OK;
+}
+
+// Complex values of a model (bucket) array for `batch` frames.
+int64_t model_values(const rsft_plan_s* pl, int64_t batch) {
+  int64_t n = 0;
+  for (int64_t f = 0; f < batch; ++f) n += pl->descs[size_t(pl->uniform ? 0 : f)].bucket_stride;
+  return n;
+}
+
+// Byte layout of a refinement workspace (each part 256-byte aligned).
+struct RefineLayout {
+  int64_t G, dG, G2, dG2, model, radius, fcand, total;
+};
+RefineLayout refine_layout(const rsft_plan_s* pl, int64_t batch, int32_t tones) {
+  auto up = [](int64_t v) { return (v + 255) / 256 * 256; };
+  const int64_t fac = up(model_factor_count(pl, batch, tones) * 8);
+  RefineLayout L{};
+  L.G = 0;
+  L.dG = L.G + fac;
+  L.G2 = L.dG + fac;
+  L.dG2 = L.G2 + fac;
+  L.model = L.dG2 + fac;
+  L.radius = L.model + up(model_values(pl, batch) * 8);
+  L.fcand = L.radius + up(batch * tones * 8);
+  L.total = L.fcand + up(batch * tones * pl->descs[0].ndim * 8);
+  return L;
+}
+}  // namespace
+
+rsft_status rsft_refine_workspace_size(rsft_plan_t pl, int64_t batch, int32_t tones, int64_t* bytes) {
+  if (!bytes) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
+  const rsft_status st = check_model(pl, batch, tones);
+  if (st != RSFT_OK) return st;
+  *bytes = refine_layout(pl, batch, tones).total;
+  return RSFT_OK;
+}
+
+rsft_status rsft_initial_amplitudes(rsft_plan_t pl, const void* d_observed, const double* d_freqs,
+                                    int64_t batch, int32_t tones, void* d_amps, float* d_spread,
+                                    void* d_workspace, void* stream) {
+  rsft_status st = check_model(pl, batch, tones);
+  if (st != RSFT_OK) return st;
+  if (!d_freqs || !d_amps || !d_workspace) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL pointer");
+  const float2* obs = nullptr;
+  if ((st = observed_buckets(pl, d_observed, batch, &obs)) != RSFT_OK) return st;
+  float2* G = static_cast<float2*>(d_workspace);
+  float2* dG = G + model_factor_count(pl, batch, tones);
+  LAUNCH_TRY(rsft::launch_initial_amplitudes(pl->ptrs, d_freqs, batch, tones, pl->descs[0].ndim, pl->T,
+                                             pl->maxB, pl->sum_tw_max, G, dG, obs,
+                                             static_cast<float2*>(d_amps), d_spread, stream));
+  return RSFT_OK;
+}
+
+rsft_status rsft_refine(rsft_plan_t pl, const void* d_observed, double* d_freqs, void* d_amps, int64_t batch,
+                        int32_t tones, int32_t steps, double trust_bins, void* d_workspace, double* d_loss,
+                        void* stream) {
+  rsft_status st = check_model(pl, batch, tones);
+  if (st != RSFT_OK) return st;
+  if (!d_freqs || !d_amps || !d_workspace) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL pointer");
+  if (steps < 0 || steps > 100000) return fail(RSFT_ERROR_INVALID_ARGUMENT, "steps must be 0..100000");
+  if (!(trust_bins > 0.0) || !std::isfinite(trust_bins))
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "trust_bins must be > 0");
+  const float2* obs = nullptr;
+  if ((st = observed_buckets(pl, d_observed, batch, &obs)) != RSFT_OK) return st;
+  const RefineLayout L = refine_layout(pl, batch, tones);
+  char* base = static_cast<char*>(d_workspace);
+  rsft::RefineWork w{};
+  w.G = reinterpret_cast<float2*>(base + L.G);
+  w.dG = reinterpret_cast<float2*>(base + L.dG);
+  w.G2 = reinterpret_cast<float2*>(base + L.G2);
+  w.dG2 = reinterpret_cast<float2*>(base + L.dG2);
+  w.model = reinterpret_cast<float2*>(base + L.model);
+  w.radius = reinterpret_cast<double*>(base + L.radius);
+  w.fcand = reinterpret_cast<double*>(base + L.fcand);
+  LAUNCH_TRY(rsft::launch_refine(pl->ptrs, obs, d_freqs, static_cast<float2*>(d_amps), batch, tones,
+                                 pl->descs[0].ndim, pl->T, pl->maxB, pl->sum_tw_max, steps, trust_bins, w,
+                                 d_loss, stream));
+  return RSFT_OK;
+}
+
 rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* stream) {
   if (!pl || !d_flags) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument");
   if (pl->last_batch < 0) return fail(RSFT_ERROR_NOT_READY, "no execute yet");
@@ -1005,7 +1188,7 @@ rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* strea
   for (int64_t f = 0; f < batch; ++f) words += size_t(pl->descs[size_t(pl->uniform ? 0 : f)].flag_stride);
   HIP_TRY(hipMemcpyAsync(pl->d_flags.ptr, d_flags, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   const auto& q = pl->ptrs;
-  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, s));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, s));
   return estimate_stage(pl, batch, s);
 }
 
@@ -1080,6 +1263,7 @@ rsft_status rsft_plan_info(rsft_plan_t pl, int64_t frame, rsft_plan_info_t* out)
   out->fold_vec = pl->fold.vec;
   out->fold_nontemporal = pl->fold.nontemporal;
   out->estimate_workers = pl->est_workers;
+  out->vote_kernel = pl->vote_path;
   return RSFT_OK;
 }
 
@@ -1101,6 +1285,12 @@ rsft_status rsft_set_option(rsft_plan_t pl, int32_t option, int64_t value) {
       return RSFT_OK;
     case RSFT_OPT_FOLD_NONTEMPORAL:
       pl->fold.nontemporal = value != 0 ? 1 : 0;
+      drop_graphs(pl);
+      return RSFT_OK;
+    case RSFT_OPT_VOTE_WORDS:
+      if (value != 0 && value != 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, "RSFT_OPT_VOTE_WORDS must be 0 or 1");
+      pl->vote_words = int(value);
+      choose_vote_path(pl);
       drop_graphs(pl);
       return RSFT_OK;
     case RSFT_OPT_ESTIMATE_WORKERS:

@@ -256,12 +256,18 @@ __device__ void solve_small(double (&H)[6][6], double (&r)[6], int n, double (&x
   (void)piv;
 }
 
+// With `observed` set (refinement), grad_model is the model and the output
+// gradient is 2 (model - observed), formed here; the frequency step is then
+// clipped to the tone's trust radius (radius[tone] bins) and f + step goes
+// to fcand (step_amps unused, grad_freqs / grad_amps may be NULL).
 __global__ __launch_bounds__(kBackThreads) void model_backward_kernel(
     DevPtrs p, const float2* __restrict__ amps, int K, int T, int sum_b,
     const float2* __restrict__ G, const float2* __restrict__ dG,
     const float2* __restrict__ grad_model, double* __restrict__ grad_freqs,
     float2* __restrict__ grad_amps, double* __restrict__ step_freqs,
-    float2* __restrict__ step_amps) {
+    float2* __restrict__ step_amps, const float2* __restrict__ observed,
+    const double* __restrict__ radius, const double* __restrict__ freqs,
+    double* __restrict__ fcand) {
   __shared__ float2 sg[4 * 128], sdg[4 * 128];
   __shared__ float slots[kBackThreads / 64];
   constexpr int kPairs = kMaxDims * (kMaxDims + 1) / 2;
@@ -270,8 +276,10 @@ __global__ __launch_bounds__(kBackThreads) void model_backward_kernel(
   const FrameDesc& de = model_desc(p, f);
   const int D = de.ndim;
   const int tid = threadIdx.x;
-  const bool want_step = step_freqs != nullptr;
+  const bool want_step = step_freqs != nullptr || fcand != nullptr;   // the Gauss-Newton block
   const float2* gr = grad_model + frame_bucket_base(p, f);
+  const float2* ob = observed ? observed + frame_bucket_base(p, f) : nullptr;
+  const bool want_cand = fcand != nullptr;
   // with P = prod_d G_d and part_d = dG_d prod_{e != d} G_e:
   float2 cb = make_float2(0.f, 0.f);        // sum Gr conj(P)
   float2 cf[kMaxDims];                      // sum conj(Gr) part_d
@@ -292,7 +300,11 @@ __global__ __launch_bounds__(kBackThreads) void model_backward_kernel(
     }
     __syncthreads();
     for (int k = tid; k < de.B; k += kBackThreads) {
-      const float2 e = gr[int64_t(s) * de.B + k];
+      float2 e = gr[int64_t(s) * de.B + k];
+      if (ob) {
+        const float2 y = ob[int64_t(s) * de.B + k];
+        e = make_float2(2.f * (e.x - y.x), 2.f * (e.y - y.y));
+      }
       float2 gv[kMaxDims], dv[kMaxDims];
       int acc_off = 0;
 #pragma unroll
@@ -360,11 +372,11 @@ __global__ __launch_bounds__(kBackThreads) void model_backward_kernel(
     const double ci = block_sum(cf[d].y, slots);
     gfv[d] = br * cr - bi * ci;               // Re(b (cr + j ci))
   }
-  if (tid == 0) {
+  if (tid == 0 && grad_amps) {
     grad_amps[f * K + t] = make_float2(float(gbr), float(gbi));
     for (int d = 0; d < D; ++d) grad_freqs[(f * K + t) * D + d] = gfv[d];
   }
-  if (!want_step) return;
+  if (!want_step && !want_cand) return;
   // Gauss-Newton block of this tone over (Re b, Im b, f_0 .. f_{D-1}):
   // H = Re(J^H J) with J = [P, jP, b part_0, ..., b part_{D-1}], and the
   // step solves H x = -g / 2 (g = gradient of sum |model - observed|^2).
@@ -408,11 +420,232 @@ __global__ __launch_bounds__(kBackThreads) void model_backward_kernel(
   rhs[1] = -0.5 * gbi;
   for (int d = 0; d < D; ++d) rhs[2 + d] = -0.5 * gfv[d];
   solve_small(H, rhs, n, x);
+  if (want_cand) {
+    // trust region of the tone: radius bins per dimension
+    const double rad = radius[f * K + t];
+    for (int d = 0; d < D; ++d) {
+      const double cap = rad / double(de.n[d]);
+      const double st = x[2 + d] < -cap ? -cap : (x[2 + d] > cap ? cap : x[2 + d]);
+      fcand[(f * K + t) * D + d] = freqs[(f * K + t) * D + d] + st;
+    }
+    return;
+  }
   step_amps[f * K + t] = make_float2(float(x[0]), float(x[1]));
   // trust region: at most a quarter bin per step and dimension
   for (int d = 0; d < D; ++d) {
     const double cap = 0.25 / double(de.n[d]);
     step_freqs[(f * K + t) * D + d] = x[2 + d] < -cap ? -cap : (x[2 + d] > cap ? cap : x[2 + d]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Refinement with per-tone step acceptance (rsft_refine). Per step:
+//   model_basis(f) -> G, dG;  model_combine -> model
+//   refine_gn: each tone's Gauss-Newton step from the residual
+//     r = model - observed (as model_backward with the output gradient 2 r),
+//     its frequency step clipped to the tone's trust radius (bins / N_d),
+//     f' = f + step -> fcand
+//   model_basis(f') -> G2
+//   refine_accept: per tone, with P = prod_d G_d(f), Q = prod_d G2_d(f') and
+//     the inner products pp = <P,P>, qq = <Q,Q>, pq = <P,Q>, rp = <P,r>,
+//     rq = <Q,r> (<x,y> = sum conj(x) y): the amplitude for f' by least
+//     squares against the residual without the tone, b' = (b conj(pq) - rq)
+//     / qq, and the tone's own loss change dL = 2 Re <r, delta> + |delta|^2,
+//     delta = b' Q - b P; dL < 0 accepts (f', b') and doubles the radius (up
+//     to its maximum), else the frequency stays, b <- b - rp / pp (the
+//     least-squares amplitude at f) and the radius halves.
+// Tones are decoupled: every tone's step is taken against the same residual.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBackThreads) void refine_accept_kernel(
+    DevPtrs p, int K, int T, int sum_b, const float2* __restrict__ G, const float2* __restrict__ G2,
+    const float2* __restrict__ model, const float2* __restrict__ observed,
+    const double* __restrict__ fcand, double* __restrict__ freqs, float2* __restrict__ amps,
+    double* __restrict__ radius, double max_radius) {
+  __shared__ float2 sg[4 * 128], sq[4 * 128];
+  __shared__ float slots[kBackThreads / 64];
+  const int64_t f = blockIdx.x / K;
+  const int t = int(blockIdx.x % K);
+  const FrameDesc& de = model_desc(p, f);
+  const int D = de.ndim;
+  const int tid = threadIdx.x;
+  const int64_t fb = frame_bucket_base(p, f);
+  float pp = 0.f, qq = 0.f;
+  float2 pq = make_float2(0.f, 0.f), rp = make_float2(0.f, 0.f), rq = make_float2(0.f, 0.f);
+  for (int s = 0; s < T; ++s) {
+    const int64_t base = ((f * T + s) * K + t) * int64_t(sum_b);
+    __syncthreads();
+    for (int i = tid; i < sum_b; i += kBackThreads) {
+      sg[i] = G[base + i];
+      sq[i] = G2[base + i];
+    }
+    __syncthreads();
+    for (int k = tid; k < de.B; k += kBackThreads) {
+      const int64_t at = fb + int64_t(s) * de.B + k;
+      const float2 m = model[at];
+      const float2 y = observed[at];
+      const float2 r = make_float2(m.x - y.x, m.y - y.y);
+      float2 P = make_float2(1.f, 0.f), Q = make_float2(1.f, 0.f);
+      int acc_off = 0;
+#pragma unroll
+      for (int d = 0; d < kMaxDims; ++d) {
+        if (d < D) {
+          const int i = acc_off + ((k >> de.bshift[d]) & (de.b[d] - 1));
+          P = cmul(P, sg[i]);
+          Q = cmul(Q, sq[i]);
+          acc_off += de.b[d];
+        }
+      }
+      pp += P.x * P.x + P.y * P.y;
+      qq += Q.x * Q.x + Q.y * Q.y;
+      const float2 a = cmulc(Q, P);    // conj(P) Q
+      pq.x += a.x;
+      pq.y += a.y;
+      const float2 b = cmulc(r, P);    // conj(P) r
+      rp.x += b.x;
+      rp.y += b.y;
+      const float2 c = cmulc(r, Q);    // conj(Q) r
+      rq.x += c.x;
+      rq.y += c.y;
+    }
+  }
+  const double PP = block_sum(pp, slots), QQ = block_sum(qq, slots);
+  const double pqr = block_sum(pq.x, slots), pqi = block_sum(pq.y, slots);
+  const double rpr = block_sum(rp.x, slots), rpi = block_sum(rp.y, slots);
+  const double rqr = block_sum(rq.x, slots), rqi = block_sum(rq.y, slots);
+  if (tid != 0) return;
+  const int64_t it = f * K + t;
+  const float2 bf = amps[it];
+  const double br = bf.x, bi = bf.y;
+  const double rad = radius[it];
+  bool accept = false;
+  double bpr = 0.0, bpi = 0.0;
+  if (QQ > 0.0) {
+    // b' = (b conj(pq) - rq) / qq
+    bpr = (br * pqr + bi * pqi - rqr) / QQ;
+    bpi = (bi * pqr - br * pqi - rqi) / QQ;
+    // <r, delta> = b' conj(rq) - b conj(rp)
+    const double rdr = (bpr * rqr + bpi * rqi) - (br * rpr + bi * rpi);
+    // |delta|^2 = |b'|^2 qq + |b|^2 pp - 2 Re(conj(b') b conj(pq))
+    const double cbr = bpr * br + bpi * bi;          // conj(b') b
+    const double cbi = bpr * bi - bpi * br;
+    const double cross = cbr * pqr + cbi * pqi;      // Re((cbr + j cbi)(pqr - j pqi))
+    const double dd = (bpr * bpr + bpi * bpi) * QQ + (br * br + bi * bi) * PP - 2.0 * cross;
+    accept = 2.0 * rdr + dd < 0.0;
+  }
+  if (accept) {
+    for (int d = 0; d < D; ++d) freqs[it * D + d] = fcand[it * D + d];
+    amps[it] = make_float2(float(bpr), float(bpi));
+    radius[it] = 2.0 * rad < max_radius ? 2.0 * rad : max_radius;
+  } else {
+    if (PP > 0.0) amps[it] = make_float2(float(br - rpr / PP), float(bi - rpi / PP));
+    radius[it] = 0.5 * rad;
+  }
+}
+
+// sum_{s,k} |model - observed|^2 of each frame, in FP64 (one work-group per frame)
+__global__ __launch_bounds__(kBackThreads) void refine_loss_kernel(DevPtrs p, int T,
+                                                                   const float2* __restrict__ model,
+                                                                   const float2* __restrict__ observed,
+                                                                   double* __restrict__ loss) {
+  __shared__ double dslots[kBackThreads / 64];
+  const int64_t f = blockIdx.x;
+  const FrameDesc& de = model_desc(p, f);
+  const int64_t fb = frame_bucket_base(p, f);
+  const int64_t n = int64_t(T) * de.B;
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += kBackThreads) {
+    const float2 m = model[fb + k];
+    const float2 y = observed[fb + k];
+    const double dr = double(m.x) - double(y.x), di = double(m.y) - double(y.y);
+    acc += dr * dr + di * di;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) dslots[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < kBackThreads / 64; ++w) tot += dslots[w];
+    loss[f] = tot;
+  }
+}
+
+// trust radii of every tone set to r0 (a kernel rather than a memset, so
+// that the sequence can be captured)
+__global__ void refine_fill_kernel(double* __restrict__ radius, int64_t n, double r0) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) radius[i] = r0;
+}
+
+// Initial amplitude of every tone (one thread per (frame, tone)): the grid
+// cell nearest to f, floor(f_d N_d + 1/2) mod N_d; in each estimation round
+// s (the rounds of the descriptor's mask) the ratio of the observed bucket
+// y_s[j_s], j_s = M(cell, sigma_s) (Def. 3), to the unit-tone model
+// P_s[j_s] = prod_d G_{s,d}[j_{s,d}]; the ratio whose magnitude is the
+// median over the rounds (rank floor((n - 1) / 2) ascending, the earlier
+// round on ties) is the amplitude a; spread (when not NULL) gets
+// max_s |a_s - a| / |a| (infinity when a = 0).
+__global__ void initial_amp_kernel(DevPtrs p, const double* __restrict__ freqs, int64_t batch, int K,
+                                   int T, int sum_b, const float2* __restrict__ G,
+                                   const float2* __restrict__ observed, float2* __restrict__ amps,
+                                   float* __restrict__ spread) {
+  const int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (it >= batch * K) return;
+  const int64_t f = it / K;
+  const int t = int(it % K);
+  const FrameDesc& de = model_desc(p, f);
+  const int D = de.ndim;
+  const int64_t fb = frame_bucket_base(p, f);
+  uint32_t cell[kMaxDims];
+  for (int d = 0; d < D; ++d) {
+    const double v = floor(freqs[it * D + d] * double(de.n[d]) + 0.5);
+    const int64_t c = int64_t(v) % int64_t(de.n[d]);
+    cell[d] = uint32_t(c < 0 ? c + de.n[d] : c);
+  }
+  float2 ratio[kMaxRounds];
+  float mag[kMaxRounds];
+  int n = 0;
+  uint64_t rest = de.est_mask;
+  while (rest) {
+    const int s = __builtin_ctzll(rest);
+    rest &= rest - 1ull;
+    const float2* g = G + ((f * T + s) * K + t) * int64_t(sum_b);
+    float2 P = make_float2(1.f, 0.f);
+    int jf = 0, off = 0;
+    for (int d = 0; d < D; ++d) {
+      const uint32_t u = (uint32_t(de.sigma[s][d]) * cell[d]) & uint32_t(de.n[d] - 1);
+      const int jd = int(u >> de.lshift[d]);
+      P = cmul(P, g[off + jd]);
+      jf |= jd << de.bshift[d];
+      off += de.b[d];
+    }
+    const float2 y = observed[fb + int64_t(s) * de.B + jf];
+    const float den = P.x * P.x + P.y * P.y;
+    const float2 q = den > 0.f ? make_float2((y.x * P.x + y.y * P.y) / den, (y.y * P.x - y.x * P.y) / den)
+                               : make_float2(0.f, 0.f);
+    ratio[n] = q;
+    mag[n] = q.x * q.x + q.y * q.y;
+    ++n;
+  }
+  // the element of rank (n - 1) / 2 by magnitude (ties: the earlier round)
+  const int want = (n - 1) / 2;
+  float2 out = make_float2(0.f, 0.f);
+  for (int a = 0; a < n; ++a) {
+    int rank = 0;
+    for (int b2 = 0; b2 < n; ++b2)
+      rank += (mag[b2] < mag[a]) || (mag[b2] == mag[a] && b2 < a);
+    if (rank == want) out = ratio[a];
+  }
+  amps[it] = out;
+  if (spread) {
+    const float m2 = out.x * out.x + out.y * out.y;
+    float worst = 0.f;
+    for (int a = 0; a < n; ++a) {
+      const float dx = ratio[a].x - out.x, dy = ratio[a].y - out.y;
+      worst = fmaxf(worst, dx * dx + dy * dy);
+    }
+    spread[it] = m2 > 0.f ? sqrtf(worst / m2) : __builtin_huge_valf();
   }
 }
 
@@ -440,7 +673,61 @@ int launch_model_backward(const DevPtrs& p, const float2* amps, int64_t batch, i
   if (blocks <= 0) return hipSuccess;
   if (blocks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(model_backward_kernel, dim3(unsigned(blocks)), dim3(kBackThreads), 0, st, p, amps,
-                     K, T, sum_b, G, dG, grad_model, grad_freqs, grad_amps, step_freqs, step_amps);
+                     K, T, sum_b, G, dG, grad_model, grad_freqs, grad_amps, step_freqs, step_amps,
+                     static_cast<const float2*>(nullptr), static_cast<const double*>(nullptr),
+                     static_cast<const double*>(nullptr), static_cast<double*>(nullptr));
+  return hipGetLastError();
+}
+
+int launch_initial_amplitudes(const DevPtrs& p, const double* freqs, int64_t batch, int K, int D, int T,
+                              int maxB, int sum_b, float2* G, float2* dG, const float2* observed,
+                              float2* amps, float* spread, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t items = batch * T * D * int64_t(K);
+  if (items <= 0) return hipSuccess;
+  if (items >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  (void)maxB;
+  hipLaunchKernelGGL(model_basis_kernel, dim3(unsigned(items)), dim3(kBasisThreads), 0, st, p, freqs, K, D,
+                     T, sum_b, G, dG);
+  const int64_t n = batch * K;
+  hipLaunchKernelGGL(initial_amp_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, freqs, batch,
+                     K, T, sum_b, static_cast<const float2*>(G), observed, amps, spread);
+  return hipGetLastError();
+}
+
+int launch_refine(const DevPtrs& p, const float2* observed, double* freqs, float2* amps, int64_t batch,
+                  int K, int D, int T, int maxB, int sum_b, int steps, double trust_bins,
+                  const RefineWork& w, double* loss, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t items = batch * T * D * int64_t(K);
+  const int64_t tones = batch * int64_t(K);
+  if (items <= 0) return hipSuccess;
+  if (items >= (int64_t(1) << 31) || batch > 65535 || T > 65535) return hipErrorInvalidValue;
+  const dim3 cgrid{unsigned((maxB + kCombineThreads - 1) / kCombineThreads), unsigned(T), unsigned(batch)};
+  hipLaunchKernelGGL(refine_fill_kernel, dim3(unsigned((tones + 255) / 256)), dim3(256), 0, st, w.radius,
+                     tones, trust_bins);
+  for (int step = 0; step <= steps; ++step) {
+    hipLaunchKernelGGL(model_basis_kernel, dim3(unsigned(items)), dim3(kBasisThreads), 0, st, p, freqs, K, D,
+                       T, sum_b, w.G, w.dG);
+    hipLaunchKernelGGL(model_combine_kernel, cgrid, dim3(kCombineThreads), 0, st, p, amps, K, T, sum_b, w.G,
+                       w.model);
+    if (loss)
+      hipLaunchKernelGGL(refine_loss_kernel, dim3(unsigned(batch)), dim3(kBackThreads), 0, st, p, T,
+                         static_cast<const float2*>(w.model), observed, loss + int64_t(step) * batch);
+    if (step == steps) break;
+    hipLaunchKernelGGL(model_backward_kernel, dim3(unsigned(tones)), dim3(kBackThreads), 0, st, p,
+                       static_cast<const float2*>(amps), K, T, sum_b, static_cast<const float2*>(w.G),
+                       static_cast<const float2*>(w.dG), static_cast<const float2*>(w.model),
+                       static_cast<double*>(nullptr), static_cast<float2*>(nullptr),
+                       static_cast<double*>(nullptr), static_cast<float2*>(nullptr), observed,
+                       static_cast<const double*>(w.radius), static_cast<const double*>(freqs), w.fcand);
+    hipLaunchKernelGGL(model_basis_kernel, dim3(unsigned(items)), dim3(kBasisThreads), 0, st, p,
+                       static_cast<const double*>(w.fcand), K, D, T, sum_b, w.G2, w.dG2);
+    hipLaunchKernelGGL(refine_accept_kernel, dim3(unsigned(tones)), dim3(kBackThreads), 0, st, p, K, T, sum_b,
+                       static_cast<const float2*>(w.G), static_cast<const float2*>(w.G2),
+                       static_cast<const float2*>(w.model), observed, static_cast<const double*>(w.fcand),
+                       freqs, amps, w.radius, trust_bins);
+  }
   return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct FrameDesc {
   int32_t bitmap_words;                // ceil(N / 32)
   int32_t segments;                    // 1: round s reads segment s (input [T][N] per frame)
   int32_t pad0;
+  int64_t vtab_off;                    // uint32 [T][B_last][N_last / 32]: word-parallel vote tables
 };
 
 // Device-side view of a launch: pointers into the plan's arrays.
@@ -109,6 +110,11 @@ struct DevPtrs {
   // every compaction chunk, position p holding a frame congruent to p mod 8
   // (work-groups are dealt to the eight XCDs round-robin); (-1, -1) pads
   const int32_t* chunk_list;
+  // word-parallel vote: the tables of every descriptor (FrameDesc::vtab_off)
+  // and, for uneven plans whose frames differ in chunk count, [n][2] (frame,
+  // first chunk) groups of kVoteCpw chunks; (-1, -1) pads
+  const uint32_t* vote_tab;
+  const int32_t* vote_list;
 };
 
 // Launch configuration of the fold stage, chosen per plan.
@@ -128,11 +134,18 @@ int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
 int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw,
                int identity_relabel, int nchunks_override, const int32_t* order, void* stream);
 // vote paths: per cell (any shape), rows of 64..4096 cells (T <= 4), rows of
-// exactly 32 cells (bit-parallel masks)
-constexpr int kVoteCells = 0, kVoteRows = 1, kVoteMasks32 = 2;
-// nlist > 0: one work-group per chunk_list entry (whole batch, frame0 = 0)
+// exactly 32 cells (bit-parallel masks), rows of 128..4096 cells (word-
+// parallel masks, any T)
+constexpr int kVoteCells = 0, kVoteRows = 1, kVoteMasks32 = 2, kVoteWords = 3;
+constexpr int kVoteCpw = 4;   // compaction chunks per work-group of the word-parallel vote
+// nlist > 0: one work-group per chunk_list entry (whole batch, frame0 = 0);
+// the word-parallel vote instead takes vote_list (nvlist > 0: one work-group
+// per (frame, first chunk) entry, groups of kVoteCpw chunks). tab_words: LDS
+// words of that vote's per-round table, the largest B_last * N_last / 32 of
+// the plan
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
-                int max_words, int dims_mask, int vote_path, int frame0, int64_t nlist, void* stream);
+                int max_words, int dims_mask, int vote_path, int frame0, int64_t nlist, int64_t nvlist,
+                int tab_words, void* stream);
 // items: 1 also lists the estimate's overflow items (plans with overflow
 // workers); fpb: frames per work-group (1, or 256 / chunks per frame in a
 // uniform plan of at most 128 chunks per frame)
@@ -152,6 +165,23 @@ int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int plane, int pad,
 int launch_model_forward(const DevPtrs& p, const double* freqs, const float2* amps, int64_t batch,
                          int K, int D, int T, int maxB, int sum_b, float2* G, float2* dG,
                          float2* model, void* stream);
+// Workspace of a refinement: factors at f (G, dG) and at the candidate
+// frequencies (G2, dG2), [batch][T][K][sum_b] each; the model, in the bucket
+// layout; per tone the trust radius (bins) and the candidate frequencies.
+struct RefineWork {
+  float2 *G, *dG, *G2, *dG2, *model;
+  double *radius, *fcand;
+};
+// Initial amplitudes of tones at `freqs` from the observed buckets (G, dG:
+// factor scratch of one model).
+int launch_initial_amplitudes(const DevPtrs& p, const double* freqs, int64_t batch, int K, int D, int T,
+                              int maxB, int sum_b, float2* G, float2* dG, const float2* observed,
+                              float2* amps, float* spread, void* stream);
+// `steps` refinement steps in place on freqs / amps; loss (may be NULL):
+// [steps + 1][batch] FP64 losses before each step and after the last.
+int launch_refine(const DevPtrs& p, const float2* observed, double* freqs, float2* amps, int64_t batch,
+                  int K, int D, int T, int maxB, int sum_b, int steps, double trust_bins,
+                  const RefineWork& w, double* loss, void* stream);
 // Device address of the library's static scratch array on `device`, which
 // must be the current device (resolved once per device, then cached).
 int static_scratch(int device, void** out);

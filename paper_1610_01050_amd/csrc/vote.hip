@@ -358,9 +358,230 @@ __global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int 
   }
 }
 
+// vote_words_kernel (rows of 128..4096 cells, any T): the word-parallel
+// form of the 32-cell mask vote. A row of N_last cells is W = N_last / 32
+// words. Cell x of the row lands in bucket column b_s(x) = [sigma_{s,last}
+// x]_{N_last} >> log2 L_last in round s (Def. 3), and the cells of column b
+// are the L_last preimages x = [sigma_inv u] for u in [b L, (b+1) L)
+// (Def. 4). The plan holds per descriptor the tables M_s[b][w] (bit x of
+// word w set when cell 32 w + x lies in column b). Per round a work-group
+// copies that round's table and flags into LDS, then each thread ORs, for
+// the 128 cells (four words) it owns in each of its kVoteCpw chunks, the
+// table rows of the flagged columns of the row's B_last-bit flag window:
+// one 16-byte LDS read per flagged bucket instead of one bucket lookup per
+// cell. The T round masks are combined by a bit-sliced counter of NB bits
+// and compared with mu (NB = 0: mu = T, a plain AND), giving the same bits
+// as the per-cell sum of eq. a_i. One work-group per group of kVoteCpw
+// consecutive compaction chunks of a frame (so the table copies are shared
+// by kVoteCpw chunks); each thread writes its four bitmap words per chunk
+// with one store.
+constexpr int kWordsPerVoteThread = 4;
+
+// Loads of round s's table pieces and flag words of this thread (see
+// vote_words_kernel), all issued before any is used.
+template <int kTabPer, int kFlagPer>
+__device__ __forceinline__ void vote_prefetch(uint4 (&tnext)[kTabPer], uint32_t (&fnext)[kFlagPer],
+                                              const uint32_t* gtab, const uint32_t* fl, int s, uint32_t ntab,
+                                              uint32_t npiece, int words) {
+  const uint4* src = reinterpret_cast<const uint4*>(gtab + int64_t(s) * ntab);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kTabPer; ++k) {
+    const uint32_t i = uint32_t(tid) + uint32_t(k) * kVoteThreads;
+    tnext[k] = i < npiece ? src[i] : make_uint4(0u, 0u, 0u, 0u);
+  }
+#pragma unroll
+  for (int k = 0; k < kFlagPer; ++k) {
+    const int i = tid + k * kVoteThreads;
+    fnext[k] = i < words ? fl[int64_t(s) * words + i] : 0u;
+  }
+}
+
+template <int D, int NB, int kTabPer>
+__global__ __launch_bounds__(kVoteThreads) void vote_words_kernel(DevPtrs p, int T, int mu, int frame0,
+                                                                 int use_list, int tab_words) {
+  extern __shared__ uint32_t smem[];
+  uint32_t* tab = smem;                       // [B_last][W] words of the current round
+  uint32_t* rflags = smem + tab_words;        // the current round's flag words
+  __shared__ uint32_t wcount[kVoteCpw][kVoteThreads / 64];
+  constexpr int kW = kWordsPerVoteThread;
+  constexpr int kAcc = NB > 0 ? NB : 1;
+  int64_t f;
+  int c0;
+  if (use_list) {
+    const int32_t* e = p.vote_list + 2 * int64_t(blockIdx.x);
+    f = e[0];
+    c0 = e[1];
+    if (f < 0) return;
+  } else {
+    f = frame0 + int64_t(blockIdx.y);
+    c0 = int(blockIdx.x) * kVoteCpw;
+  }
+  const FrameDesc& d = desc_of(p, f);
+  const int cch = d.cchunks, nd = d.ndim;   // loaded together, then tested
+  if ((c0 >= cch) | (nd != D)) return;
+  const int64_t rel = rel_of(p, f);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int words = d.words;
+  uint32_t nm[D], ls[D], bs[D], ns[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    nm[dd] = uint32_t(d.n[dd] - 1);
+    ls[dd] = uint32_t(d.lshift[dd]);
+    bs[dd] = uint32_t(d.bshift[dd]);
+    ns[dd] = uint32_t(d.nshift[dd]);
+  }
+  const uint32_t nl = nm[D - 1] + 1u;
+  const uint32_t bl = uint32_t(d.b[D - 1]);
+  const uint32_t W = nl >> 5;
+  const uint32_t ntab = bl * W;
+  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
+  const uint32_t* gtab = p.vote_tab + d.vtab_off;
+  const int q0 = tid * kW;                                  // first word of this thread in a chunk
+  const uint32_t w0 = uint32_t(q0) & (W - 1u);              // their word offset in the row (W >= 4)
+  bool active[kVoteCpw];
+  int64_t iw[kVoteCpw];                                     // first cell of those words
+#pragma unroll
+  for (int k = 0; k < kVoteCpw; ++k) {
+    const int64_t cell0 = int64_t(c0 + k) << kCompactShift;
+    const int64_t rem = d.N - cell0;
+    const int ncell = rem <= 0 ? 0 : int(rem < (int64_t(1) << kCompactShift) ? rem : (int64_t(1) << kCompactShift));
+    active[k] = c0 + k < cch && q0 < (ncell >> 5);
+    iw[k] = cell0 + (int64_t(q0) << 5);
+  }
+  uint32_t acc[kAcc][kVoteCpw * kW];
+#pragma unroll
+  for (int a = 0; a < kAcc; ++a)
+#pragma unroll
+    for (int q = 0; q < kVoteCpw * kW; ++q) acc[a][q] = NB > 0 ? 0u : ~0u;
+
+  // Round s's table and flags are loaded into registers while round s - 1
+  // is being voted (kTabPer 16-byte pieces per thread cover the plan's
+  // largest table, kFlagPer flag words B = 16384 buckets), then stored to
+  // LDS once every thread is done with the previous round.
+  constexpr int kFlagPer = kMaxBuckets / 32 / kVoteThreads;
+  const uint32_t npiece = ntab >> 2;
+  uint4 tnext[kTabPer];
+  uint32_t fnext[kFlagPer];
+  vote_prefetch<kTabPer, kFlagPer>(tnext, fnext, gtab, fl, 0, ntab, npiece, words);
+  for (int s = 0; s < T; ++s) {
+    __syncthreads();                                        // readers of the previous round are done
+#pragma unroll
+    for (int k = 0; k < kTabPer; ++k) {
+      const uint32_t i = uint32_t(tid) + uint32_t(k) * kVoteThreads;
+      if (i < npiece) reinterpret_cast<uint4*>(tab)[i] = tnext[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kFlagPer; ++k) {
+      const int i = tid + k * kVoteThreads;
+      if (i < words) rflags[i] = fnext[k];
+    }
+    __syncthreads();
+    if (s + 1 < T) vote_prefetch<kTabPer, kFlagPer>(tnext, fnext, gtab, fl, s + 1, ntab, npiece, words);
+#pragma unroll
+    for (int k = 0; k < kVoteCpw; ++k) {
+      uint32_t m0 = 0u, m1 = 0u, m2 = 0u, m3 = 0u;
+      if (active[k]) {
+        uint32_t rowpart = 0u;
+#pragma unroll
+        for (int dd = 0; dd < D - 1; ++dd) {
+          const uint32_t cd = uint32_t(iw[k] >> ns[dd]) & nm[dd];
+          rowpart |= (((uint32_t(d.sigma[s][dd]) * cd) & nm[dd]) >> ls[dd]) << bs[dd];
+        }
+        // the row's B_last flags: whole words when B_last >= 32, else a
+        // field (rowpart is a multiple of B_last: the window never straddles)
+        const int nw = bl >= 32u ? int(bl >> 5) : 1;
+        for (int kw = 0; kw < nw; ++kw) {
+          uint32_t win = rflags[(rowpart >> 5) + uint32_t(kw)];
+          if (bl < 32u) win = (win >> (rowpart & 31u)) & ((1u << bl) - 1u);
+          while (win) {
+            const uint32_t b = uint32_t(kw) * 32u + uint32_t(__ffs(win) - 1);
+            win &= win - 1u;
+            const uint4 v = *reinterpret_cast<const uint4*>(tab + b * W + w0);
+            m0 |= v.x;
+            m1 |= v.y;
+            m2 |= v.z;
+            m3 |= v.w;
+          }
+        }
+      }
+      const uint32_t m[kW] = {m0, m1, m2, m3};
+#pragma unroll
+      for (int q = 0; q < kW; ++q) {
+        if constexpr (NB == 0) {
+          acc[0][k * kW + q] &= m[q];
+        } else {
+          uint32_t carry = m[q];
+#pragma unroll
+          for (int a = 0; a < NB; ++a) {
+            const uint32_t t = acc[a][k * kW + q] & carry;
+            acc[a][k * kW + q] ^= carry;
+            carry = t;
+          }
+        }
+      }
+    }
+  }
+  uint32_t* bm = p.bitmap + d.bitmap_off + rel * d.bitmap_stride;
+#pragma unroll
+  for (int k = 0; k < kVoteCpw; ++k) {
+    uint32_t hit[kW];
+#pragma unroll
+    for (int q = 0; q < kW; ++q) {
+      if constexpr (NB == 0) {
+        hit[q] = acc[0][k * kW + q];
+      } else {
+        // acc >= mu, bit-sliced, most significant bit first
+        uint32_t ge = 0u, eq = ~0u;
+#pragma unroll
+        for (int a = NB - 1; a >= 0; --a) {
+          const uint32_t mk = ((uint32_t(mu) >> a) & 1u) ? ~0u : 0u;
+          ge |= eq & acc[a][k * kW + q] & ~mk;
+          eq &= ~(acc[a][k * kW + q] ^ mk);
+        }
+        hit[q] = ge | eq;
+      }
+    }
+    uint32_t cnt = 0u;
+    if (active[k]) {
+      *reinterpret_cast<uint4*>(bm + (iw[k] >> 5)) = make_uint4(hit[0], hit[1], hit[2], hit[3]);
+      cnt = uint32_t(__popc(hit[0]) + __popc(hit[1]) + __popc(hit[2]) + __popc(hit[3]));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0) wcount[k][wave] = cnt;
+  }
+  __syncthreads();
+  if (tid < kVoteCpw && c0 + tid < cch) {
+    uint32_t total = 0u;
+    for (int w = 0; w < kVoteThreads / 64; ++w) total += wcount[tid][w];
+    p.chunk_counts[d.chunk_off + rel * d.chunk_stride + c0 + tid] = total;
+  }
+}
+
+// counters of NB bits hold counts up to T; NB = 0: mu = T (a plain AND);
+// TP table pieces of 16 bytes per thread
+template <int D, int TP>
+static void launch_vote_words(dim3 grid, size_t shmem, hipStream_t st, const DevPtrs& p, int T, int mu,
+                              int frame0, int use_list, int tab_words) {
+  const size_t sh = size_t(tab_words) * 4 + shmem;
+  if (mu == T) hipLaunchKernelGGL((vote_words_kernel<D, 0, TP>), grid, dim3(kVoteThreads), sh, st, p, T, mu, frame0, use_list, tab_words);
+  else if (T <= 3) hipLaunchKernelGGL((vote_words_kernel<D, 2, TP>), grid, dim3(kVoteThreads), sh, st, p, T, mu, frame0, use_list, tab_words);
+  else if (T <= 7) hipLaunchKernelGGL((vote_words_kernel<D, 3, TP>), grid, dim3(kVoteThreads), sh, st, p, T, mu, frame0, use_list, tab_words);
+  else hipLaunchKernelGGL((vote_words_kernel<D, 7, TP>), grid, dim3(kVoteThreads), sh, st, p, T, mu, frame0, use_list, tab_words);
+}
+
 template <int D>
 static void launch_vote_d(const DevPtrs& p, dim3 grid, size_t shmem, hipStream_t st, int T, int mu,
-                          int frame0, int use_list, bool rows, bool masks) {
+                          int frame0, int use_list, bool rows, bool masks, bool wordsp, int tab_words) {
+  if (wordsp) {
+    if (tab_words <= 4 * 2 * kVoteThreads) launch_vote_words<D, 2>(grid, shmem, st, p, T, mu, frame0, use_list, tab_words);
+    else if (tab_words <= 4 * 8 * kVoteThreads) launch_vote_words<D, 8>(grid, shmem, st, p, T, mu, frame0, use_list, tab_words);
+    else launch_vote_words<D, 16>(grid, shmem, st, p, T, mu, frame0, use_list, tab_words);
+    return;
+  }
   if (masks) {   // counters of NB bits hold counts up to T
     if (T <= 3) hipLaunchKernelGGL((vote_mask_kernel<D, 2>), grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0, use_list);
     else if (T <= 7) hipLaunchKernelGGL((vote_mask_kernel<D, 3>), grid, dim3(kVoteThreads), shmem, st, p, T, mu, frame0, use_list);
@@ -380,19 +601,25 @@ static void launch_vote_d(const DevPtrs& p, dim3 grid, size_t shmem, hipStream_t
 }
 
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks, int max_words,
-                int dims_mask, int vote_path, int frame0, int64_t nlist, void* stream) {
+                int dims_mask, int vote_path, int frame0, int64_t nlist, int64_t nvlist, int tab_words,
+                void* stream) {
   if (nframes <= 0) return hipSuccess;
-  const size_t shmem = size_t(T) * size_t(max_words) * sizeof(uint32_t);
+  const bool wordsp = vote_path == kVoteWords;
+  // the word-parallel vote stages one round's flags; the others all rounds'
+  const size_t shmem = size_t(wordsp ? 1 : T) * size_t(max_words) * sizeof(uint32_t);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int use_list = nlist > 0 ? 1 : 0;
-  if (use_list && (frame0 != 0 || nlist >= (int64_t(1) << 31))) return hipErrorInvalidValue;
-  const dim3 grid = use_list ? dim3{unsigned(nlist), 1u, 1u} : dim3{unsigned(max_cchunks), unsigned(nframes), 1u};
+  // the word-parallel vote takes its own list of chunk groups
+  const int64_t list_len = wordsp ? nvlist : nlist;
+  const int use_list = list_len > 0 ? 1 : 0;
+  if (use_list && (frame0 != 0 || list_len >= (int64_t(1) << 31))) return hipErrorInvalidValue;
+  const int gx = wordsp ? (max_cchunks + kVoteCpw - 1) / kVoteCpw : max_cchunks;
+  const dim3 grid = use_list ? dim3{unsigned(list_len), 1u, 1u} : dim3{unsigned(gx), unsigned(nframes), 1u};
   const bool rows = vote_path == kVoteRows && T <= 4;
   const bool masks = vote_path == kVoteMasks32;
-  if (dims_mask & 1) launch_vote_d<1>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks);
-  if (dims_mask & 2) launch_vote_d<2>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks);
-  if (dims_mask & 4) launch_vote_d<3>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks);
-  if (dims_mask & 8) launch_vote_d<4>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks);
+  if (dims_mask & 1) launch_vote_d<1>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp, tab_words);
+  if (dims_mask & 2) launch_vote_d<2>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp, tab_words);
+  if (dims_mask & 4) launch_vote_d<3>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp, tab_words);
+  if (dims_mask & 8) launch_vote_d<4>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp, tab_words);
   return hipGetLastError();
 }
 

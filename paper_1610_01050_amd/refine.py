@@ -11,11 +11,13 @@ and B-point DFT of the plan). ``BucketModel`` exposes this model and its
 hand-written backward (HIP kernels behind rsft_model_forward /
 rsft_model_backward) as a torch.autograd.Function, with gradients with
 respect to the frequencies (float64) and the complex amplitudes (complex64).
-``refine`` fits frequencies and amplitudes to observed buckets by Gauss-Newton
-steps that the backward kernel solves per tone.
+``refine`` fits frequencies and amplitudes to observed buckets by per-tone
+trust-region Gauss-Newton steps with step acceptance (rsft_refine), and
+``initial_amplitudes`` gives detected tones their starting amplitudes
+(rsft_initial_amplitudes).
 
-Everything runs in the library's kernels; torch provides device memory, the
-autograd plumbing and the elementwise residual.
+Everything runs in the library's kernels; torch provides device memory and
+the autograd plumbing.
 """
 
 import torch
@@ -57,27 +59,66 @@ def model_loss(freqs, amps, plan, observed):
 
 
 @torch.no_grad()
-def refine(plan, observed, freqs, amps, steps=20, record_loss=True):
-    """Gauss-Newton refinement of (freqs, amps) against observed buckets
-    (flat complex64, layout of Plan.buckets()). Each step evaluates the model,
-    its residual and, in the backward kernel, every tone's Gauss-Newton step
-    over (b_t, f_t) (tones decoupled). Returns (freqs, amps, losses), losses
-    being the loss before each step and after the last (on the device)."""
+def refine(plan, observed, freqs, amps, steps=20, record_loss=True, trust_bins=0.25):
+    """Refinement of (freqs, amps) against observed buckets (flat complex64,
+    layout of Plan.buckets(); None: the plan's own buckets of the last
+    execute) by per-tone trust-region Gauss-Newton steps with step
+    acceptance, all in the library (rsft_refine). Returns (freqs, amps,
+    losses), losses [steps + 1, batch] (FP64, on the device) holding the loss
+    before each step and after the last, or None."""
     f = freqs.detach().clone().contiguous()
     a = amps.detach().clone().contiguous()
-    ws = plan.model_workspace(f.shape[0], f.shape[1])
-    model = torch.empty(plan.model_size(f.shape[0]), dtype=torch.complex64, device=f.device)
-    losses = []
-    for _ in range(steps):
-        plan.model_forward(f, a, ws, out=model)
-        r = model - observed
-        if record_loss:
-            losses.append((r.real.double() ** 2 + r.imag.double() ** 2).sum())
-        _, _, sf, sa = plan.model_backward(a, 2.0 * r, ws, steps=True)
-        f += sf
-        a += sa
-    if record_loss:
-        plan.model_forward(f, a, ws, out=model)
-        r = model - observed
-        losses.append((r.real.double() ** 2 + r.imag.double() ** 2).sum())
-    return f, a, (torch.stack(losses) if losses else None)
+    ws = plan.refine_workspace(f.shape[0], f.shape[1])
+    loss = (torch.empty((steps + 1) * f.shape[0], dtype=torch.float64, device=f.device)
+            if record_loss else None)
+    plan.refine(f, a, steps, ws, observed=observed, trust_bins=trust_bins, loss=loss)
+    return f, a, (loss.view(steps + 1, f.shape[0]) if record_loss else None)
+
+
+@torch.no_grad()
+def initial_amplitudes(plan, freqs, observed=None, with_spread=False):
+    """Starting amplitudes of tones at `freqs` (float64 [batch, K, D]) from
+    the buckets their nearest cells fall in (rsft_initial_amplitudes); with
+    with_spread also each tone's per-round spread."""
+    f = freqs.contiguous()
+    ws = plan.refine_workspace(f.shape[0], f.shape[1])
+    return plan.initial_amplitudes(f, ws, observed=observed, with_spread=with_spread)
+
+
+@torch.no_grad()
+def select_tones(plan, recs, K, candidates=4, max_spread=0.5, observed=None):
+    """Starting tones for refinement from a detection list (host-side choice
+    of which detections to refine): per frame the candidates * K peak
+    records of largest magnitude, their amplitudes and per-round spreads
+    from rsft_initial_amplitudes, then the K of largest magnitude among
+    those with spread <= max_spread (a peak whose rounds disagree is the
+    Remark-1 ambiguity, not a tone), filled up with the strongest remaining
+    candidates when fewer pass. Returns (freqs float64 [batch, K, D],
+    amps complex64 [batch, K], passed [batch]) on the device."""
+    import numpy as np
+    batch = plan.last_batch
+    D = len(plan.descs[0]["shape"])
+    C = candidates * K
+    cand = np.zeros((batch, C, D))
+    for f in range(batch):
+        sel = recs[(recs["frame"] == f) & (recs["is_peak"] == 1)]
+        sel = sel[np.argsort(-sel["magnitude"], kind="stable")][:C]
+        if len(sel) == 0:
+            continue
+        cand[f, :len(sel)] = sel["freq"][:, :D]
+        cand[f, len(sel):] = sel["freq"][0, :D]
+    fc = torch.tensor(cand, dtype=torch.float64, device="cuda").contiguous()
+    ac, sp = initial_amplitudes(plan, fc, observed=observed, with_spread=True)
+    ok = (sp <= max_spread).cpu().numpy()
+    freqs = np.zeros((batch, K, D))
+    pick = np.zeros((batch, K), dtype=np.int64)
+    passed = np.zeros(batch, dtype=np.int64)
+    for f in range(batch):
+        order = [c for c in range(C) if ok[f, c]]
+        passed[f] = min(len(order), K)
+        order += [c for c in range(C) if not ok[f, c]]
+        pick[f] = order[:K]
+        freqs[f] = cand[f, pick[f]]
+    idx = torch.tensor(pick, device="cuda")
+    amps = torch.gather(ac, 1, idx).contiguous()
+    return torch.tensor(freqs, dtype=torch.float64, device="cuda").contiguous(), amps, passed

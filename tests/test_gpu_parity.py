@@ -57,12 +57,16 @@ CASES = {
     # 7-bit vote counters
     "rows_of_32_T5_mu3": ((256, 32), (16, 8), 5, 3, "c64", 2, 4, 1e-3, 60.0),
     "rows_of_32_T9_mu5": ((128, 32), (8, 4), 9, 5, "c64", 1, 3, 1e-3, 60.0),
+    # the word-parallel vote's largest table (B_last * N_last / 32 = 16384 words)
+    "rows_of_4096_b128": ((64, 4096), (8, 128), 3, 0, "c64", 1, 4, 1e-3, 60.0),
+    "rows_of_128_T6_mu4": ((256, 128), (16, 8), 6, 4, "c64", 2, 4, 1e-3, 60.0),
 }
 
 
-def _run_case(name, per_frame=False, noise="known"):
+def _run_case(name, per_frame=False, noise="known", vote_words=1):
+    from paper_1610_01050_amd import OPT_VOTE_WORDS
     shape, buckets, T, mu, dtype, batch, K, pfa, atten = CASES[name]
-    print(f"case {name} per_frame={per_frame} noise={noise}", flush=True)
+    print(f"case {name} per_frame={per_frame} noise={noise} vote_words={vote_words}", flush=True)
     npdt = np.complex128 if dtype == "c128" else np.complex64
     frames = []
     freqs = []
@@ -75,6 +79,7 @@ def _run_case(name, per_frame=False, noise="known"):
     plan = _plan(shape=shape, buckets=buckets, rounds=T, sigma=sigma, window_atten_db=atten,
                  flat_atten_db=flat, pfa=pfa, mu=mu, dtype=dtype, max_batch=batch,
                  noise_mode=noise, max_detections=1 << 18)
+    plan.set_option(OPT_VOTE_WORDS, vote_words)
     xd = torch.from_numpy(np.stack(frames)).to("cuda")
     if per_frame:
         plan.execute_per_frame(xd)
@@ -113,13 +118,17 @@ def test_estimated_noise_floor_matches_oracle(name):
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["ongrid_256x256_c128", "cube_256x128x32", "four_dim",
-                                  "five_rounds_mu3", "one_dim_4096", "rows_of_32_T5_mu3",
-                                  "rows_of_32_T9_mu5"])
-def test_votes_bit_exact_from_oracle_flags(name):
+@pytest.mark.parametrize("name,vote_words", [
+    ("ongrid_256x256_c128", 1), ("ongrid_256x256_c128", 0), ("cube_256x128x32", 1),
+    ("four_dim", 1), ("five_rounds_mu3", 1), ("one_dim_4096", 1), ("one_dim_4096", 0),
+    ("rows_of_32_T5_mu3", 1), ("rows_of_32_T9_mu5", 1), ("offgrid_1024x1024", 1),
+    ("offgrid_1024x1024", 0), ("rows_of_4096_b128", 1), ("rows_of_128_T6_mu4", 1),
+    ("short_rows_512x64", 1)])
+def test_votes_bit_exact_from_oracle_flags(name, vote_words):
     """Voting, second stage and ordering are integer work: given the oracle's
-    flags, the detections and their votes must match exactly."""
-    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name)
+    flags, the detections and their votes must match exactly (word-parallel
+    masks where the rows suit them, and the candidate enumeration)."""
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name, vote_words=vote_words)
     words = np.concatenate([pack_flags(r["flags"]).ravel() for r in refs]).view(np.int32)
     plan.vote_flags(torch.from_numpy(words.copy()).to("cuda"))
     recs2, counts2 = plan.detect()

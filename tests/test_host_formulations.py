@@ -7,6 +7,11 @@ its plain definition (no GPU, no shared code with the HIP path).
   buckets; a bit-sliced counter adds the rounds and a bit-sliced comparison
   with mu gives the detections. Must equal {i : sum_s c_s[M(i, sigma_s)] >=
   mu} (Def. 3, eq. a_i) cell by cell.
+* The word-parallel vote of rows of 128..4096 cells: per round a table
+  M_s[b][w] built by scattering each column's preimages x = [sigma^-1 u]
+  (Def. 4), the OR of the flagged columns' table rows over four words at a
+  time, and the rounds combined by AND (mu = T) or a bit-sliced counter.
+  Must equal the same per-cell sum.
 * Segmented scan of many small frames in one 256-wide block: each frame's
   exclusive chunk offsets, records and overflow items (records beyond the
   first 1024 of a chunk that fit the frame's capacity, in items of 256) must
@@ -87,6 +92,78 @@ def test_mask32_vote_equals_per_cell_sum(shape, buckets, T, mu, p):
     flags = [rng.random(int(np.prod(buckets))) < p for _ in range(T)]
     want = votes_per_cell(shape, buckets, sigma, flags, mu)
     got = votes_mask32(shape, buckets, sigma, flags, mu)
+    assert np.array_equal(got, want)
+    assert 0 < want.sum() < want.size       # both outcomes occur
+
+
+def votes_words(shape, buckets, sigma, flags, mu):
+    """The word-parallel form for rows of 128..4096 cells (four words per
+    thread, tables rebuilt per round)."""
+    D, T = len(shape), len(sigma)
+    nl, bl = shape[-1], buckets[-1]
+    W = nl // 32
+    L = nl // bl
+    nb = 0 if mu == T else 2 if T <= 3 else 3 if T <= 7 else 7
+    nwords = int(np.prod(shape)) // 32
+    acc = np.zeros((max(nb, 1), nwords), dtype=np.uint64)
+    if nb == 0:
+        acc[:] = 0xFFFFFFFF
+    for s, sig in enumerate(sigma):
+        sinv = pow(int(sig[-1]), -1, nl)
+        tab = np.zeros((bl, W), dtype=np.uint64)
+        for u in range(nl):                     # scatter the preimages
+            x = (sinv * u) % nl
+            tab[u // L, x // 32] |= np.uint64(1 << (x % 32))
+        for g in range(0, nwords, 4):           # one thread: four words of one row
+            coords = np.unravel_index(g * 32, shape)
+            rowpart = 0
+            for d in range(D - 1):
+                Ld = shape[d] // buckets[d]
+                rowpart = rowpart * buckets[d] + ((sig[d] * coords[d]) % shape[d]) // Ld
+            rowpart *= bl
+            w0 = g % W
+            m = np.zeros(4, dtype=np.uint64)
+            for b in range(bl):
+                if flags[s][rowpart + b]:
+                    m |= tab[b, w0:w0 + 4]
+            for q in range(4):
+                if nb == 0:
+                    acc[0, g + q] &= m[q]
+                    continue
+                carry = m[q]
+                for k in range(nb):
+                    t = acc[k, g + q] & carry
+                    acc[k, g + q] ^= carry
+                    carry = t
+    if nb == 0:
+        hit = acc[0]
+    else:
+        full = np.uint64(0xFFFFFFFF)
+        ge = np.zeros(nwords, dtype=np.uint64)
+        eq = np.full(nwords, full, dtype=np.uint64)
+        for k in range(nb - 1, -1, -1):
+            mk = full if (mu >> k) & 1 else np.uint64(0)
+            ge |= eq & acc[k] & (~mk & full)
+            eq &= ~(acc[k] ^ mk) & full
+        hit = ge | eq
+    bits = (hit[:, None] >> np.arange(32, dtype=np.uint64)[None, :]) & np.uint64(1)
+    return bits.astype(bool).ravel()
+
+
+@pytest.mark.parametrize("shape,buckets,T,mu,p", [
+    ((8, 1024), (4, 64), 3, 3, 0.3),
+    ((4, 4096), (2, 128), 3, 2, 0.2),
+    ((16, 128), (4, 8), 5, 3, 0.4),
+    ((4, 8, 256), (2, 4, 16), 9, 5, 0.5),
+    ((2, 2048), (2, 128), 1, 1, 0.1),
+    ((512,), (32,), 4, 4, 0.6),
+])
+def test_word_parallel_vote_equals_per_cell_sum(shape, buckets, T, mu, p):
+    rng = np.random.default_rng(sum(shape) * 17 + T)
+    sigma = [[int(rng.integers(0, n // 2)) * 2 + 1 for n in shape] for _ in range(T)]
+    flags = [rng.random(int(np.prod(buckets))) < p for _ in range(T)]
+    want = votes_per_cell(shape, buckets, sigma, flags, mu)
+    got = votes_words(shape, buckets, sigma, flags, mu)
     assert np.array_equal(got, want)
     assert 0 < want.sum() < want.size       # both outcomes occur
 

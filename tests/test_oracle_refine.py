@@ -112,3 +112,110 @@ def test_gauss_newton_converges_quadratically_on_noise_free_tone():
     err_bins = np.abs((f - freqs) * np.array(shape))
     assert err_bins.max() < 1e-7
     assert abs(a[0] / amps[0] - 1) < 1e-7
+
+
+def test_factored_model_equals_full_grid_round():
+    """The per-dimension evaluation of one tone's rounds (and of its
+    frequency derivatives) equals the literal full-grid rounds (2-D and 3-D,
+    off-grid tones, Chebyshev and rectangular windows)."""
+    rng = np.random.default_rng(31)
+    for shape, b, atten in (((64, 32), (8, 4), 60.0), ((16, 8, 32), (4, 2, 8), 60.0),
+                            ((32, 64), (4, 8), 0.0)):
+        plan = _plan(shape, b, atten=atten, flat=atten, seed=len(shape))
+        f = rng.random(len(shape))
+        want = RF.round_buckets(RF.tone_signal(shape, f), plan)
+        got = RF.factored_round_buckets(f, plan)
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+        for d in range(len(shape)):
+            want = RF.round_buckets(RF.tone_derivative_signal(shape, f, d), plan)
+            got = RF.factored_round_buckets(f, plan, dim=d)
+            assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_initial_amplitudes_exact_on_noise_free_tones():
+    """Noise-free observation of well-separated off-grid tones: the bucket
+    of each tone's nearest cell divided by the round's unit-tone response
+    returns the tone's amplitude: exactly for one tone; for several, within
+    the others' leakage into the bucket, whose L = 128 cells each carry
+    -60 dB sidelobes of random phase (about sqrt(L) 1e-3 = 1.1e-2 relative;
+    bound 3x that), the median over the three clean rounds setting aside a
+    round where another tone's main lobe shares the bucket."""
+    shape, b = (256, 128), (16, 16)
+    rng = np.random.default_rng(41)
+    plan = _plan(shape, b, seed=13)
+    freqs, amps = _tones(rng, shape, 1)
+    observed = RF.model(freqs, amps, plan)
+    got = RF.initial_amplitudes(freqs, plan, observed)
+    assert abs(got[0] - amps[0]) <= 1e-10 * abs(amps[0])
+    plan = _plan(shape, b, seed=3)
+    assert R.estimation_rounds(plan) == [0, 1, 2]
+    freqs = np.array([[0.1037, 0.2021], [0.5512, 0.7043], [0.8301, 0.3379]])
+    amps = np.array([1.0 + 0.5j, -0.7 + 0.2j, 0.3 - 1.1j])
+    observed = RF.model(freqs, amps, plan)
+    got = RF.initial_amplitudes(freqs, plan, observed)
+    assert np.max(np.abs(got / amps - 1)) < 3 * np.sqrt(128) * 1e-3
+
+
+def test_amplitude_spread_of_tone_and_of_mixed_rounds():
+    """The spread max_s |a_s - a| / |a| of the per-round ratios: 0 (to
+    rounding) for a noise-free single tone; for observed buckets built as
+    c_s times the unit-tone model in round s (a different amplitude per
+    round, as when different tones fill a cell's buckets), the median-
+    magnitude c_s and max_s |c_s - c_med| / |c_med| exactly."""
+    shape, b = (256, 128), (16, 16)
+    plan = _plan(shape, b, seed=3)
+    assert R.estimation_rounds(plan) == [0, 1, 2]
+    rng = np.random.default_rng(71)
+    freqs, amps = _tones(rng, shape, 1)
+    a, sp = RF.initial_amplitudes(freqs, plan, RF.model(freqs, amps, plan), with_spread=True)
+    assert sp[0] < 1e-10
+    c = np.array([1.0 + 0.2j, -0.3 + 0.5j, 2.0 - 1.0j])     # magnitudes 1.02, 0.58, 2.24
+    P = RF.factored_round_buckets(freqs[0], plan)
+    observed = np.stack([c[s] * P[s] for s in range(3)])
+    a, sp = RF.initial_amplitudes(freqs, plan, observed, with_spread=True)
+    assert abs(a[0] - c[0]) < 1e-12
+    assert abs(sp[0] - np.max(np.abs(c - c[0])) / abs(c[0])) < 1e-12
+
+
+def test_nearest_cell_rounds_half_up():
+    plan = _plan((64, 32), (8, 4), seed=3)
+    assert RF.nearest_cell((10.5 / 64, 3.49 / 32), plan) == (11, 3)
+    assert RF.nearest_cell((63.6 / 64, -0.2 / 32), plan) == (0, 0)
+
+
+def test_refine_step_converges_on_noise_free_tone():
+    """One tone, noise-free: from 0.2 bin and 10% off, the accepted
+    trust-region steps reach the true frequency to 1e-7 bin and amplitude to
+    1e-7, and the loss never increases (for a single tone the tone's own
+    loss change is the total change, which the acceptance test requires to
+    be negative)."""
+    shape, b = (128, 64), (16, 8)
+    rng = np.random.default_rng(51)
+    plan = _plan(shape, b, seed=9)
+    freqs, amps = _tones(rng, shape, 1)
+    observed = RF.model(freqs, amps, plan)
+    f0 = freqs + np.array([[0.2 / shape[0], -0.15 / shape[1]]])
+    a0 = amps * (1.1 - 0.05j)
+    f, a, rad, losses = RF.refine(f0, a0, plan, observed, steps=8)
+    assert np.abs((f - freqs) * np.array(shape)).max() < 1e-7
+    assert abs(a[0] / amps[0] - 1) < 1e-7
+    assert all(l1 <= l0 * (1 + 1e-12) + 1e-20 for l0, l1 in zip(losses, losses[1:]))
+
+
+def test_refine_step_rejects_a_step_that_raises_the_loss():
+    """A step is kept only when it lowers the tone's own loss: at the exact
+    parameters every step is rejected, the frequency stays, the amplitude is
+    the least-squares one (the truth) and the trust radius halves; a start
+    far off with a tiny radius moves by at most that radius per step."""
+    shape, b = (64, 64), (8, 8)
+    rng = np.random.default_rng(61)
+    plan = _plan(shape, b, seed=4)
+    freqs, amps = _tones(rng, shape, 2)
+    observed = RF.model(freqs, amps, plan)
+    f, a, rad = RF.refine_step(freqs, amps, np.array([0.25, 0.25]), plan, observed)
+    assert np.array_equal(f, freqs)
+    assert np.max(np.abs(a - amps)) < 1e-9 * np.max(np.abs(amps))
+    assert np.allclose(rad, 0.125)
+    f0 = freqs + 0.3 / np.array(shape)
+    f, a, rad = RF.refine_step(f0, amps, np.array([0.01, 0.01]), plan, observed)
+    assert np.abs((f - f0) * np.array(shape)).max() <= 0.01 + 1e-12
