@@ -179,7 +179,7 @@ typedef struct {
   int32_t fold_nontemporal;  /* fold: 1 = non-temporal input loads */
   int32_t estimate_workers;  /* compact/estimate: 1 = overflow workers */
   int32_t vote_kernel;       /* 0 per cell, 1 candidate rows, 2 32-cell masks, 3 word-parallel masks */
-  int32_t reserved;
+  int32_t dft_two_pass;      /* 1: the DFT runs in two passes (RSFT_OPT_DFT_SPLIT) */
 } rsft_plan_info_t;
 
 typedef struct rsft_plan_s* rsft_plan_t;
@@ -219,6 +219,8 @@ rsft_status rsft_execute(rsft_plan_t plan, const void* d_input, int64_t batch,
  * - fold stage (the HBM-bound stage): work-group size (256 / 512 threads),
  *   samples per thread (4 / 2), ordinary vs non-temporal input loads; the
  *   fastest is kept and *best_ms (may be NULL) gets its average duration;
+ * - DFT, where both forms apply (RSFT_OPT_DFT_SPLIT): one work-group per
+ *   transform or two passes, the faster kept;
  * - vote, where both kernels apply (RSFT_OPT_VOTE_WORDS): word-parallel
  *   masks or the enumeration of candidate cells, the faster kept;
  * - compact/estimate: without or with overflow workers (the records of
@@ -443,7 +445,14 @@ enum {
      128..4096 cells and B_last * N_last / 32 <= 16384: 1 = word-parallel
      masks (default), 0 = enumeration of the candidate cells of flagged
      buckets (T <= 4; larger T keeps the masks). Same detections either way. */
-  RSFT_OPT_VOTE_WORDS = 6
+  RSFT_OPT_VOTE_WORDS = 6,
+  /* DFT stage for plans whose frames all have D >= 2, B / B_0 <= 4096 and
+     the KNOWN noise floor: 1 = two passes over many small work-groups (the
+     trailing dimensions per group of index-0 slabs, then dimension 0 per
+     group of output columns with the threshold), 0 = one work-group per
+     (round, frame). Same results (to FP32 rounding). Default 1; chosen by
+     rsft_autotune. */
+  RSFT_OPT_DFT_SPLIT = 7
 };
 rsft_status rsft_set_option(rsft_plan_t plan, int32_t option, int64_t value);
 

@@ -6,7 +6,8 @@ library has not been built.
 """
 
 from .binding import (  # noqa: F401
-    DETECTION_DTYPE, OPT_ESTIMATE_WORKERS, OPT_GRAPH, OPT_TIMING, OPT_VOTE_WORDS, STAGES, SYMBOLS, Plan, RsftError,
+    DETECTION_DTYPE, OPT_ESTIMATE_WORKERS, OPT_GRAPH, OPT_TIMING, OPT_VOTE_WORDS,
+    OPT_DFT_SPLIT, STAGES, SYMBOLS, Plan, RsftError,
     chebyshev_window, design_thresholds, draw_sigma, flat_window, load_library, mod_inverse,
     stage1_probability,
 )

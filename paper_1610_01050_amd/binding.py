@@ -33,6 +33,7 @@ OPT_GRAPH, OPT_TIMING = 0, 1
 OPT_FOLD_THREADS, OPT_FOLD_VEC, OPT_FOLD_NONTEMPORAL = 2, 3, 4
 OPT_ESTIMATE_WORKERS = 5
 OPT_VOTE_WORDS = 6
+OPT_DFT_SPLIT = 7
 STAGES = ("fold", "dft", "vote", "estimate")
 
 # Every symbol include/rsft.h declares.
@@ -118,7 +119,7 @@ class PlanInfo(ctypes.Structure):
         ("estimation_rounds", ctypes.c_uint64),
         ("fold_threads", ctypes.c_int32), ("fold_vec", ctypes.c_int32),
         ("fold_nontemporal", ctypes.c_int32), ("estimate_workers", ctypes.c_int32),
-        ("vote_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("vote_kernel", ctypes.c_int32), ("dft_two_pass", ctypes.c_int32),
     ]
 
 
@@ -478,6 +479,7 @@ class Plan:
                      "nontemporal": out.fold_nontemporal},
             "estimate_workers": out.estimate_workers,
             "vote_kernel": ("per_cell", "candidate_rows", "masks_32", "word_masks")[out.vote_kernel],
+            "dft_two_pass": out.dft_two_pass,
         }
 
     # -- bucketized forward model of complex tones (off-grid refinement) --

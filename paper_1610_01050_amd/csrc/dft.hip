@@ -89,6 +89,7 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ re, const flo
 // round of kDftWaves * R items holds whole groups (the tiles per group,
 // ceil(n/16) <= 8, divide 16), every item of a round is computed before any
 // of its outputs is written, and rounds touch disjoint lines.
+template <int kWaves>
 __device__ __forceinline__ void mode_product(float* __restrict__ re, float* __restrict__ im,
                                              const float2* __restrict__ tw, int n, int inner_shift,
                                              int nlines, int nl_shift) {
@@ -98,21 +99,21 @@ __device__ __forceinline__ void mode_product(float* __restrict__ re, float* __re
   const int krow = lane >> 4;
   const int nkt = (n + 15) >> 4;
   const int items = ((nlines + 15) >> 4) * nkt;
-  const int per_wave = (items + kDftWaves - 1) / kDftWaves;
+  const int per_wave = (items + kWaves - 1) / kWaves;
   const int R = per_wave < kDftItems ? per_wave : kDftItems;
   const int inner = 1 << inner_shift;
-  for (int r0 = 0; r0 < items; r0 += R * kDftWaves) {
+  for (int r0 = 0; r0 < items; r0 += R * kWaves) {
     floatx4 accR[kDftItems], accI[kDftItems];
 #pragma unroll
     for (int q = 0; q < kDftItems; ++q) {
-      const int item = r0 + q * kDftWaves + wave;
+      const int item = r0 + q * kWaves + wave;
       if (q < R && item < items)
         dft_tile(re, im, tw, n, inner_shift, nlines, nl_shift, item / nkt, item % nkt, accR[q], accI[q]);
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kDftItems; ++q) {
-      const int item = r0 + q * kDftWaves + wave;
+      const int item = r0 + q * kWaves + wave;
       if (q < R && item < items) {
         const int grp = item / nkt;
         const int kt = item % nkt;
@@ -146,6 +147,7 @@ __device__ __forceinline__ void mode_product(float* __restrict__ re, float* __re
 // the transform needs no barrier between reading and writing. Every
 // exponent is reduced modulo n as an integer before the table lookup
 // (W_16^a = tw[a r], W_r^a = tw[16 a]).
+template <int kWaves>
 __device__ __forceinline__ void mode_product_r16(float* __restrict__ re, float* __restrict__ im,
                                                  const float2* __restrict__ tw, int n, int inner_shift,
                                                  int nlines, int nl_shift) {
@@ -159,7 +161,7 @@ __device__ __forceinline__ void mode_product_r16(float* __restrict__ re, float* 
   const int inner = 1 << inner_shift;
   const int mask = n - 1;
   const int ntiles = ((nlines << rshift) + 15) >> 4;
-  for (int tile = wave; tile < ntiles; tile += kDftWaves) {
+  for (int tile = wave; tile < ntiles; tile += kWaves) {
     const int line = (tile << (4 - rshift)) + (col >> rshift);
     const bool lvalid = line < nlines;
     const int base = lvalid ? (line >> inner_shift) * n * inner + (line & (inner - 1)) : 0;
@@ -292,9 +294,9 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   for (int dd = 0; dd < d.ndim; ++dd) {
     const int n = d.b[dd];
     if (n >= 16)
-      mode_product_r16(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
+      mode_product_r16<kDftWaves>(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
     else
-      mode_product(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
+      mode_product<kDftWaves>(re, im, tws + twoff[dd], n, d.bshift[dd], B / n, nls);
   }
 
   float2* bout = p.buckets + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
@@ -384,6 +386,179 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// dft in two passes (frames of D >= 2, KNOWN noise floor): each round's
+// transform is spread over many small work-groups instead of one.
+//   pass 1: work-group (frame, round, slab group). A slab is the S = B / B_0
+//           buckets of one index along dimension 0; a group of G slabs
+//           (G S <= kSplitElems) sums its column-chunk partials into LDS and
+//           is transformed along dimensions 1 .. D-1 (the same mode
+//           products), then written in transform order to `inter`.
+//   pass 2: work-group (frame, round, column group). It owns C = min(S, 32)
+//           consecutive trailing output positions J' (the paper's indexing)
+//           for every index along dimension 0: it loads the transform
+//           columns K' = tau J' (per dimension, tau_{s,d} j_d mod B_d), the
+//           B_0-point DFT along dimension 0 in LDS, then reads row k_0 =
+//           tau_{s,0} j_0 for output row j_0 and writes buckets, squared
+//           magnitudes and flags: a group owns whole flag words (C = 32, or
+//           the whole transform when S < 32).
+// ---------------------------------------------------------------------------
+
+constexpr int kSplitThreads = 256;
+constexpr int kSplitWaves = kSplitThreads / 64;
+constexpr int kSplitElems = 4096;     // buckets per pass-1 work-group (at most)
+
+__device__ __forceinline__ int64_t split_frame(const int32_t* order, int64_t slot) {
+  return order ? int64_t(order[slot]) : slot;
+}
+
+__global__ __launch_bounds__(kSplitThreads) void dft_pass1_kernel(DevPtrs p, int T, float2* __restrict__ inter,
+                                                                  const int32_t* __restrict__ order) {
+  extern __shared__ float smem[];
+  const int64_t f = split_frame(order, blockIdx.z);
+  const int s = blockIdx.y;
+  const FrameDesc& d = desc_of(p, f);
+  const int nd = d.ndim, B = d.B, b0 = d.b[0];
+  const int S = B / b0;
+  const int G = S >= kSplitElems ? 1 : (kSplitElems / S < b0 ? kSplitElems / S : b0);
+  const int groups = b0 / G;
+  if (int(blockIdx.x) >= groups) return;
+  const int E = G * S;                          // buckets of this work-group
+  const int nls = __builtin_ctz(uint32_t(d.b[nd - 1]));
+  const int plane = E + (E >> nls);
+  float* re = smem;
+  float* im = smem + plane;
+  float2* tws = reinterpret_cast<float2*>(smem + 2 * plane);
+  const int tid = threadIdx.x;
+  const int64_t rel = rel_of(p, f);
+  // twiddles of dimensions 1 .. D-1, concatenated
+  int twoff[kMaxDims];
+  {
+    int acc = 0;
+#pragma unroll
+    for (int dd = 0; dd < kMaxDims; ++dd) {
+      twoff[dd] = acc;
+      if (dd >= 1 && dd < nd) {
+        const int bd = d.b[dd];
+        if (tid < bd) tws[acc + tid] = p.tw[d.tw_off[dd] + tid];
+        acc += bd;
+      }
+    }
+  }
+  const int e0 = int(blockIdx.x) * E;
+  const float2* part = p.part + d.part_off + rel * d.part_stride + int64_t(s) * B + e0;
+  const int nch = d.nchunks;
+  for (int e = tid; e < E; e += kSplitThreads) {
+    float2 v = part[e];
+    for (int c = 1; c < nch; ++c) {
+      const float2 w = part[int64_t(c) * T * B + e];
+      v.x += w.x;
+      v.y += w.y;
+    }
+    re[lds_at(e, nls)] = v.x;
+    im[lds_at(e, nls)] = v.y;
+  }
+  __syncthreads();
+  for (int dd = 1; dd < nd; ++dd) {
+    const int n = d.b[dd];
+    if (n == 1) continue;                       // a 1-point DFT is the identity
+    if (n >= 16)
+      mode_product_r16<kSplitWaves>(re, im, tws + twoff[dd], n, d.bshift[dd], E / n, nls);
+    else
+      mode_product<kSplitWaves>(re, im, tws + twoff[dd], n, d.bshift[dd], E / n, nls);
+  }
+  float2* out = inter + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B + e0;
+  for (int e = tid; e < E; e += kSplitThreads) out[e] = make_float2(re[lds_at(e, nls)], im[lds_at(e, nls)]);
+}
+
+__global__ __launch_bounds__(kSplitThreads) void dft_pass2_kernel(DevPtrs p, int T, const float2* __restrict__ inter,
+                                                                  const int32_t* __restrict__ order) {
+  extern __shared__ float smem[];
+  const int64_t f = split_frame(order, blockIdx.z);
+  const int s = blockIdx.y;
+  const FrameDesc& d = desc_of(p, f);
+  const int nd = d.ndim, B = d.B, b0 = d.b[0];
+  const int S = B / b0;
+  const int C = S < 32 ? S : 32;
+  if (int(blockIdx.x) >= S / C) return;
+  const int c0 = int(blockIdx.x) * C;
+  const int cs = __builtin_ctz(uint32_t(C));
+  const int E = b0 * C;
+  const int plane = E + (E >> cs);
+  float* re = smem;
+  float* im = smem + plane;
+  float2* tws = reinterpret_cast<float2*>(smem + 2 * plane);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t rel = rel_of(p, f);
+  if (tid < b0) tws[tid] = p.tw[d.tw_off[0] + tid];
+  const float2* src = inter + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
+  for (int e = tid; e < E; e += kSplitThreads) {
+    const int k0 = e >> cs;
+    const int jp = c0 + (e & (C - 1));         // trailing output position J'
+    int kp = 0;                                 // its transform column K'
+    for (int dd = 1; dd < nd; ++dd) {
+      const int bd = d.b[dd];
+      const int jd = (jp >> d.bshift[dd]) & (bd - 1);
+      kp |= ((d.tau[s][dd] * jd) & (bd - 1)) << d.bshift[dd];
+    }
+    const float2 v = src[int64_t(k0) * S + kp];
+    re[lds_at(e, cs)] = v.x;
+    im[lds_at(e, cs)] = v.y;
+  }
+  __syncthreads();
+  if (b0 >= 16)
+    mode_product_r16<kSplitWaves>(re, im, tws, b0, cs, C, cs);
+  else
+    mode_product<kSplitWaves>(re, im, tws, b0, cs, C, cs);
+  const int64_t fb = d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
+  float2* bout = p.buckets + fb;
+  float* pout = p.powers + fb;
+  uint32_t* fout = p.flags + d.flag_off + rel * d.flag_stride + int64_t(s) * d.words;
+  const double gamma = d.gamma[s];
+  const int t0 = d.tau[s][0];
+  for (int e00 = wave * 64; e00 < E; e00 += kSplitThreads) {
+    const int e = e00 + lane;
+    bool flag = false;
+    int j = 0;
+    if (e < E) {
+      const int j0 = e >> cs;
+      const int c = e & (C - 1);
+      const int k0 = (t0 * j0) & (b0 - 1);
+      const int at = lds_at((k0 << cs) | c, cs);
+      const float xr = re[at], xi = im[at];
+      const float pw = xr * xr + xi * xi;
+      j = j0 * S + c0 + c;
+      bout[j] = make_float2(xr, xi);
+      pout[j] = pw;
+      flag = double(pw) >= gamma;
+    }
+    const unsigned long long m = __ballot(flag);
+    // lanes 0..31 and 32..63 each cover 32 consecutive output buckets
+    // starting at a multiple of 32 (C = 32: one output row each; C = S:
+    // the transform in output order)
+    const int ja = __shfl(j, 0);
+    const int jb = __shfl(j, 32);
+    if (lane == 0) fout[ja >> 5] = uint32_t(m & 0xffffffffull);
+    if (lane == 32 && e < E) fout[jb >> 5] = uint32_t(m >> 32);
+  }
+}
+
+int launch_dft_split(const DevPtrs& p, int64_t nframes, int T, int max_b0, int max_groups1, int max_groups2,
+                     int sum_tw, float2* inter, const int32_t* order, void* stream) {
+  if (nframes <= 0) return hipSuccess;
+  if (nframes > 65535 || T > 65535) return hipErrorInvalidValue;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t sh1 = size_t(4 * kSplitElems) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
+  hipLaunchKernelGGL(dft_pass1_kernel, dim3(unsigned(max_groups1), unsigned(T), unsigned(nframes)),
+                     dim3(kSplitThreads), sh1, st, p, T, inter, order);
+  const size_t sh2 = size_t(2 * (max_b0 * 32 + max_b0)) * sizeof(float) + size_t(max_b0) * sizeof(float2);
+  hipLaunchKernelGGL(dft_pass2_kernel, dim3(unsigned(max_groups2), unsigned(T), unsigned(nframes)),
+                     dim3(kSplitThreads), sh2, st, p, T, static_cast<const float2*>(inter), order);
+  return hipGetLastError();
 }
 
 int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw, int identity,

@@ -74,6 +74,9 @@ struct rsft_plan_s {
   int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, est_nmask = 0;
   int rows_ok = 1, masks_ok = 1;   // every frame suits the row vote / the 32-cell mask vote
   int words_ok = 1;                // every frame suits the word-parallel vote
+  int split_ok = 1;                // every frame suits the two-pass DFT
+  int dft_split = 1;               // RSFT_OPT_DFT_SPLIT: use it (where it applies)
+  int split_b0 = 0, split_g1 = 0, split_g2 = 0;   // its launch extents
   int vote_words = 1;              // RSFT_OPT_VOTE_WORDS: prefer the word-parallel vote
   int tab_words = 0;               // LDS words of its per-round table (largest frame)
   int vote_path = rsft::kVoteCells;
@@ -86,7 +89,7 @@ struct rsft_plan_s {
   int scan_fpb = 1;              // frames per scan work-group
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles, d_chunk_list,
-      d_dft_order, d_vote_tab, d_vote_list;
+      d_dft_order, d_vote_tab, d_vote_list, d_inter;
   DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
       d_offsets, d_records, d_scan_done, d_chunk_items, d_item_counts, d_item_offsets;
   rsft::DevPtrs ptrs{};
@@ -450,7 +453,7 @@ void free_plan(rsft_plan_s* pl) {
   if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
   DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
                           &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_chunk_list,
-                          &pl->d_dft_order, &pl->d_vote_tab, &pl->d_vote_list, &pl->d_part,
+                          &pl->d_dft_order, &pl->d_vote_tab, &pl->d_vote_list, &pl->d_inter, &pl->d_part,
                           &pl->d_buckets, &pl->d_powers, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
                           &pl->d_scan_done, &pl->d_chunk_items, &pl->d_item_counts, &pl->d_item_offsets};
@@ -530,6 +533,18 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
       const int64_t tw = int64_t(d.b[d.ndim - 1]) * (nl / 32);
       if (nl < 128 || nl > 4096 || tw > 16384) pl->words_ok = 0;
       else pl->tab_words = std::max(pl->tab_words, int(tw));
+      // two-pass DFT extents: pass-1 groups of G slabs (S = B / B_0 buckets
+      // each, G S <= kSplitMaxSlab), pass-2 groups of min(S, 32) columns
+      const int b0 = d.b[0];
+      const int S = d.B / b0;
+      if (d.ndim < 2 || S > rsft::kSplitMaxSlab || d.noise_mode != RSFT_NOISE_KNOWN) {
+        pl->split_ok = 0;
+      } else {
+        const int G = std::min(rsft::kSplitMaxSlab / S, b0);
+        pl->split_b0 = std::max(pl->split_b0, b0);
+        pl->split_g1 = std::max(pl->split_g1, b0 / G);
+        pl->split_g2 = std::max(pl->split_g2, S / std::min(S, 32));
+      }
     }
     int sum_tw = 0;
     for (int k = 0; k < d.ndim; ++k) sum_tw += d.b[k];
@@ -662,6 +677,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = upload(pl->d_dft_order, dft_order)) != RSFT_OK) return st;
   if ((st = alloc(pl->d_part, size_t(part_off) * sizeof(float2))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_buckets, size_t(bucket_off) * sizeof(float2))) != RSFT_OK) return st;
+  if (pl->split_ok && (st = alloc(pl->d_inter, size_t(bucket_off) * sizeof(float2))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_powers, size_t(bucket_off) * sizeof(float))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_flags, size_t(flag_off) * sizeof(uint32_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_bitmap, size_t(bitmap_off) * sizeof(uint32_t))) != RSFT_OK) return st;
@@ -758,6 +774,21 @@ rsft_status estimate_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   return RSFT_OK;
 }
 
+// B-point DFT, threshold and flags of every round of the batch: the two-
+// pass kernels where they apply and are chosen, else one work-group per
+// (round, frame).
+rsft_status dft_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
+  const int32_t* order = pl->uniform ? nullptr : static_cast<const int32_t*>(pl->d_dft_order.ptr);
+  if (pl->split_ok && pl->dft_split) {
+    LAUNCH_TRY(rsft::launch_dft_split(pl->ptrs, batch, pl->T, pl->split_b0, pl->split_g1, pl->split_g2,
+                                      pl->sum_tw_max, static_cast<float2*>(pl->d_inter.ptr), order, st));
+  } else {
+    LAUNCH_TRY(rsft::launch_dft(pl->ptrs, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0,
+                                order, st));
+  }
+  return RSFT_OK;
+}
+
 // Reverse mapping, accumulation and second stage for the whole batch.
 rsft_status vote_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   LAUNCH_TRY(rsft::launch_vote(pl->ptrs, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask,
@@ -775,8 +806,10 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
     if (fs != RSFT_OK) return fs;
   }
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-  LAUNCH_TRY(rsft::launch_dft(q, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0,
-                              pl->uniform ? nullptr : static_cast<const int32_t*>(pl->d_dft_order.ptr), st));
+  {
+    const rsft_status ds = dft_stage(pl, batch, st);
+    if (ds != RSFT_OK) return ds;
+  }
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   {
     const rsft_status vs = vote_stage(pl, batch, st);
@@ -935,6 +968,23 @@ rsft_status rsft_autotune(rsft_plan_t pl, const void* d_input, int64_t batch, vo
       }
   if (st != RSFT_OK) return st;
   pl->fold = best;
+  // DFT: one work-group per transform, or the two-pass kernels; the fold
+  // of d_input leaves the partial buckets both read
+  if (pl->split_ok) {
+    if ((st = fold_stage(pl, d_input, batch, s, pl->fold)) != RSFT_OK) return st;
+    float dft_ms[2] = {0.f, 0.f};
+    for (int v = 0; v < 2; ++v) {
+      pl->dft_split = v;
+      if ((st = dft_stage(pl, batch, s)) != RSFT_OK) return st;
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < repeats && st == RSFT_OK; ++r) st = dft_stage(pl, batch, s);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      if (st != RSFT_OK) return st;
+      HIP_TRY(hipEventElapsedTime(&dft_ms[v], e0, e1));
+    }
+    pl->dft_split = dft_ms[1] <= dft_ms[0] ? 1 : 0;
+  }
   // estimate layout: one execute of d_input leaves its flags and detected-
   // cell bitmap; scan + compact/estimate (which only read those) are then
   // timed without and with overflow workers. Dense chunks favour the
@@ -1264,6 +1314,7 @@ rsft_status rsft_plan_info(rsft_plan_t pl, int64_t frame, rsft_plan_info_t* out)
   out->fold_nontemporal = pl->fold.nontemporal;
   out->estimate_workers = pl->est_workers;
   out->vote_kernel = pl->vote_path;
+  out->dft_two_pass = pl->split_ok && pl->dft_split ? 1 : 0;
   return RSFT_OK;
 }
 
@@ -1291,6 +1342,11 @@ rsft_status rsft_set_option(rsft_plan_t pl, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, "RSFT_OPT_VOTE_WORDS must be 0 or 1");
       pl->vote_words = int(value);
       choose_vote_path(pl);
+      drop_graphs(pl);
+      return RSFT_OK;
+    case RSFT_OPT_DFT_SPLIT:
+      if (value != 0 && value != 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, "RSFT_OPT_DFT_SPLIT must be 0 or 1");
+      pl->dft_split = int(value);
       drop_graphs(pl);
       return RSFT_OK;
     case RSFT_OPT_ESTIMATE_WORKERS:

@@ -63,8 +63,8 @@ CASES = {
 }
 
 
-def _run_case(name, per_frame=False, noise="known", vote_words=1):
-    from paper_1610_01050_amd import OPT_VOTE_WORDS
+def _run_case(name, per_frame=False, noise="known", vote_words=1, dft_split=1):
+    from paper_1610_01050_amd import OPT_DFT_SPLIT, OPT_VOTE_WORDS
     shape, buckets, T, mu, dtype, batch, K, pfa, atten = CASES[name]
     print(f"case {name} per_frame={per_frame} noise={noise} vote_words={vote_words}", flush=True)
     npdt = np.complex128 if dtype == "c128" else np.complex64
@@ -80,6 +80,7 @@ def _run_case(name, per_frame=False, noise="known", vote_words=1):
                  flat_atten_db=flat, pfa=pfa, mu=mu, dtype=dtype, max_batch=batch,
                  noise_mode=noise, max_detections=1 << 18)
     plan.set_option(OPT_VOTE_WORDS, vote_words)
+    plan.set_option(OPT_DFT_SPLIT, dft_split)
     xd = torch.from_numpy(np.stack(frames)).to("cuda")
     if per_frame:
         plan.execute_per_frame(xd)
@@ -99,6 +100,17 @@ def test_fused_path_matches_oracle(name):
     for f, ref in enumerate(refs):
         _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
         assert counts[f] == len(cells_from_records(recs, oplan.shape, f))
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["ongrid_256x256_c128", "offgrid_1024x1024", "cube_256x128x32",
+                                  "four_dim", "tiny_last_bucket", "max_rounds_64"])
+def test_single_workgroup_dft_matches_oracle(name):
+    """The DFT stage with one work-group per (round, frame) instead of the
+    two passes (RSFT_OPT_DFT_SPLIT = 0), the rest unchanged."""
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name, dft_split=0)
+    for f, ref in enumerate(refs):
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
     plan.close()
 
 
