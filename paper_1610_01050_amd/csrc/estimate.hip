@@ -42,13 +42,17 @@ namespace rsft {
 
 constexpr int kEstThreads = 256;
 constexpr int kEstAny = 0;   // template round count of the loop variant (any number of rounds)
+constexpr int kGainLds = kEstGainLds;
 
 // Per-frame constants of the estimate, uniform across the work-group.
-template <int D, int M>
+template <int D, int M, bool G>
 struct EstFrame {
   static constexpr int kM = M > 0 ? M : 1;
   uint32_t nm[D], lm[D], ls[D], bs[D], ns[D];
-  const float* ig[D];              // inverse flat-window gains per dimension
+  const float* ig[D];              // inverse flat-window gains per dimension (global)
+  const float* igs;                // the same in LDS (dimension d at goff[d]) when in_lds
+  uint32_t goff[D];
+  int mu, T;
   uint32_t sig_est[kM][D];
   const float* pw_est[kM];         // squared magnitudes |fhat_s|^2 of the estimation rounds
   const uint32_t* fl;              // flags [T][words]
@@ -59,10 +63,23 @@ struct EstFrame {
   int B;
 };
 
-template <int D, int M>
+// The inverse flat-window gain of dimension d at offset idx inside a
+// bucket: from the LDS copy, or (G: plans with a frame whose sum of L_d
+// exceeds kGainLds) from global memory.
+template <int D, int M, bool G>
+__device__ __forceinline__ float inv_gain(const EstFrame<D, M, G>& e, int dd, uint32_t idx) {
+  if constexpr (G) return e.ig[dd][idx];
+  else return e.igs[e.goff[dd] + idx];
+}
+
+// load_frame also copies the frame's inverse gains to `sgain` (LDS) when
+// they fit (all threads of the work-group call it; a barrier follows the
+// copy).
+template <int D, int M, bool G>
 __device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d, int64_t rel,
-                                           EstFrame<D, M>& e) {
+                                           EstFrame<D, M, G>& e, float* sgain) {
   const float* pw = p.powers + d.bucket_off + rel * d.bucket_stride;
+  uint32_t tot = 0u;
 #pragma unroll
   for (int dd = 0; dd < D; ++dd) {
     e.nm[dd] = uint32_t(d.n[dd] - 1);
@@ -71,7 +88,18 @@ __device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d,
     e.bs[dd] = uint32_t(d.bshift[dd]);
     e.ns[dd] = uint32_t(d.nshift[dd]);
     e.ig[dd] = p.inv_gains + d.gain_off[dd];
+    e.goff[dd] = tot;
+    tot += uint32_t(d.l[dd]);
   }
+  e.igs = sgain;
+  if constexpr (!G) {
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd)
+      for (uint32_t k = threadIdx.x; k <= e.lm[dd]; k += kEstThreads) sgain[e.goff[dd] + k] = e.ig[dd][k];
+  }
+  __syncthreads();
+  e.mu = d.mu;
+  e.T = d.T;
 #pragma unroll
   for (int q = 0; q < M; ++q) {
     const int s = d.est_rounds[q];
@@ -130,8 +158,8 @@ __device__ __forceinline__ double log_parabola_offset(float pm, float p0, float 
 // Squared gain-corrected magnitude of neighbour `code` (digit d of code in
 // base 3 is o_d + 1): the median over the estimation rounds, from the
 // per-round squared inverse gains g and bucket offsets jb of the offsets.
-template <int D, int M>
-__device__ __forceinline__ float neighbour_power(const EstFrame<D, M>& e, const float (&g)[M][D][3],
+template <int D, int M, bool G>
+__device__ __forceinline__ float neighbour_power(const EstFrame<D, M, G>& e, const float (&g)[M][D][3],
                                                  const uint32_t (&jb)[M][D][3], int code) {
   float v[M];
 #pragma unroll
@@ -153,8 +181,8 @@ __device__ __forceinline__ float neighbour_power(const EstFrame<D, M>& e, const 
 
 // The same for D = 4, from the permuted index u0[q][d] = [sigma c]_N of the
 // cell itself (no array indexed at run time).
-template <int D, int M>
-__device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, const uint32_t (&u0)[M][D],
+template <int D, int M, bool G>
+__device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M, G>& e, const uint32_t (&u0)[M][D],
                                                      int code) {
   float v[M];
 #pragma unroll
@@ -167,7 +195,7 @@ __device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, co
       const int o = c % 3 - 1;
       c /= 3;
       const uint32_t u = (u0[q][dd] + e.sig_est[q][dd] * uint32_t(o)) & e.nm[dd];
-      const float ig = e.ig[dd][u & e.lm[dd]];
+      const float ig = inv_gain(e, dd, u & e.lm[dd]);
       gg *= ig * ig;
       jf |= (u >> e.ls[dd]) << e.bs[dd];
     }
@@ -179,8 +207,8 @@ __device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M>& e, co
 // The same for any number of estimation rounds (kEstAny): the rounds of the
 // mask in increasing order, each value inserted into a sorted per-thread
 // array, then the median as in median_of.
-template <int D, int M>
-__device__ __forceinline__ float neighbour_power_any(const EstFrame<D, M>& e, const uint32_t (&cell)[D],
+template <int D, int M, bool G>
+__device__ __forceinline__ float neighbour_power_any(const EstFrame<D, M, G>& e, const uint32_t (&cell)[D],
                                                      int code) {
   float v[kMaxRounds];
   int n = 0;
@@ -197,7 +225,7 @@ __device__ __forceinline__ float neighbour_power_any(const EstFrame<D, M>& e, co
       c /= 3;
       const uint32_t sg = uint32_t(e.sig[s * kMaxDims + dd]);
       const uint32_t u = (sg * cell[dd] + sg * uint32_t(o)) & e.nm[dd];
-      const float ig = e.ig[dd][u & e.lm[dd]];
+      const float ig = inv_gain(e, dd, u & e.lm[dd]);
       gg *= ig * ig;
       jf |= (u >> e.ls[dd]) << e.bs[dd];
     }
@@ -226,9 +254,9 @@ constexpr bool on_axis(int code, int D) {
 // One record. D <= 3: the 3^D neighbourhood lives in registers (loops
 // unrolled); D = 4: its 81 values are kept in this thread's LDS column
 // `pcol` (stride kEstThreads) and visited by ordinary loops.
-template <int D, int M>
-__device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int64_t f,
-                                             unsigned long long flat, rsft_detection* out,
+template <int D, int M, bool G>
+__device__ __forceinline__ void write_record(const EstFrame<D, M, G>& e, int T, int64_t f,
+                                             unsigned long long flat, DetRec* out,
                                              float* pcol) {
   constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
   constexpr bool kRegs = D <= 3;
@@ -238,8 +266,9 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
   for (int dd = 0; dd < D; ++dd) cell[dd] = uint32_t(flat >> e.ns[dd]) & e.nm[dd];
   // votes: the flag of the cell's bucket in every round, four rounds' flag
   // words loaded at a time (s < s0 + 4 <= 64 stays inside the sigma table)
-  int votes = 0;
-  for (int s0 = 0; s0 < T; s0 += 4) {
+  // (every detected cell of a plan with mu = T has exactly T votes)
+  int votes = e.mu == T ? T : 0;
+  for (int s0 = 0; s0 < T && e.mu != T; s0 += 4) {
     uint32_t wd[4], sh[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -280,14 +309,14 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
   if constexpr (kRegs && M == kEstAny) {
 #pragma unroll
     for (int code = 0; code < kNb; ++code)
-      if (on_axis(code, D)) preg[code] = neighbour_power_any<D, M>(e, cell, code);
+      if (on_axis(code, D)) preg[code] = neighbour_power_any<D, M, G>(e, cell, code);
 #pragma unroll
     for (int code = 0; code < kNb; ++code)
       if (code != kCentre && on_axis(code, D)) visit(code, preg[kCentre], preg[code], peak);
     if (peak) {
 #pragma unroll
       for (int code = 0; code < kNb; ++code)
-        if (!on_axis(code, D)) visit(code, preg[kCentre], neighbour_power_any<D, M>(e, cell, code), peak);
+        if (!on_axis(code, D)) visit(code, preg[kCentre], neighbour_power_any<D, M, G>(e, cell, code), peak);
     }
   } else if constexpr (kRegs) {
     // Per round and dimension the three offsets o_d = -1, 0, 1 share one
@@ -304,7 +333,7 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
           const uint32_t u = (u0 + sg * uint32_t(o - 1)) & e.nm[dd];
-          const float ig = e.ig[dd][u & e.lm[dd]];
+          const float ig = inv_gain(e, dd, u & e.lm[dd]);
           g[q][dd][o] = ig * ig;
           jb[q][dd][o] = (u >> e.ls[dd]) << e.bs[dd];
         }
@@ -316,19 +345,19 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
     // AND over all of them, so the order does not change it).
 #pragma unroll
     for (int code = 0; code < kNb; ++code)
-      if (on_axis(code, D)) preg[code] = neighbour_power<D, M>(e, g, jb, code);
+      if (on_axis(code, D)) preg[code] = neighbour_power<D, M, G>(e, g, jb, code);
 #pragma unroll
     for (int code = 0; code < kNb; ++code)
       if (code != kCentre && on_axis(code, D)) visit(code, preg[kCentre], preg[code], peak);
     if (peak) {
 #pragma unroll
       for (int code = 0; code < kNb; ++code)
-        if (!on_axis(code, D)) visit(code, preg[kCentre], neighbour_power<D, M>(e, g, jb, code), peak);
+        if (!on_axis(code, D)) visit(code, preg[kCentre], neighbour_power<D, M, G>(e, g, jb, code), peak);
     }
   } else {
     if constexpr (M == kEstAny) {
 #pragma unroll 1
-      for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_any<D, M>(e, cell, code);
+      for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_any<D, M, G>(e, cell, code);
     } else {
       uint32_t u0[M][D];
 #pragma unroll
@@ -337,7 +366,7 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
         for (int dd = 0; dd < D; ++dd) u0[q][dd] = e.sig_est[q][dd] * cell[dd];
       }
 #pragma unroll 1
-      for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_dyn<D, M>(e, u0, code);
+      for (int code = 0; code < kNb; ++code) pcol[code * kEstThreads] = neighbour_power_dyn<D, M, G>(e, u0, code);
     }
     const float pc0 = pcol[kCentre * kEstThreads];
 #pragma unroll 1
@@ -349,47 +378,38 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M>& e, int T, int
     else return pcol[code * kEstThreads];
   };
   const float p0 = P(kCentre);
-  rsft_detection rec;
-  rec.frame = f;
+  DetRec rec;
+  rec.key = (unsigned long long)flat | ((unsigned long long)votes << kKeyVotesShift) |
+            ((peak ? 1ull : 0ull) << (kKeyVotesShift + 7));
+  rec.frame = uint32_t(f);
+  rec.magnitude = sqrtf(p0);
 #pragma unroll
-  for (int dd = 0; dd < kMaxDims; ++dd) {
-    rec.idx[dd] = 0;
-    rec.freq[dd] = 0.0;
-  }
+  for (int dd = 0; dd < kMaxDims; ++dd) rec.delta[dd] = 0.f;
   int stride = 1;
 #pragma unroll
   for (int dd = D - 1; dd >= 0; --dd) {
-    const double delta = log_parabola_offset(P(kCentre - stride), p0, P(kCentre + stride));
-    // N_d is a power of two: scaling by 2^-log2(N_d) equals the division exactly
-    double fr = ldexp(double(cell[dd]) + delta, -__builtin_ctz(e.nm[dd] + 1u));
-    if (fr < 0.0) fr += 1.0;
-    if (fr >= 1.0) fr -= 1.0;
-    rec.idx[dd] = cell[dd];
-    rec.freq[dd] = fr;
+    rec.delta[dd] = float(log_parabola_offset(P(kCentre - stride), p0, P(kCentre + stride)));
     stride *= 3;
   }
-  rec.votes = votes;
-  rec.is_peak = peak ? 1 : 0;
-  rec.magnitude = sqrtf(p0);
-  rec.reserved = 0.f;
   *out = rec;
 }
 
 // Records of list[0 .. min(n, room)) in batches of kEstThreads: each thread
 // builds one record in LDS, then the work-group copies the batch out with
-// contiguous 8-byte stores (a record is 88 bytes, 8-byte aligned).
-template <int D, int M>
+// contiguous 8-byte stores (a record is 32 bytes).
+template <int D, int M, bool G>
 __device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc& d, int64_t f,
                                               int64_t rel, int T, const uint32_t* list, int n,
-                                              unsigned long long cell0, rsft_detection* out,
-                                              int64_t room, float* pcol, rsft_detection* stage) {
-  EstFrame<D, M> e;
-  load_frame<D, M>(p, d, rel, e);
+                                              unsigned long long cell0, DetRec* out,
+                                              int64_t room, float* pcol, DetRec* stage,
+                                              float* sgain) {
+  EstFrame<D, M, G> e;
+  load_frame<D, M, G>(p, d, rel, e, sgain);
   const int lim = int(n < room ? n : room);
-  constexpr int kWords = int(sizeof(rsft_detection) / 8);
+  constexpr int kWords = int(sizeof(DetRec) / 8);
   for (int q0 = 0; q0 < lim; q0 += kEstThreads) {
     const int q = q0 + int(threadIdx.x);
-    if (q < lim) write_record<D, M>(e, T, f, cell0 | (unsigned long long)list[q], stage + threadIdx.x, pcol);
+    if (q < lim) write_record<D, M, G>(e, T, f, cell0 | (unsigned long long)list[q], stage + threadIdx.x, pcol);
     __syncthreads();
     const int nw = (lim - q0 < kEstThreads ? lim - q0 : kEstThreads) * kWords;
     const unsigned long long* src = reinterpret_cast<const unsigned long long*>(stage);
@@ -408,21 +428,22 @@ constexpr int est_waves(int D, int M) {
 
 // estimate_list for a frame of `ne` estimation rounds, 1 <= ne <= MMAX
 // (MMAX = kEstAny: any count, by the loop variant).
-template <int D, int MMAX>
+template <int D, int MMAX, bool G>
 __device__ __forceinline__ void estimate_list_n(int ne, const DevPtrs& p, const FrameDesc& d, int64_t f,
                                                 int64_t rel, int T, const uint32_t* list, int n,
-                                                unsigned long long cell0, rsft_detection* out,
-                                                int64_t room, float* pcol, rsft_detection* stage) {
+                                                unsigned long long cell0, DetRec* out,
+                                                int64_t room, float* pcol, DetRec* stage,
+                                                float* sgain) {
   if constexpr (MMAX == kEstAny) {
-    estimate_list<D, kEstAny>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage);
+    estimate_list<D, kEstAny, G>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage, sgain);
     return;
   }
   switch (ne) {
-    case 1: if constexpr (MMAX >= 1) estimate_list<D, 1>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
-    case 2: if constexpr (MMAX >= 2) estimate_list<D, 2>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
-    case 3: if constexpr (MMAX >= 3) estimate_list<D, 3>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
-    case 4: if constexpr (MMAX >= 4) estimate_list<D, 4>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
-    default: if constexpr (MMAX >= 5) estimate_list<D, 5>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage); break;
+    case 1: if constexpr (MMAX >= 1) estimate_list<D, 1, G>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage, sgain); break;
+    case 2: if constexpr (MMAX >= 2) estimate_list<D, 2, G>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage, sgain); break;
+    case 3: if constexpr (MMAX >= 3) estimate_list<D, 3, G>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage, sgain); break;
+    case 4: if constexpr (MMAX >= 4) estimate_list<D, 4, G>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage, sgain); break;
+    default: if constexpr (MMAX >= 5) estimate_list<D, 5, G>(p, d, f, rel, T, list, n, cell0, out, room, pcol, stage, sgain); break;
   }
 }
 
@@ -449,11 +470,11 @@ __device__ __forceinline__ int64_t wave_search(const int64_t* __restrict__ a, in
 // Records of ranks r_lo .. r_lo + n - 1 of chunk c of frame f: the work-group
 // lists those detected cells from the chunk's bitmap words wv (kWpt per
 // thread; popcounts and a block prefix sum) and builds their records.
-template <int D, int M, int kWpt>
+template <int D, int M, bool G, int kWpt>
 __device__ __forceinline__ void build_range(const DevPtrs& p, int T, const FrameDesc& d, int64_t f, int c,
                                             const uint32_t (&wv)[kWpt], int r_lo, int n, int64_t rank0,
-                                            uint32_t* list, uint32_t* wsum, rsft_detection* stage,
-                                            float* pcol) {
+                                            uint32_t* list, uint32_t* wsum, DetRec* stage,
+                                            float* pcol, float* sgain) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -486,8 +507,8 @@ __device__ __forceinline__ void build_range(const DevPtrs& p, int T, const Frame
     }
   }
   __syncthreads();
-  estimate_list_n<D, M>(d.n_est, p, d, f, rel_of(p, f), T, list, n, (unsigned long long)c << kCompactShift,
-                        p.records + p.offsets[f] + rank0 + r_lo, n, pcol, stage);
+  estimate_list_n<D, M, G>(d.n_est, p, d, f, rel_of(p, f), T, list, n, (unsigned long long)c << kCompactShift,
+                        p.records + p.offsets[f] + rank0 + r_lo, n, pcol, stage, sgain);
 }
 
 constexpr int kWordsPerThread = (1 << (kCompactShift - 5)) / kEstThreads;   // a chunk's bitmap words
@@ -522,7 +543,7 @@ __host__ __device__ constexpr bool serves(int M, int ne) {
 // pass, a denser one in passes of kListMax cells.
 constexpr int kListMax = 2048;   // cells listed at once: a chunk's, else one pass's
 
-template <int D, int M>
+template <int D, int M, bool G>
 __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est_waves(D, M)))) void compact_estimate_kernel(DevPtrs p, int T,
                                                                        int64_t nframes,
                                                                        int max_cchunks,
@@ -531,8 +552,9 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
   constexpr int kNb = D == 1 ? 3 : D == 2 ? 9 : D == 3 ? 27 : 81;
   __shared__ uint32_t list[kListMax];
   __shared__ uint32_t wsum[kEstThreads / 64];
-  __shared__ rsft_detection stage[kEstThreads];
+  __shared__ DetRec stage[kEstThreads];
   __shared__ float pbuf[D >= 4 ? kNb * kEstThreads : 1];
+  __shared__ float sgain[kGainLds];
   int64_t f;
   int c;
   if (!chunk_of(p, blockIdx.x, nframes, max_cchunks, xcd_groups, use_list, f, c)) return;
@@ -563,7 +585,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
   const int64_t rank0 = p.chunk_offsets[ck];
   const int64_t frame_off = p.offsets[f];
   if ((chunk_count == 0u) | (rank0 >= cap)) return;
-  rsft_detection* out = p.records + frame_off + rank0;
+  DetRec* out = p.records + frame_off + rank0;
   const unsigned long long cell0 = (unsigned long long)c << kCompactShift;
   const int64_t room0 = cap - rank0;
   float* pcol = pbuf + threadIdx.x;
@@ -599,7 +621,8 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
       }
     }
     __syncthreads();
-    estimate_list_n<D, M>(ne, p, d, f, rel, T, list, min(total, kListMax), cell0, out, room0, pcol, stage);
+    estimate_list_n<D, M, G>(ne, p, d, f, rel, T, list, min(total, kListMax), cell0, out, room0, pcol, stage,
+                          sgain);
     return;
   }
   // dense chunk: passes of kListMax / 32 words (at most kListMax cells each)
@@ -630,8 +653,8 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
       list[k++] = (uint32_t(w - w0) << 5) | uint32_t(bit);
     }
     __syncthreads();
-    estimate_list_n<D, M>(ne, p, d, f, rel, T, list, total, cell0, out + running, room0 - running, pcol,
-                        stage);
+    estimate_list_n<D, M, G>(ne, p, d, f, rel, T, list, total, cell0, out + running, room0 - running, pcol,
+                          stage, sgain);
     running += total;
     if (running >= room0) return;   // uniform: the frame's capacity is used up
     __syncthreads();
@@ -645,7 +668,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
 // kChunkRecords + 2^kItemShift k ... for the chunk's k-th item. Every other
 // work-group owns one chunk and its ranks 0 .. kChunkRecords - 1. One record
 // builder serves both.
-template <int D, int M>
+template <int D, int M, bool G>
 __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est_waves(D, M)))) void split_estimate_kernel(DevPtrs p, int T,
                                                                      int64_t nframes,
                                                                      int max_cchunks,
@@ -657,8 +680,9 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
   constexpr int kWpt = kWordsPerThread;
   __shared__ uint32_t list[kChunkRecords];
   __shared__ uint32_t wsum[kEstThreads / 64];
-  __shared__ rsft_detection stage[kEstThreads];
+  __shared__ DetRec stage[kEstThreads];
   __shared__ float pbuf[D >= 4 ? kNb * kEstThreads : 1];
+  __shared__ float sgain[kGainLds];
   const int tid = threadIdx.x;
   const bool worker = int64_t(blockIdx.x) < og;
   int64_t f = 0, i = 0, hi = 0, fbeg = 0, fend = 0;
@@ -732,7 +756,7 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
       r_lo = 0;
       n = int(min(min(int64_t(count), cap - rank0), int64_t(kChunkRecords)));
     }
-    build_range<D, M, kWpt>(p, T, *dp, f, c, wv, r_lo, n, rank0, list, wsum, stage, pbuf + tid);
+    build_range<D, M, G, kWpt>(p, T, *dp, f, c, wv, r_lo, n, rank0, list, wsum, stage, pbuf + tid, sgain);
     if (!worker) return;
   }
 }
@@ -740,16 +764,16 @@ __global__ __launch_bounds__(kEstThreads) __attribute__((amdgpu_waves_per_eu(est
 // Per dimension count, one kernel built for the most estimation rounds any
 // frame of the plan uses (uneven plans mix frames of 1..M rounds, sigma per
 // frame).
-template <int D>
+template <int D, bool G>
 static void launch_estimate_d(const DevPtrs& p, dim3 grid, int og, hipStream_t st, int T, int64_t nframes,
                               int max_cchunks, int xcd, int use_list, int est_mask) {
 #define RSFT_EST(M)                                                                                      \
   do {                                                                                                   \
     if (og > 0)                                                                                          \
-      hipLaunchKernelGGL((split_estimate_kernel<D, M>), grid, dim3(kEstThreads), 0, st, p, T, nframes,    \
+      hipLaunchKernelGGL((split_estimate_kernel<D, M, G>), grid, dim3(kEstThreads), 0, st, p, T, nframes,    \
                          max_cchunks, xcd, use_list, og);                                                \
     else                                                                                                 \
-      hipLaunchKernelGGL((compact_estimate_kernel<D, M>), grid, dim3(kEstThreads), 0, st, p, T, nframes,  \
+      hipLaunchKernelGGL((compact_estimate_kernel<D, M, G>), grid, dim3(kEstThreads), 0, st, p, T, nframes,  \
                          max_cchunks, xcd, use_list);                                                    \
   } while (0)
   const int small = est_mask & ((2 << kMaxEstRounds) - 1);
@@ -763,7 +787,7 @@ static void launch_estimate_d(const DevPtrs& p, dim3 grid, int og, hipStream_t s
 }
 
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
-                    int est_mask, int workers, int num_cus, int64_t nlist, void* stream) {
+                    int est_mask, int workers, int num_cus, int64_t nlist, int global_gains, void* stream) {
   if (nframes <= 0) return hipSuccess;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int xcd = nframes >= 16 ? 1 : 0;
@@ -775,10 +799,18 @@ int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, i
   const int64_t blocks = og + (use_list ? nlist : rows * int64_t(max_cchunks));
   if (blocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
   const dim3 grid{unsigned(blocks), 1u, 1u};
-  if (dims_mask & 1) launch_estimate_d<1>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);
-  if (dims_mask & 2) launch_estimate_d<2>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);
-  if (dims_mask & 4) launch_estimate_d<3>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);
-  if (dims_mask & 8) launch_estimate_d<4>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);
+#define RSFT_EST_D(D)                                                                                    \
+  do {                                                                                                   \
+    if (global_gains)                                                                                    \
+      launch_estimate_d<D, true>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);     \
+    else                                                                                                 \
+      launch_estimate_d<D, false>(p, grid, og, st, T, nframes, max_cchunks, xcd, use_list, est_mask);    \
+  } while (0)
+  if (dims_mask & 1) RSFT_EST_D(1);
+  if (dims_mask & 2) RSFT_EST_D(2);
+  if (dims_mask & 4) RSFT_EST_D(3);
+  if (dims_mask & 8) RSFT_EST_D(4);
+#undef RSFT_EST_D
   return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct rsft_plan_s {
   int maxB = 0, max_words = 0, max_cchunks = 0, sum_tw_max = 0, dims_mask = 0, est_nmask = 0;
   int rows_ok = 1, masks_ok = 1;   // every frame suits the row vote / the 32-cell mask vote
   int words_ok = 1;                // every frame suits the word-parallel vote
+  int global_gains = 0;            // some frame's sum of L_d exceeds the estimate's LDS copy
   int split_ok = 1;                // every frame suits the two-pass DFT
   int dft_split = 1;               // RSFT_OPT_DFT_SPLIT: use it (where it applies)
   int split_b0 = 0, split_g1 = 0, split_g2 = 0;   // its launch extents
@@ -526,6 +527,11 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     pl->max_cchunks = std::max(pl->max_cchunks, d.cchunks);
     pl->dims_mask |= 1 << (d.ndim - 1);
     pl->est_nmask |= 1 << std::min(d.n_est, rsft::kMaxEstRounds + 1);
+    {
+      int64_t lsum = 0;
+      for (int k = 0; k < d.ndim; ++k) lsum += d.l[k];
+      if (lsum > rsft::kEstGainLds) pl->global_gains = 1;
+    }
     if (d.n_last < 64 || d.n_last > 4096) pl->rows_ok = 0;
     if (d.n_last != 32) pl->masks_ok = 0;
     {
@@ -689,7 +695,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = alloc(pl->d_chunk_items, size_t(chunk_off) * sizeof(int64_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_item_counts, size_t(pl->max_frames) * sizeof(int64_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_item_offsets, size_t(pl->max_frames + 1) * sizeof(int64_t))) != RSFT_OK) return st;
-  if ((st = alloc(pl->d_records, size_t(rec_total) * sizeof(rsft_detection))) != RSFT_OK) return st;
+  if ((st = alloc(pl->d_records, size_t(rec_total) * sizeof(rsft::DetRec))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_scan_done, sizeof(uint32_t))) != RSFT_OK) return st;
   HIP_TRY(hipMemset(pl->d_scan_done.ptr, 0, sizeof(uint32_t)));   // the scan keeps it 0 between launches
   HIP_TRY(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
@@ -716,7 +722,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.chunk_items = static_cast<int64_t*>(pl->d_chunk_items.ptr);
   q.item_counts = static_cast<int64_t*>(pl->d_item_counts.ptr);
   q.item_offsets = static_cast<int64_t*>(pl->d_item_offsets.ptr);
-  q.records = static_cast<rsft_detection*>(pl->d_records.ptr);
+  q.records = static_cast<rsft::DetRec*>(pl->d_records.ptr);
   q.scan_done = static_cast<uint32_t*>(pl->d_scan_done.ptr);
   q.tiles = static_cast<const int32_t*>(pl->d_tiles.ptr);
   q.chunk_list = static_cast<const int32_t*>(pl->d_chunk_list.ptr);
@@ -770,7 +776,7 @@ rsft_status estimate_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   const auto& q = pl->ptrs;
   LAUNCH_TRY(rsft::launch_scan(q, batch, pl->est_workers, pl->scan_fpb, st));
   LAUNCH_TRY(rsft::launch_estimate(q, batch, pl->T, pl->max_cchunks, pl->dims_mask, pl->est_nmask,
-                                   pl->est_workers, pl->num_cus, pl->nchunk_list, st));
+                                   pl->est_workers, pl->num_cus, pl->nchunk_list, pl->global_gains, st));
   return RSFT_OK;
 }
 
@@ -1277,8 +1283,31 @@ rsft_status rsft_detect(rsft_plan_t pl, void* stream, rsft_detection* h_out, int
   }
   const int64_t stored = offsets[size_t(batch)];
   const int64_t ncopy = std::min(stored, capacity);
-  if (ncopy > 0)
-    HIP_TRY(hipMemcpy(h_out, pl->d_records.ptr, size_t(ncopy) * sizeof(rsft_detection), hipMemcpyDeviceToHost));
+  if (ncopy > 0) {
+    // the device keeps 32-byte records; form the ABI records here
+    std::vector<rsft::DetRec> recs(static_cast<size_t>(ncopy));
+    HIP_TRY(hipMemcpy(recs.data(), pl->d_records.ptr, size_t(ncopy) * sizeof(rsft::DetRec), hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < ncopy; ++r) {
+      const rsft::DetRec& src = recs[size_t(r)];
+      const auto& d = pl->descs[size_t(pl->uniform ? 0 : src.frame)];
+      const uint64_t cell = src.key & rsft::kKeyCellMask;
+      rsft_detection& o = h_out[r];
+      std::memset(&o, 0, sizeof(o));
+      o.frame = int64_t(src.frame);
+      o.votes = int32_t((src.key >> rsft::kKeyVotesShift) & 127u);
+      o.is_peak = int32_t((src.key >> (rsft::kKeyVotesShift + 7)) & 1u);
+      o.magnitude = src.magnitude;
+      for (int k = 0; k < d.ndim; ++k) {
+        const int64_t idx = int64_t(cell >> d.nshift[k]) & int64_t(d.n[k] - 1);
+        // N_d is a power of two: scaling by 2^-log2(N_d) is the division exactly
+        double fr = std::ldexp(double(idx) + double(src.delta[k]), -ilog2(d.n[k]));
+        if (fr < 0.0) fr += 1.0;
+        if (fr >= 1.0) fr -= 1.0;
+        o.idx[k] = idx;
+        o.freq[k] = fr;
+      }
+    }
+  }
   if (n_written) *n_written = std::max<int64_t>(ncopy, 0);
   if (ncopy < stored) truncated = true;
   if (truncated) return fail(RSFT_ERROR_CAPACITY, "detection records truncated; counts are exact");

@@ -77,6 +77,19 @@ struct FrameDesc {
   int64_t vtab_off;                    // uint32 [T][B_last][N_last / 32]: word-parallel vote tables
 };
 
+// A detection as the estimate stores it on the device: 32 bytes instead of
+// the 88 of rsft_detection, which rsft_detect forms on the host from it
+// (frequency (idx + delta) / N_d in FP64, wrapped to [0, 1)).
+struct DetRec {
+  uint64_t key;                // bits 0..39 row-major cell, 40..46 votes, 47 is_peak
+  uint32_t frame;
+  float magnitude;             // gain-corrected magnitude
+  float delta[kMaxDims];       // off-grid offset per dimension (bins, in [-1/2, 1/2])
+};
+static_assert(sizeof(DetRec) == 32, "DetRec is 32 bytes");
+constexpr int kKeyVotesShift = 40;
+constexpr uint64_t kKeyCellMask = (uint64_t(1) << 40) - 1;
+
 // Device-side view of a launch: pointers into the plan's arrays.
 struct DevPtrs {
   const FrameDesc* descs;
@@ -104,7 +117,7 @@ struct DevPtrs {
   int64_t* item_counts;        // [frames] items per frame
   int64_t* item_offsets;       // [frames + 1] first item of each frame
   uint32_t* scan_done;         // frames finished by the scan (0 between launches)
-  rsft_detection* records;
+  DetRec* records;
   const int32_t* tiles;        // uneven plans: [ntiles][3] (frame, class, chunk)
   // uneven plans whose frames differ in chunk count: [n][2] (frame, chunk) of
   // every compaction chunk, position p holding a frame congruent to p mod 8
@@ -158,11 +171,15 @@ int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunk
 // workers); fpb: frames per work-group (1, or 256 / chunks per frame in a
 // uniform plan of at most 128 chunks per frame)
 int launch_scan(const DevPtrs& p, int64_t nframes, int items, int fpb, void* stream);
+// inverse flat-window gains the estimate keeps in LDS: frames whose sum over
+// d of L_d is larger make the plan launch the variant reading them from
+// global memory (global_gains = 1)
+constexpr int kEstGainLds = 384;
 // est_mask: bit m set when some frame uses m estimation rounds (1..5); bit 6
 // when some frame uses more (the loop variant)
 // workers: 1 adds overflow workers (two per compute unit of the num_cus)
 int launch_estimate(const DevPtrs& p, int64_t nframes, int T, int max_cchunks, int dims_mask,
-                    int est_mask, int workers, int num_cus, int64_t nlist, void* stream);
+                    int est_mask, int workers, int num_cus, int64_t nlist, int global_gains, void* stream);
 // Per-frame comparator path.
 int launch_plain_fold(const DevPtrs& p, const void* input, int dtype, int64_t frame,
                       int round, int B, void* stream);
