@@ -355,20 +355,24 @@ def precision_report(gpu_buckets, gpu_flags, recs, outs, shape, buckets):
 
 def refine_section(dev, steps=20, oracle_frames=1):
     """Detect -> estimate -> refine on 16 frames of 2048x2048 (K = 32
-    off-grid tones, B = 128x128): the fused RSFT of the frames, the 32
-    strongest peaks of each frame as starting frequencies, their starting
-    amplitudes from the buckets (rsft_initial_amplitudes), then `steps`
-    refinement steps (rsft_refine) timed with events. Every true tone within
-    one bin of a starting peak is scored before and after; the FP64 oracle
-    refines the first `oracle_frames` frames from the same start and
-    observed buckets."""
+    off-grid tones, B = 128x128): the fused RSFT of the frames; starting
+    tones chosen among the detector's peak records (select_tones: per-round
+    agreement, then peeling on the residual of the tones found); their
+    detector frequencies and amplitudes from the buckets
+    (rsft_initial_amplitudes); then `steps` refinement iterations
+    (rsft_refine) timed with events. Every true tone within one bin of a
+    chosen start is scored before and after, by amplitude class. The
+    least-squares fit the refinement converges to is compared with the one
+    reached from the true parameters (the noise decides how far that fit is
+    from the truth), and each frame's final loss with the loss at the true
+    parameters. The FP64 oracle refines the first `oracle_frames` frames
+    from the same start and observed buckets."""
     import torch
     from paper_1610_01050_amd import Plan
     from paper_1610_01050_amd.refine import refine, select_tones
     cfg = synth.WORKLOADS["offgrid_2048x2048"]
     F, K = 16, cfg["K"]
     shape = cfg["shape"]
-    D = len(shape)
     log(f"refinement: generating {F} frames {shape} ...")
     frames, metas = synth.make_batch("offgrid_2048x2048", F)
     sigma = synth.shared_sigma("offgrid_2048x2048")
@@ -378,59 +382,96 @@ def refine_section(dev, steps=20, oracle_frames=1):
     plan.execute(x)
     recs, _ = plan.detect()
     obs = torch.cat([b.reshape(-1) for b in plan.buckets()]).contiguous()
-    f0, a0, passed = select_tones(plan, recs, K, observed=obs)
+    t0 = time.perf_counter()
+    f0, a0, counts = select_tones(plan, recs, K, observed=obs)
+    torch.cuda.synchronize()
+    select_s = time.perf_counter() - t0
     start = f0.cpu().numpy()
-    refine(plan, obs, f0, a0, steps=2, record_loss=False)          # warm-up
+    passed = counts.cpu().numpy()
+    refine(plan, obs, f0, a0, steps=2, record_loss=False, counts=counts)          # warm-up
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    fr, ar, _ = refine(plan, obs, f0, a0, steps=steps, record_loss=False)
+    fr, ar, _ = refine(plan, obs, f0, a0, steps=steps, record_loss=False, counts=counts)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    _, _, losses = refine(plan, obs, f0, a0, steps=steps, record_loss=True)
-    losses = losses.cpu().numpy().sum(axis=1)
+    _, _, losses = refine(plan, obs, f0, a0, steps=steps, record_loss=True, counts=counts)
+    losses = losses.cpu().numpy()
     end = fr.cpu().numpy()
     amp0 = a0.cpu().numpy()
     amp1 = ar.cpu().numpy()
+    # the fit reached from the true parameters, and the loss there
+    tf = torch.tensor(np.stack([m["freqs"] for m in metas]), dtype=torch.float64, device=dev).contiguous()
+    ta = torch.tensor(np.stack([m["amps"] for m in metas]).astype(np.complex64), device=dev).contiguous()
+    f_ml, _, _ = refine(plan, obs, tf, ta, steps=steps, record_loss=False)
+    f_ml = f_ml.cpu().numpy()
+    _, _, loss_truth = refine(plan, obs, tf, ta, steps=0, record_loss=True)
+    loss_truth = loss_truth.cpu().numpy()[0]
 
     def circ(a, b):
         return (((a - b + 0.5) % 1.0) - 0.5) * np.array(shape)
 
-    tones = []   # per true tone initialized by a peak: (frame, tone, |b|^2, err before, err after)
+    tones = []   # per true tone with a chosen start within one bin
+    ml_diff = []
+    complete = 0
     for f in range(F):
+        found = 0
         for t, ft in enumerate(metas[f]["freqs"]):
-            d = np.abs(circ(start[f], ft)).max(axis=1)
+            if passed[f] == 0:
+                continue
+            d = np.abs(circ(start[f, :passed[f]], ft)).max(axis=1)
             u = int(np.argmin(d))
             if d[u] >= 1.0:
                 continue
+            found += 1
             tones.append((f, t, float(abs(metas[f]["amps"][t]) ** 2), float(d[u]),
                           float(np.abs(circ(end[f, u], ft)).max()),
-                          float(abs(amp1[f, u] / metas[f]["amps"][t] - 1))))
-    ev = np.array([[v[3], v[4], v[5]] for v in tones]) if tones else np.zeros((0, 3))
-    worst = sorted(tones, key=lambda v: -v[4])[:5]
+                          float(abs(amp1[f, u] / metas[f]["amps"][t] - 1)),
+                          float(np.abs(circ(end[f, u], f_ml[f, t])).max())))
+        if found == K and passed[f] == K:
+            complete += 1
+            ml_diff += [v[6] for v in tones[-K:]]
+    ev = np.array([v[2:] for v in tones]) if tones else np.zeros((0, 5))
+
+    def cls(lo, hi):
+        q = (ev[:, 0] >= lo) & (ev[:, 0] < hi)
+        if not q.any():
+            return {"tones": 0}
+        b, a = ev[q, 1], ev[q, 2]
+        return {"tones": int(q.sum()),
+                "err_rms_bins": [float(np.sqrt(np.mean(b ** 2))), float(np.sqrt(np.mean(a ** 2)))],
+                "err_max_bins": [float(b.max()), float(a.max())],
+                "tones_worse_after": int(np.sum(a > b))}
+
     out = {"workload": f"{F} frames of 2048x2048 complex64, K={K} off-grid tones, B=128x128, T=3",
-           "start": f"per frame the {K} strongest detected peaks (off-grid estimates) among the "
-                    f"{4 * K} strongest whose per-round amplitudes agree (spread <= 0.5), "
-                    "amplitudes from rsft_initial_amplitudes",
+           "start": f"per frame up to {K} of the {64 * K} strongest detected peaks: those whose per-round "
+                    "amplitudes agree (spread <= 0.5), then two peeling rounds (5 refinement steps, "
+                    "the residual after the tones found, the other peaks' agreement on it); the "
+                    "chosen records' detector frequencies, amplitudes from rsft_initial_amplitudes",
+           "select_s": select_s,
+           "tones_refined": int(passed.sum()),
            "steps": steps, "ms_per_step": ms / steps, "ms_total": ms,
-           "true_tones": F * K, "tones_initialized": len(tones),
-           "consistent_peaks_per_frame_min": int(passed.min()),
-           "freq_err_rms_bins": [float(np.sqrt(np.mean(ev[:, 0] ** 2))), float(np.sqrt(np.mean(ev[:, 1] ** 2)))],
-           "freq_err_max_bins": [float(ev[:, 0].max()), float(ev[:, 1].max())],
-           "tones_worse_after": int(np.sum(ev[:, 1] > ev[:, 0])),
-           "amp_rel_err_median_after": float(np.median(ev[:, 2])),
-           "worst_tones_after": [{"frame": v[0], "tone": v[1], "amp_sq": v[2], "err_before_bins": v[3],
-                                  "err_after_bins": v[4]} for v in worst],
-           "loss_first_last": [float(losses[0]), float(losses[-1])]}
-    log(f"refinement: {out['ms_per_step']:.3f} ms/step, {len(tones)} tones, freq rms "
-        f"{out['freq_err_rms_bins'][0]:.4f} -> {out['freq_err_rms_bins'][1]:.4f} bin, max "
-        f"{out['freq_err_max_bins'][0]:.4f} -> {out['freq_err_max_bins'][1]:.4f}")
+           "true_tones": F * K, "true_tones_started": len(tones),
+           "frames_with_all_tones_started": complete,
+           "by_amplitude": {"|b|^2<0.1": cls(0.0, 0.1), "0.1<=|b|^2<1": cls(0.1, 1.0),
+                            "|b|^2>=1": cls(1.0, np.inf)},
+           "err_rms_bins": [float(np.sqrt(np.mean(ev[:, 1] ** 2))), float(np.sqrt(np.mean(ev[:, 2] ** 2)))],
+           "err_max_bins": [float(ev[:, 1].max()), float(ev[:, 2].max())],
+           "amp_rel_err_median_after": float(np.median(ev[:, 3])),
+           "vs_fit_from_truth_max_bins": float(max(ml_diff)) if ml_diff else None,
+           "loss_sum": {"start": float(losses[0].sum()), "end": float(losses[-1].sum()),
+                        "at_true_parameters": float(loss_truth.sum())},
+           "frames_end_loss_at_or_below_truth": int(np.sum(losses[-1] <= loss_truth))}
+    log(f"refinement: {out['ms_per_step']:.3f} ms/step, {len(tones)} tones started, "
+        f"{complete} complete frames; rms {out['err_rms_bins'][0]:.4f} -> {out['err_rms_bins'][1]:.4f} bin; "
+        f"strong {out['by_amplitude']['|b|^2>=1']}; vs fit from truth {out['vs_fit_from_truth_max_bins']}")
     per = cfg["rounds"] * int(np.prod(cfg["buckets"]))
     obs_np = obs.cpu().numpy()
     handoff = {"sigma": sigma, "steps": steps,
                "frames": [{"start_f": start[f], "start_a": amp0[f], "end_f": end[f], "end_a": amp1[f],
+                           "active": int(passed[f]),
                            "observed": obs_np[f * per:(f + 1) * per].reshape(
                                (cfg["rounds"],) + tuple(cfg["buckets"]))}
                           for f in range(oracle_frames)]}
@@ -450,10 +491,11 @@ def refine_vs_oracle(handoff):
     df, da = [], []
     t0 = time.perf_counter()
     for fr in handoff["frames"]:
+        k = fr["active"]
         wf, wa, _, _ = oracle_refine.refine(fr["start_f"], fr["start_a"].astype(np.complex128), oplan,
-                                            fr["observed"].astype(np.complex128), handoff["steps"])
-        df.append(np.abs((((fr["end_f"] - wf + 0.5) % 1.0) - 0.5) * np.array(shape)).max())
-        da.append(np.max(np.abs(fr["end_a"] / wa - 1)))
+                                            fr["observed"].astype(np.complex128), handoff["steps"], active=k)
+        df.append(np.abs((((fr["end_f"][:k] - wf[:k] + 0.5) % 1.0) - 0.5) * np.array(shape)).max())
+        da.append(np.max(np.abs(fr["end_a"][:k] / wa[:k] - 1)))
     return {"frames": len(handoff["frames"]), "refined_freq_max_diff_bins": float(max(df)),
             "refined_amp_max_rel_diff": float(max(da)), "oracle_seconds": time.perf_counter() - t0}
 

@@ -397,17 +397,26 @@ rsft_status rsft_model_backward(rsft_plan_t plan, const void* d_amps, int64_t ba
  * order one for a peak made of different tones' energy in different rounds
  * (the ambiguity of Remark 1), which a caller can drop before refining.
  *
- * rsft_refine: `steps` steps in place on d_freqs / d_amps, all on the
- * device. Each step, every tone against the same residual r = model -
- * observed (tones decoupled): the tone's Gauss-Newton step over (Re b,
+ * rsft_refine: `steps` iterations in place on d_freqs / d_amps, all on the
+ * device. d_tone_counts (device int32 [batch], or NULL for K everywhere):
+ * only the first counts[f] tones of frame f take part; the others are left
+ * unchanged and are not part of the model (a way to give frames different
+ * tone counts). An iteration first evaluates each frame's loss: when it is
+ * above the lowest loss of that frame so far (decoupled steps of tones that
+ * share buckets can overshoot together), the frame's lowest-loss state is
+ * restored, its trust radii halve and it takes no step this iteration.
+ * Otherwise every active tone, against the same residual r = model -
+ * observed (tones decoupled), takes its Gauss-Newton step over (Re b,
  * Im b, f) (as rsft_model_backward), its frequency step clipped to the
- * tone's trust radius (starting at trust_bins bins per dimension); then the
- * amplitude re-solved for the new frequency f' by least squares against the
- * residual without the tone; the step is kept when it lowers the tone's own
- * loss (others fixed), and the radius doubles (at most trust_bins); else
- * the frequency stays, the amplitude becomes the least-squares one at f and
- * the radius halves. d_loss (may be NULL): double [steps + 1][batch], the
- * loss of each frame before each step and after the last, in FP64.
+ * tone's trust radius (starting at trust_bins bins per dimension); the
+ * amplitude is re-solved for the new frequency f' by least squares against
+ * the residual without the tone; the step is kept when it lowers the tone's
+ * own loss (others fixed), and the radius doubles (at most trust_bins);
+ * else the frequency stays, the amplitude becomes the least-squares one at
+ * f and the radius halves. The same loss check ends the last iteration, so
+ * the result is each frame's lowest-loss state. d_loss (may be NULL):
+ * double [steps + 1][batch], each frame's lowest loss so far at the start of
+ * every iteration and at the end (non-increasing), in FP64.
  * Frequencies are FP64 throughout; sums are FP32 with FP64 reductions.
  * Errors: as rsft_model_forward; INVALID_ARGUMENT (steps outside 0..100000,
  * trust_bins <= 0); NOT_READY. Async on `stream`.
@@ -417,8 +426,27 @@ rsft_status rsft_initial_amplitudes(rsft_plan_t plan, const void* d_observed, co
                                     int64_t batch, int32_t tones, void* d_amps, float* d_spread,
                                     void* d_workspace, void* stream);
 rsft_status rsft_refine(rsft_plan_t plan, const void* d_observed, double* d_freqs, void* d_amps,
-                        int64_t batch, int32_t tones, int32_t steps, double trust_bins,
-                        void* d_workspace, double* d_loss, void* stream);
+                        int64_t batch, int32_t tones, const int32_t* d_tone_counts, int32_t steps,
+                        double trust_bins, void* d_workspace, double* d_loss, void* stream);
+
+/*
+ * Residual of observed buckets after the model of K tones per frame:
+ *   d_residual_s[k] = observed_s[k] - sum_{t < counts[f]} b_t prod_d G_{s,d}(f_t)[k_d]
+ * (the model of rsft_model_forward; eq. f is linear in the signal, so the
+ * residual is the round buckets of what the tones do not explain). For
+ * finding tones that share a bucket with a stronger one in some round: the
+ * amplitudes and spreads of rsft_initial_amplitudes taken on the residual
+ * of the tones already found (pass d_residual as its d_observed).
+ * d_observed: as rsft_refine (NULL: the plan's buckets of the last
+ * execute); d_tone_counts: as rsft_refine (NULL: all K); d_residual:
+ * device complex64 in the layout of rsft_get_buckets (may not alias
+ * d_observed); d_workspace: rsft_model_workspace_size bytes. Errors: as
+ * rsft_model_forward; NOT_READY. Async on `stream`.
+ */
+rsft_status rsft_model_residual(rsft_plan_t plan, const void* d_observed, const double* d_freqs,
+                                const void* d_amps, int64_t batch, int32_t tones,
+                                const int32_t* d_tone_counts, void* d_residual, void* d_workspace,
+                                void* stream);
 
 /* Per-frame derived parameters; frame indexes the descriptors of rsft_plan. */
 rsft_status rsft_plan_info(rsft_plan_t plan, int64_t frame, rsft_plan_info_t* out);

@@ -205,7 +205,7 @@ def initial_amplitudes(freqs, plan, observed, with_spread=False):
     return (out, spread) if with_spread else out
 
 
-def refine_step(freqs, amps, radius, plan, observed, max_radius=0.25):
+def refine_step(freqs, amps, radius, plan, observed, max_radius=0.25, active=None):
     """One step of per-tone trust-region Gauss-Newton on
     loss = sum_{s,k} |model_s[k] - observed_s[k]|^2, every tone against the
     same residual r = model - observed (tones decoupled):
@@ -224,12 +224,13 @@ def refine_step(freqs, amps, radius, plan, observed, max_radius=0.25):
        else keep f, take the least-squares amplitude at f,
        b - <P, r> / <P, P>, and halve the radius.
 
-    freqs [K][D], amps [K] complex, radius [K] in bins. Returns new
-    (freqs, amps, radius)."""
-    K = len(freqs)
+    freqs [K][D], amps [K] complex, radius [K] in bins; active: the number
+    of tones taking part (the first `active`; the rest are left as they are
+    and do not enter the model). Returns new (freqs, amps, radius)."""
+    K = len(freqs) if active is None else int(active)
     D = plan.D
     P = [factored_round_buckets(freqs[t], plan) for t in range(K)]
-    r = sum(complex(amps[t]) * P[t] for t in range(K)) - observed
+    r = sum((complex(amps[t]) * P[t] for t in range(K)), np.zeros_like(observed)) - observed
     nf = np.array(freqs, dtype=np.float64, copy=True)
     na = np.array(amps, dtype=np.complex128, copy=True)
     nr = np.array(radius, dtype=np.float64, copy=True)
@@ -261,20 +262,53 @@ def refine_step(freqs, amps, radius, plan, observed, max_radius=0.25):
     return nf, na, nr
 
 
-def refine(freqs, amps, plan, observed, steps, radius0=0.25):
-    """``steps`` refine_step iterations from (freqs, amps) with every trust
-    radius starting at radius0 bins. Returns (freqs, amps, radius, losses),
-    losses holding the loss before each step and after the last."""
+def model_loss(freqs, amps, plan, observed, active=None):
+    """The loss of the first `active` tones (all when None)."""
+    K = len(freqs) if active is None else int(active)
+    m = sum((complex(amps[t]) * factored_round_buckets(freqs[t], plan) for t in range(K)),
+            np.zeros_like(observed))
+    return float(np.sum(np.abs(m - observed) ** 2))
+
+
+def model_residual(freqs, amps, plan, observed, active=None):
+    """observed - the model of the first `active` tones (all when None), the
+    factored model of each tone scaled by its amplitude: the round buckets
+    of what those tones leave unexplained (the rounds are linear in the
+    signal)."""
+    K = len(freqs) if active is None else int(active)
+    m = sum((complex(amps[t]) * factored_round_buckets(freqs[t], plan) for t in range(K)),
+            np.zeros_like(observed))
+    return np.asarray(observed, dtype=np.complex128) - m
+
+
+def refine(freqs, amps, plan, observed, steps, radius0=0.25, active=None):
+    """``steps`` iterations from (freqs, amps), every trust radius starting at
+    radius0 bins. Each iteration first evaluates the loss of the current
+    state: when it is above the lowest loss reached so far (the tones'
+    decoupled steps can overshoot together where they share buckets), the
+    state of that lowest loss is restored, every radius halves and the
+    iteration takes no step; otherwise the state is kept as the best and
+    refine_step runs. After the last iteration the same check applies once
+    more. Returns (freqs, amps, radius, losses), losses holding the lowest
+    loss so far before each iteration and after the last (non-increasing)."""
+    K = len(freqs) if active is None else int(active)
     f = np.array(freqs, dtype=np.float64, copy=True)
     a = np.array(amps, dtype=np.complex128, copy=True)
     rad = np.full(len(f), float(radius0))
-
-    def loss_of(f, a):
-        m = sum(complex(a[t]) * factored_round_buckets(f[t], plan) for t in range(len(f)))
-        return float(np.sum(np.abs(m - observed) ** 2))
-
-    losses = [loss_of(f, a)]
-    for _ in range(steps):
-        f, a, rad = refine_step(f, a, rad, plan, observed, max_radius=radius0)
-        losses.append(loss_of(f, a))
+    best = math.inf
+    saved = (f.copy(), a.copy())
+    losses = []
+    for it in range(steps + 1):
+        loss = model_loss(f, a, plan, observed, K)
+        if loss > best:
+            f, a = saved[0].copy(), saved[1].copy()
+            rad[:K] *= 0.5
+            losses.append(best)
+            continue
+        best = loss
+        saved = (f.copy(), a.copy())
+        losses.append(best)
+        if it == steps:
+            break
+        f, a, rad = refine_step(f, a, rad, plan, observed, max_radius=radius0, active=K)
     return f, a, rad, losses

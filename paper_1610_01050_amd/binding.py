@@ -46,6 +46,7 @@ SYMBOLS = (
     "rsft_stage1_probability", "rsft_draw_sigma",
     "rsft_model_workspace_size", "rsft_model_forward", "rsft_model_forward_noalloc",
     "rsft_model_backward", "rsft_refine_workspace_size", "rsft_initial_amplitudes", "rsft_refine",
+    "rsft_model_residual",
     "rsft_design_thresholds",
 )
 
@@ -178,8 +179,9 @@ def load_library(path=None):
     lib.rsft_model_backward.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     lib.rsft_refine_workspace_size.argtypes = [vp, i64, ctypes.c_int32, ctypes.POINTER(i64)]
     lib.rsft_initial_amplitudes.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp]
-    lib.rsft_refine.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+    lib.rsft_refine.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_double,
                                 vp, vp, vp]
+    lib.rsft_model_residual.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp]
     lib.rsft_design_thresholds.argtypes = [ctypes.POINTER(DesignParams),
                                            ctypes.POINTER(DesignResult)]
     lib.rsft_draw_sigma.argtypes = [ctypes.c_uint64, ctypes.c_int32,
@@ -522,6 +524,40 @@ class Plan:
             _stream_handle(stream)))
         return out
 
+    @staticmethod
+    def _observed_ptr(observed):
+        import torch
+        if observed is None:
+            return 0
+        if not (isinstance(observed, torch.Tensor) and observed.is_cuda
+                and observed.dtype == torch.complex64 and observed.is_contiguous()):
+            raise TypeError("observed must be a contiguous CUDA complex64 tensor")
+        return observed.data_ptr()
+
+    @staticmethod
+    def _counts_ptr(counts, batch):
+        import torch
+        if counts is None:
+            return 0
+        if not (isinstance(counts, torch.Tensor) and counts.is_cuda and counts.dtype == torch.int32
+                and counts.is_contiguous() and counts.numel() == batch):
+            raise TypeError("counts must be a contiguous CUDA int32 tensor of batch elements")
+        return counts.data_ptr()
+
+    def model_residual(self, freqs, amps, workspace, observed=None, counts=None, out=None, stream=None):
+        """observed - model of the first counts[f] tones of every frame
+        (rsft_model_residual): a complex64 tensor in the layout of buckets()
+        (flat). observed: default this plan's buckets of the last execute."""
+        import torch
+        batch, K = self._model_args(freqs, amps)
+        if out is None:
+            out = torch.empty(self.model_size(batch), dtype=torch.complex64, device="cuda")
+        _check(self._lib, self._lib.rsft_model_residual(
+            self._h, ctypes.c_void_p(self._observed_ptr(observed)), ctypes.c_void_p(freqs.data_ptr()),
+            ctypes.c_void_p(amps.data_ptr()), batch, K, ctypes.c_void_p(self._counts_ptr(counts, batch)),
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr()), _stream_handle(stream)))
+        return out
+
     def model_forward_noalloc(self, freqs, amps, out, stream=None):
         """model_forward into the caller's `out` with the factors in the
         library's static scratch array (no allocation anywhere; the factors
@@ -573,7 +609,7 @@ class Plan:
         batch, K = int(freqs.shape[0]), int(freqs.shape[1])
         amps = torch.empty((batch, K), dtype=torch.complex64, device="cuda")
         spread = torch.empty((batch, K), dtype=torch.float32, device="cuda") if with_spread else None
-        obs = 0 if observed is None else observed.contiguous().data_ptr()
+        obs = self._observed_ptr(observed)
         _check(self._lib, self._lib.rsft_initial_amplitudes(
             self._h, ctypes.c_void_p(obs), ctypes.c_void_p(freqs.data_ptr()), batch, K,
             ctypes.c_void_p(amps.data_ptr()), ctypes.c_void_p(spread.data_ptr() if with_spread else 0),
@@ -581,16 +617,18 @@ class Plan:
         return (amps, spread) if with_spread else amps
 
     def refine(self, freqs, amps, steps, workspace, observed=None, trust_bins=0.25, loss=None,
-               stream=None):
+               counts=None, stream=None):
         """rsft_refine in place on freqs (float64 [batch, K, D]) and amps
         (complex64 [batch, K]); loss: None or a float64 CUDA tensor of
-        (steps + 1) * batch elements."""
+        (steps + 1) * batch elements; counts: None or an int32 CUDA tensor
+        [batch] of the tones taking part in each frame."""
         batch, K = self._model_args(freqs, amps)
-        obs = 0 if observed is None else observed.contiguous().data_ptr()
+        obs = self._observed_ptr(observed)
         lp = 0 if loss is None else loss.data_ptr()
+        cp = self._counts_ptr(counts, batch)
         _check(self._lib, self._lib.rsft_refine(
             self._h, ctypes.c_void_p(obs), ctypes.c_void_p(freqs.data_ptr()),
-            ctypes.c_void_p(amps.data_ptr()), batch, K, int(steps), float(trust_bins),
+            ctypes.c_void_p(amps.data_ptr()), batch, K, ctypes.c_void_p(cp), int(steps), float(trust_bins),
             ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(lp), _stream_handle(stream)))
         return freqs, amps
 

@@ -1165,7 +1165,7 @@ int64_t model_values(const rsft_plan_s* pl, int64_t batch) {
 
 // Byte layout of a refinement workspace (each part 256-byte aligned).
 struct RefineLayout {
-  int64_t G, dG, G2, dG2, model, radius, fcand, total;
+  int64_t G, dG, G2, dG2, model, radius, fcand, saved_f, saved_a, best, loss_now, skip, total;
 };
 RefineLayout refine_layout(const rsft_plan_s* pl, int64_t batch, int32_t tones) {
   auto up = [](int64_t v) { return (v + 255) / 256 * 256; };
@@ -1178,7 +1178,12 @@ RefineLayout refine_layout(const rsft_plan_s* pl, int64_t batch, int32_t tones) 
   L.model = L.dG2 + fac;
   L.radius = L.model + up(model_values(pl, batch) * 8);
   L.fcand = L.radius + up(batch * tones * 8);
-  L.total = L.fcand + up(batch * tones * pl->descs[0].ndim * 8);
+  L.saved_f = L.fcand + up(batch * tones * pl->descs[0].ndim * 8);
+  L.saved_a = L.saved_f + up(batch * tones * pl->descs[0].ndim * 8);
+  L.best = L.saved_a + up(batch * tones * 8);
+  L.loss_now = L.best + up(batch * 8);
+  L.skip = L.loss_now + up(batch * 8);
+  L.total = L.skip + up(batch * 4);
   return L;
 }
 }  // namespace
@@ -1207,9 +1212,29 @@ rsft_status rsft_initial_amplitudes(rsft_plan_t pl, const void* d_observed, cons
   return RSFT_OK;
 }
 
+rsft_status rsft_model_residual(rsft_plan_t pl, const void* d_observed, const double* d_freqs,
+                                const void* d_amps, int64_t batch, int32_t tones,
+                                const int32_t* d_tone_counts, void* d_residual, void* d_workspace,
+                                void* stream) {
+  rsft_status st = check_model(pl, batch, tones);
+  if (st != RSFT_OK) return st;
+  if (!d_freqs || !d_amps || !d_residual || !d_workspace)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL pointer");
+  const float2* obs = nullptr;
+  if ((st = observed_buckets(pl, d_observed, batch, &obs)) != RSFT_OK) return st;
+  if (static_cast<const void*>(obs) == d_residual)
+    return fail(RSFT_ERROR_INVALID_ARGUMENT, "d_residual may not alias the observed buckets");
+  float2* G = static_cast<float2*>(d_workspace);
+  float2* dG = G + model_factor_count(pl, batch, tones);
+  LAUNCH_TRY(rsft::launch_model_residual(pl->ptrs, obs, d_freqs, static_cast<const float2*>(d_amps), batch,
+                                         tones, pl->descs[0].ndim, pl->T, pl->maxB, pl->sum_tw_max,
+                                         d_tone_counts, G, dG, static_cast<float2*>(d_residual), stream));
+  return RSFT_OK;
+}
+
 rsft_status rsft_refine(rsft_plan_t pl, const void* d_observed, double* d_freqs, void* d_amps, int64_t batch,
-                        int32_t tones, int32_t steps, double trust_bins, void* d_workspace, double* d_loss,
-                        void* stream) {
+                        int32_t tones, const int32_t* d_tone_counts, int32_t steps, double trust_bins,
+                        void* d_workspace, double* d_loss, void* stream) {
   rsft_status st = check_model(pl, batch, tones);
   if (st != RSFT_OK) return st;
   if (!d_freqs || !d_amps || !d_workspace) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL pointer");
@@ -1228,9 +1253,14 @@ rsft_status rsft_refine(rsft_plan_t pl, const void* d_observed, double* d_freqs,
   w.model = reinterpret_cast<float2*>(base + L.model);
   w.radius = reinterpret_cast<double*>(base + L.radius);
   w.fcand = reinterpret_cast<double*>(base + L.fcand);
+  w.saved_f = reinterpret_cast<double*>(base + L.saved_f);
+  w.saved_a = reinterpret_cast<float2*>(base + L.saved_a);
+  w.best = reinterpret_cast<double*>(base + L.best);
+  w.loss_now = reinterpret_cast<double*>(base + L.loss_now);
+  w.skip = reinterpret_cast<int32_t*>(base + L.skip);
   LAUNCH_TRY(rsft::launch_refine(pl->ptrs, obs, d_freqs, static_cast<float2*>(d_amps), batch, tones,
-                                 pl->descs[0].ndim, pl->T, pl->maxB, pl->sum_tw_max, steps, trust_bins, w,
-                                 d_loss, stream));
+                                 pl->descs[0].ndim, pl->T, pl->maxB, pl->sum_tw_max, steps, trust_bins,
+                                 d_tone_counts, w, d_loss, stream));
   return RSFT_OK;
 }
 

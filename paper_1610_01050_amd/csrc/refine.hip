@@ -176,9 +176,13 @@ __device__ __forceinline__ int64_t frame_bucket_base(const DevPtrs& p, int64_t f
   return de.bucket_off + model_rel(p, f) * de.bucket_stride;
 }
 
+// counts (may be NULL): tones of each frame that enter the model (the first
+// counts[f]; all K when NULL); observed (may be NULL): write observed - model
+// instead of the model
 __global__ __launch_bounds__(kCombineThreads) void model_combine_kernel(
     DevPtrs p, const float2* __restrict__ amps, int K, int T, int sum_b,
-    const float2* __restrict__ G, float2* __restrict__ model) {
+    const float2* __restrict__ G, float2* __restrict__ model, const int32_t* __restrict__ counts,
+    const float2* __restrict__ observed) {
   const int s = blockIdx.y;
   const int64_t f = blockIdx.z;
   const FrameDesc& de = model_desc(p, f);
@@ -194,13 +198,19 @@ __global__ __launch_bounds__(kCombineThreads) void model_combine_kernel(
   (void)kd;
   float2 acc = make_float2(0.f, 0.f);
   const float2* g = G + (f * T + s) * int64_t(K) * sum_b;
-  for (int t = 0; t < K; ++t) {
+  const int kt = counts ? (counts[f] < K ? counts[f] : K) : K;
+  for (int t = 0; t < kt; ++t) {
     float2 v = amps[f * K + t];
     for (int d = 0; d < de.ndim; ++d) v = cmul(v, g[int64_t(t) * sum_b + off[d]]);
     acc.x += v.x;
     acc.y += v.y;
   }
-  model[frame_bucket_base(p, f) + int64_t(s) * de.B + k] = acc;
+  const int64_t at = frame_bucket_base(p, f) + int64_t(s) * de.B + k;
+  if (observed) {
+    const float2 y = observed[at];
+    acc = make_float2(y.x - acc.x, y.y - acc.y);
+  }
+  model[at] = acc;
 }
 
 // sum of v over the work-group (wave shuffles, then one LDS slot per wave);
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(kBackThreads) void model_backward_kernel(
     float2* __restrict__ grad_amps, double* __restrict__ step_freqs,
     float2* __restrict__ step_amps, const float2* __restrict__ observed,
     const double* __restrict__ radius, const double* __restrict__ freqs,
-    double* __restrict__ fcand) {
+    double* __restrict__ fcand, const int32_t* __restrict__ counts, const int32_t* __restrict__ skip) {
   __shared__ float2 sg[4 * 128], sdg[4 * 128];
   __shared__ float slots[kBackThreads / 64];
   constexpr int kPairs = kMaxDims * (kMaxDims + 1) / 2;
@@ -276,6 +286,12 @@ __global__ __launch_bounds__(kBackThreads) void model_backward_kernel(
   const FrameDesc& de = model_desc(p, f);
   const int D = de.ndim;
   const int tid = threadIdx.x;
+  // refinement: a frame the guard restored takes no step, nor do tones past
+  // the frame's count; their candidate is the current frequency
+  if (fcand && ((skip && skip[f]) || (counts && t >= counts[f]))) {
+    if (tid < D) fcand[(f * K + t) * D + tid] = freqs[(f * K + t) * D + tid];
+    return;
+  }
   const bool want_step = step_freqs != nullptr || fcand != nullptr;   // the Gauss-Newton block
   const float2* gr = grad_model + frame_bucket_base(p, f);
   const float2* ob = observed ? observed + frame_bucket_base(p, f) : nullptr;
@@ -461,11 +477,13 @@ __global__ __launch_bounds__(kBackThreads) void refine_accept_kernel(
     DevPtrs p, int K, int T, int sum_b, const float2* __restrict__ G, const float2* __restrict__ G2,
     const float2* __restrict__ model, const float2* __restrict__ observed,
     const double* __restrict__ fcand, double* __restrict__ freqs, float2* __restrict__ amps,
-    double* __restrict__ radius, double max_radius) {
+    double* __restrict__ radius, double max_radius, const int32_t* __restrict__ counts,
+    const int32_t* __restrict__ skip) {
   __shared__ float2 sg[4 * 128], sq[4 * 128];
   __shared__ float slots[kBackThreads / 64];
   const int64_t f = blockIdx.x / K;
   const int t = int(blockIdx.x % K);
+  if (skip[f] || (counts && t >= counts[f])) return;
   const FrameDesc& de = model_desc(p, f);
   const int D = de.ndim;
   const int tid = threadIdx.x;
@@ -571,11 +589,54 @@ __global__ __launch_bounds__(kBackThreads) void refine_loss_kernel(DevPtrs p, in
   }
 }
 
-// trust radii of every tone set to r0 (a kernel rather than a memset, so
-// that the sequence can be captured)
+// trust radii of every tone set to r0, and per frame no best loss yet and
+// no skipped step (kernels rather than memsets, so that the sequence can be
+// captured)
 __global__ void refine_fill_kernel(double* __restrict__ radius, int64_t n, double r0) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) radius[i] = r0;
+}
+__global__ void refine_frame_init_kernel(double* __restrict__ best, int32_t* __restrict__ skip, int64_t batch) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < batch) {
+    best[i] = __builtin_huge_val();
+    skip[i] = 0;
+  }
+}
+
+// The per-frame guard of an iteration (one work-group per frame): the loss
+// of the current state above the lowest so far (tones' decoupled steps can
+// overshoot together where they share buckets) restores the state of that
+// lowest loss, halves the trust radii and marks the frame to take no step;
+// otherwise the current state becomes the best. loss_out (may be NULL)
+// receives the lowest loss so far.
+__global__ __launch_bounds__(kBackThreads) void refine_guard_kernel(
+    int K, int D, const int32_t* __restrict__ counts, const double* __restrict__ loss_now,
+    double* __restrict__ best, int32_t* __restrict__ skip, double* __restrict__ freqs,
+    float2* __restrict__ amps, double* __restrict__ radius, double* __restrict__ saved_f,
+    float2* __restrict__ saved_a, double* __restrict__ loss_out) {
+  const int64_t f = blockIdx.x;
+  const int kt = counts ? (counts[f] < K ? counts[f] : K) : K;
+  const double now = loss_now[f];
+  const double b = best[f];
+  const bool restore = now > b;
+  for (int t = threadIdx.x; t < kt; t += kBackThreads) {
+    const int64_t it = f * K + t;
+    if (restore) {
+      for (int d = 0; d < D; ++d) freqs[it * D + d] = saved_f[it * D + d];
+      amps[it] = saved_a[it];
+      radius[it] *= 0.5;
+    } else {
+      for (int d = 0; d < D; ++d) saved_f[it * D + d] = freqs[it * D + d];
+      saved_a[it] = amps[it];
+    }
+  }
+  if (threadIdx.x == 0) {
+    const double nb = restore ? b : now;
+    best[f] = nb;
+    skip[f] = restore ? 1 : 0;
+    if (loss_out) loss_out[f] = nb;
+  }
 }
 
 // Initial amplitude of every tone (one thread per (frame, tone)): the grid
@@ -660,7 +721,22 @@ int launch_model_forward(const DevPtrs& p, const double* freqs, const float2* am
                      K, D, T, sum_b, G, dG);
   const dim3 grid{unsigned((maxB + kCombineThreads - 1) / kCombineThreads), unsigned(T), unsigned(batch)};
   hipLaunchKernelGGL(model_combine_kernel, grid, dim3(kCombineThreads), 0, st, p, amps, K, T, sum_b, G,
-                     model);
+                     model, static_cast<const int32_t*>(nullptr), static_cast<const float2*>(nullptr));
+  return hipGetLastError();
+}
+
+int launch_model_residual(const DevPtrs& p, const float2* observed, const double* freqs, const float2* amps,
+                          int64_t batch, int K, int D, int T, int maxB, int sum_b, const int32_t* counts,
+                          float2* G, float2* dG, float2* residual, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t items = batch * T * D * int64_t(K);
+  if (items <= 0) return hipSuccess;
+  if (items >= (int64_t(1) << 31) || batch > 65535 || T > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(model_basis_kernel, dim3(unsigned(items)), dim3(kBasisThreads), 0, st, p, freqs,
+                     K, D, T, sum_b, G, dG);
+  const dim3 grid{unsigned((maxB + kCombineThreads - 1) / kCombineThreads), unsigned(T), unsigned(batch)};
+  hipLaunchKernelGGL(model_combine_kernel, grid, dim3(kCombineThreads), 0, st, p, amps, K, T, sum_b, G,
+                     residual, counts, observed);
   return hipGetLastError();
 }
 
@@ -675,7 +751,8 @@ int launch_model_backward(const DevPtrs& p, const float2* amps, int64_t batch, i
   hipLaunchKernelGGL(model_backward_kernel, dim3(unsigned(blocks)), dim3(kBackThreads), 0, st, p, amps,
                      K, T, sum_b, G, dG, grad_model, grad_freqs, grad_amps, step_freqs, step_amps,
                      static_cast<const float2*>(nullptr), static_cast<const double*>(nullptr),
-                     static_cast<const double*>(nullptr), static_cast<double*>(nullptr));
+                     static_cast<const double*>(nullptr), static_cast<double*>(nullptr),
+                     static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr));
   return hipGetLastError();
 }
 
@@ -696,7 +773,7 @@ int launch_initial_amplitudes(const DevPtrs& p, const double* freqs, int64_t bat
 }
 
 int launch_refine(const DevPtrs& p, const float2* observed, double* freqs, float2* amps, int64_t batch,
-                  int K, int D, int T, int maxB, int sum_b, int steps, double trust_bins,
+                  int K, int D, int T, int maxB, int sum_b, int steps, double trust_bins, const int32_t* counts,
                   const RefineWork& w, double* loss, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t items = batch * T * D * int64_t(K);
@@ -706,27 +783,32 @@ int launch_refine(const DevPtrs& p, const float2* observed, double* freqs, float
   const dim3 cgrid{unsigned((maxB + kCombineThreads - 1) / kCombineThreads), unsigned(T), unsigned(batch)};
   hipLaunchKernelGGL(refine_fill_kernel, dim3(unsigned((tones + 255) / 256)), dim3(256), 0, st, w.radius,
                      tones, trust_bins);
+  hipLaunchKernelGGL(refine_frame_init_kernel, dim3(unsigned((batch + 255) / 256)), dim3(256), 0, st, w.best,
+                     w.skip, batch);
   for (int step = 0; step <= steps; ++step) {
     hipLaunchKernelGGL(model_basis_kernel, dim3(unsigned(items)), dim3(kBasisThreads), 0, st, p, freqs, K, D,
                        T, sum_b, w.G, w.dG);
     hipLaunchKernelGGL(model_combine_kernel, cgrid, dim3(kCombineThreads), 0, st, p, amps, K, T, sum_b, w.G,
-                       w.model);
-    if (loss)
-      hipLaunchKernelGGL(refine_loss_kernel, dim3(unsigned(batch)), dim3(kBackThreads), 0, st, p, T,
-                         static_cast<const float2*>(w.model), observed, loss + int64_t(step) * batch);
+                       w.model, counts, static_cast<const float2*>(nullptr));
+    hipLaunchKernelGGL(refine_loss_kernel, dim3(unsigned(batch)), dim3(kBackThreads), 0, st, p, T,
+                       static_cast<const float2*>(w.model), observed, w.loss_now);
+    hipLaunchKernelGGL(refine_guard_kernel, dim3(unsigned(batch)), dim3(kBackThreads), 0, st, K, D, counts,
+                       static_cast<const double*>(w.loss_now), w.best, w.skip, freqs, amps, w.radius,
+                       w.saved_f, w.saved_a, loss ? loss + int64_t(step) * batch : static_cast<double*>(nullptr));
     if (step == steps) break;
     hipLaunchKernelGGL(model_backward_kernel, dim3(unsigned(tones)), dim3(kBackThreads), 0, st, p,
                        static_cast<const float2*>(amps), K, T, sum_b, static_cast<const float2*>(w.G),
                        static_cast<const float2*>(w.dG), static_cast<const float2*>(w.model),
                        static_cast<double*>(nullptr), static_cast<float2*>(nullptr),
                        static_cast<double*>(nullptr), static_cast<float2*>(nullptr), observed,
-                       static_cast<const double*>(w.radius), static_cast<const double*>(freqs), w.fcand);
+                       static_cast<const double*>(w.radius), static_cast<const double*>(freqs), w.fcand, counts,
+                       static_cast<const int32_t*>(w.skip));
     hipLaunchKernelGGL(model_basis_kernel, dim3(unsigned(items)), dim3(kBasisThreads), 0, st, p,
                        static_cast<const double*>(w.fcand), K, D, T, sum_b, w.G2, w.dG2);
     hipLaunchKernelGGL(refine_accept_kernel, dim3(unsigned(tones)), dim3(kBackThreads), 0, st, p, K, T, sum_b,
                        static_cast<const float2*>(w.G), static_cast<const float2*>(w.G2),
                        static_cast<const float2*>(w.model), observed, static_cast<const double*>(w.fcand),
-                       freqs, amps, w.radius, trust_bins);
+                       freqs, amps, w.radius, trust_bins, counts, static_cast<const int32_t*>(w.skip));
   }
   return hipGetLastError();
 }

@@ -190,12 +190,20 @@ int launch_plain_dft(const DevPtrs& p, int64_t frame, int T, int plane, int pad,
 int launch_model_forward(const DevPtrs& p, const double* freqs, const float2* amps, int64_t batch,
                          int K, int D, int T, int maxB, int sum_b, float2* G, float2* dG,
                          float2* model, void* stream);
+// observed - model of the first counts[f] tones (all K when counts is NULL)
+int launch_model_residual(const DevPtrs& p, const float2* observed, const double* freqs, const float2* amps,
+                          int64_t batch, int K, int D, int T, int maxB, int sum_b, const int32_t* counts,
+                          float2* G, float2* dG, float2* residual, void* stream);
 // Workspace of a refinement: factors at f (G, dG) and at the candidate
 // frequencies (G2, dG2), [batch][T][K][sum_b] each; the model, in the bucket
 // layout; per tone the trust radius (bins) and the candidate frequencies.
 struct RefineWork {
   float2 *G, *dG, *G2, *dG2, *model;
   double *radius, *fcand;
+  double *saved_f;         // [batch][K][D] state of the lowest loss so far
+  float2* saved_a;         // [batch][K]
+  double *best, *loss_now; // [batch]
+  int32_t* skip;           // [batch]: 1 when the guard restored the frame
 };
 // Initial amplitudes of tones at `freqs` from the observed buckets (G, dG:
 // factor scratch of one model).
@@ -204,8 +212,9 @@ int launch_initial_amplitudes(const DevPtrs& p, const double* freqs, int64_t bat
                               float2* amps, float* spread, void* stream);
 // `steps` refinement steps in place on freqs / amps; loss (may be NULL):
 // [steps + 1][batch] FP64 losses before each step and after the last.
+// counts (may be NULL): tones taking part per frame (the first counts[f]).
 int launch_refine(const DevPtrs& p, const float2* observed, double* freqs, float2* amps, int64_t batch,
-                  int K, int D, int T, int maxB, int sum_b, int steps, double trust_bins,
+                  int K, int D, int T, int maxB, int sum_b, int steps, double trust_bins, const int32_t* counts,
                   const RefineWork& w, double* loss, void* stream);
 // Device address of the library's static scratch array on `device`, which
 // must be the current device (resolved once per device, then cached).

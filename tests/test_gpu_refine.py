@@ -264,8 +264,8 @@ def test_detector_initialized_refinement():
     """The pipeline detect -> estimate -> refine: the strongest peaks the
     detector reports for frames of well-detectable tones whose per-round
     amplitudes agree (rsft_initial_amplitudes' spread; ghost peaks of the
-    Remark-1 ambiguity are as strong as weak tones here), then 10
-    refinement steps. Every tone is among the starts; each ends no farther
+    Remark-1 ambiguity are as strong as weak tones here), with the peeling
+    rounds of select_tones (rsft_model_residual), then 10 refinement steps. Every tone is among the starts; each ends no farther
     from the truth than the larger of its start error and 0.02 bin, the
     largest error does not grow, and the loss falls."""
     from paper_1610_01050_amd import Plan
@@ -283,10 +283,10 @@ def test_detector_initialized_refinement():
         truth.append(fr)
     plan.execute(torch.from_numpy(np.stack(frames)).to("cuda"))
     recs, _ = plan.detect()
-    f_d, a_d, passed = select_tones(plan, recs, K)
-    assert list(passed) == [K, K]
+    f_d, a_d, counts = select_tones(plan, recs, K)
+    assert counts.cpu().tolist() == [K, K]
     start = f_d.cpu().numpy()
-    fr_d, _, losses = refine(plan, None, f_d, a_d, steps=10)
+    fr_d, _, losses = refine(plan, None, f_d, a_d, steps=10, counts=counts)
     losses = losses.cpu().numpy().sum(axis=1)
     end = fr_d.cpu().numpy()
     e0, e1 = [], []
@@ -302,4 +302,89 @@ def test_detector_initialized_refinement():
     assert np.all(e1 <= np.maximum(e0, 0.02))
     assert e1.max() <= e0.max()
     assert losses[-1] < losses[0]
+    plan.close()
+
+
+def test_refine_guard_and_tone_counts_match_oracle():
+    """Eight refinement iterations on two frames with a close pair of tones
+    (1.3 x 0.9 bins apart, sharing buckets) where the decoupled steps raise
+    the loss: in frame 0 (all three tones) at the fifth iteration, in frame 1
+    (two of three tones taking part, d_tone_counts) at the last. The GPU's
+    guard restores the lowest-loss state as the FP64 oracle's does: the
+    reported losses match the oracle's within 1e-4 relative and repeat where
+    the oracle's repeat, frequencies within 2e-3 bin, amplitudes within 2e-3
+    relative; the inactive tone is left exactly as it was."""
+    shape, buckets = (256, 128), (16, 16)
+    from paper_1610_01050_amd import Plan
+    rng = np.random.default_rng(12)
+    sigma = synth.draw_sigma(rng, 3, shape)
+    plan = Plan(shape, buckets, rounds=3, sigma=sigma, pfa=1e-3, max_batch=2)
+    oplan = OR.OraclePlan(shape, buckets, sigma, 60.0, None, 1e-3)
+    drawn = []
+    for _ in range(8):
+        base = rng.random(2)
+        freqs = np.stack([base, base + np.array([1.3, 0.9]) / np.array(shape), rng.random(2)]) % 1.0
+        amps = (rng.standard_normal(3) + 1j * rng.standard_normal(3)) * 3.0
+        x = synth.synthesize(shape, freqs, None, amps) + synth.complex_noise(rng, shape)
+        obs = RF.round_buckets(x, oplan).astype(np.complex64)
+        sf = freqs + rng.uniform(-0.4, 0.4, freqs.shape) / np.array(shape)
+        sa = (amps * (1 + 0.2 * rng.standard_normal(3))).astype(np.complex64)
+        drawn.append((obs, sf, sa))
+    use, counts = (drawn[0], drawn[7]), (3, 2)
+    obs_d = torch.tensor(np.concatenate([u[0].reshape(-1) for u in use]), device="cuda")
+    start_f = np.stack([u[1] for u in use])
+    start_a = np.stack([u[2] for u in use])
+    f_d, a_d = _dev(start_f, start_a)
+    cnt = torch.tensor(counts, dtype=torch.int32, device="cuda")
+    steps = 8
+    ws = plan.refine_workspace(2, 3)
+    loss = torch.empty((steps + 1) * 2, dtype=torch.float64, device="cuda")
+    plan.refine(f_d, a_d, steps, ws, observed=obs_d, loss=loss, counts=cnt)
+    gf, ga = f_d.cpu().numpy(), a_d.cpu().numpy()
+    gl = loss.cpu().numpy().reshape(steps + 1, 2)
+    for f in range(2):
+        wf, wa, _, wl = RF.refine(start_f[f], start_a[f].astype(np.complex128), oplan,
+                                  use[f][0].astype(np.complex128), steps, active=counts[f])
+        wl = np.array(wl)
+        restored = [i for i in range(1, steps + 1) if wl[i] == wl[i - 1]]
+        assert restored, "the case exercises the guard"
+        print(f"frame {f}: oracle restores at {restored}", flush=True)
+        assert np.max(np.abs(gl[:, f] / wl - 1)) <= 1e-4
+        for i in restored:
+            assert gl[i, f] == gl[i - 1, f]
+        k = counts[f]
+        err = (((gf[f, :k] - wf[:k] + 0.5) % 1.0) - 0.5) * np.array(shape)
+        assert np.max(np.abs(err)) <= 2e-3, err
+        assert np.max(np.abs(ga[f, :k] / wa[:k] - 1)) <= 2e-3
+        assert np.array_equal(gf[f, k:], start_f[f, k:])
+        assert np.array_equal(ga[f, k:], start_a[f, k:])
+    plan.close()
+
+
+def test_model_residual_matches_oracle():
+    """observed - model of the first counts[f] tones (rsft_model_residual)
+    against the FP64 oracle on noisy observed buckets: within 1e-4 of the
+    round's rms; with counts 0 the residual is the observed buckets
+    exactly; a residual that would overwrite the observed buckets is
+    refused."""
+    shape, buckets, K = (256, 128), (16, 16), 4
+    plan, oplan, freqs, amps, rng = _setup(shape, buckets, K, seed=57, batch=3)
+    obs = []
+    for f in range(3):
+        x = synth.synthesize(shape, freqs[f], None, amps[f]) + synth.complex_noise(rng, shape)
+        obs.append(RF.round_buckets(x, oplan).astype(np.complex64))
+    obs_d = torch.tensor(np.concatenate([o.reshape(-1) for o in obs]), device="cuda")
+    f_d, a_d = _dev(freqs, amps)
+    counts = (4, 2, 0)
+    cnt = torch.tensor(counts, dtype=torch.int32, device="cuda")
+    ws = plan.model_workspace(3, K)
+    got = _frames(plan.model_residual(f_d, a_d, ws, observed=obs_d, counts=cnt), plan, 3)
+    for f in range(3):
+        want = RF.model_residual(freqs[f], amps[f], oplan, obs[f].astype(np.complex128), active=counts[f])
+        for s in range(3):
+            rms = np.sqrt(np.mean(np.abs(obs[f][s]) ** 2))
+            assert np.max(np.abs(got[f, s] - want[s])) <= 1e-4 * rms, (f, s)
+    assert np.array_equal(got[2], obs[2])
+    with pytest.raises(RuntimeError):
+        plan.model_residual(f_d, a_d, ws, observed=obs_d, counts=cnt, out=obs_d)
     plan.close()

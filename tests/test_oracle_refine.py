@@ -219,3 +219,55 @@ def test_refine_step_rejects_a_step_that_raises_the_loss():
     f0 = freqs + 0.3 / np.array(shape)
     f, a, rad = RF.refine_step(f0, amps, np.array([0.01, 0.01]), plan, observed)
     assert np.abs((f - f0) * np.array(shape)).max() <= 0.01 + 1e-12
+
+
+def test_refine_guard_and_inactive_tones():
+    """Two copies of one noise-free tone, both at amplitude 0: each takes the
+    least-squares amplitude against the same residual (the full amplitude),
+    so together they overshoot to twice it and the loss rises; the
+    per-iteration check then restores the lowest-loss state, so the reported
+    losses never rise and the result is the lowest-loss state seen. Tones
+    past `active` stay as given and are not part of the model."""
+    shape, b = (128, 64), (16, 8)
+    rng = np.random.default_rng(81)
+    plan = _plan(shape, b, seed=9)
+    freqs, amps = _tones(rng, shape, 1)
+    observed = RF.model(freqs, amps, plan)
+    f0 = np.concatenate([freqs, freqs])
+    a0 = np.zeros(2, dtype=np.complex128)
+    f1, a1, _ = RF.refine_step(f0, a0, np.full(2, 0.25), plan, observed)
+    assert RF.model_loss(f1, a1, plan, observed) > RF.model_loss(f0, a0, plan, observed)
+    f, a, rad, losses = RF.refine(f0, a0, plan, observed, steps=6)
+    assert all(l1 <= l0 for l0, l1 in zip(losses, losses[1:]))
+    assert losses[-1] == min(losses)
+    assert RF.model_loss(f, a, plan, observed) == losses[-1]
+    f0 = np.concatenate([freqs, freqs + 0.05 / np.array(shape)])
+    a0 = np.concatenate([amps, amps])
+    f, a, rad, losses = RF.refine(f0, a0, plan, observed, steps=6)
+    assert all(l1 <= l0 for l0, l1 in zip(losses, losses[1:]))
+    # a far-away third tone marked inactive: untouched, outside the model
+    f3 = np.concatenate([f0, [[0.71, 0.33]]])
+    a3 = np.concatenate([a0, [5.0 + 0j]])
+    g, c, _, l3 = RF.refine(f3, a3, plan, observed, steps=6, active=2)
+    assert np.array_equal(g[2], f3[2]) and c[2] == a3[2]
+    assert np.allclose(l3, losses)
+
+
+def test_model_residual_leaves_the_unmodelled_tone():
+    """A noise-free frame of three off-grid tones built on the full grid:
+    the residual after all three is zero (to FP64 rounding), and after the
+    first two it equals the literal round buckets (window, permutation, flat
+    window, aliasing, DFT on the full grid) of the third tone's signal."""
+    shape, b = (64, 32), (8, 4)
+    plan = _plan(shape, b, seed=9)
+    rng = np.random.default_rng(41)
+    freqs, _ = _tones(rng, shape, 3)
+    amps = np.array([2.0 - 1.0j, 0.5 + 1.5j, -1.2 + 0.3j])
+    x = synth.synthesize(shape, freqs, None, amps)
+    obs = RF.round_buckets(x, plan)
+    scale = np.max(np.abs(obs))
+    assert np.max(np.abs(RF.model_residual(freqs, amps, plan, obs))) <= 1e-10 * scale
+    third = RF.round_buckets(synth.synthesize(shape, freqs[2:], None, amps[2:]), plan)
+    got = RF.model_residual(freqs, amps, plan, obs, active=2)
+    assert np.max(np.abs(got - third)) <= 1e-10 * scale
+    assert np.max(np.abs(third)) > 1e-3 * scale
