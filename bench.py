@@ -513,26 +513,61 @@ OTHER_WORKLOADS = (
 def _workload_plan(name, nframes, max_det):
     """Plan, input array and per-frame metadata for one batched workload.
     Workloads with one sigma per frame get one descriptor per frame."""
-    from paper_1610_01050_amd import Plan
     cfg = synth.WORKLOADS[name]
-    dtype = "c128" if cfg["dtype"] == np.complex128 else "c64"
     if not cfg["sigma_per_frame"]:
         frames, metas = synth.make_batch(name, nframes)
         for m in metas:
             m["buckets"] = cfg["buckets"]
-        plan = Plan(cfg["shape"], cfg["buckets"], rounds=cfg["rounds"], sigma=synth.shared_sigma(name),
-                    window_atten_db=cfg["atten_db"], pfa=cfg["pfa"], dtype=dtype,
-                    max_batch=nframes, max_detections=max_det)
-        return plan, frames, metas
+        return _plan_for(name, nframes, max_det, metas), frames, metas
     metas = [synth.make_frame(name, f) for f in range(nframes)]
-    descs = []
     for m in metas:
         m["buckets"] = cfg["buckets"] or tuple(n // 16 for n in m["shape"])
-        descs.append(dict(shape=m["shape"], buckets=m["buckets"], rounds=cfg["rounds"], sigma=m["sigma"],
-                          window_atten_db=cfg["atten_db"], pfa=cfg["pfa"], dtype=dtype,
-                          max_detections=max_det))
     frames = np.concatenate([m.pop("frame").ravel() for m in metas])
-    return Plan.uneven(descs), frames, metas
+    return _plan_for(name, nframes, max_det, metas), frames, metas
+
+
+def _plan_for(name, nframes, max_det, metas):
+    """The plan of a batched workload for frames described by `metas`."""
+    from paper_1610_01050_amd import Plan
+    cfg = synth.WORKLOADS[name]
+    dtype = "c128" if cfg["dtype"] == np.complex128 else "c64"
+    if not cfg["sigma_per_frame"]:
+        return Plan(cfg["shape"], cfg["buckets"], rounds=cfg["rounds"], sigma=synth.shared_sigma(name),
+                    window_atten_db=cfg["atten_db"], pfa=cfg["pfa"], dtype=dtype,
+                    max_batch=nframes, max_detections=max_det)
+    descs = [dict(shape=m["shape"], buckets=m["buckets"], rounds=cfg["rounds"], sigma=m["sigma"],
+                  window_atten_db=cfg["atten_db"], pfa=cfg["pfa"], dtype=dtype, max_detections=max_det)
+             for m in metas]
+    return Plan.uneven(descs)
+
+
+def pipelined_ms(plans, bufs, steps, warmup):
+    """Milliseconds per batch with batches alternating over two plans: the
+    fold of batch k (rsft_execute_fold, one stream for all folds) beside the
+    tail of batch k - 1 (rsft_execute_tail, one stream per plan), ordered by
+    events; wall time over `steps` batches between two synchronizations."""
+    import torch
+    sF = torch.cuda.Stream()
+    sT = [torch.cuda.Stream(), torch.cuda.Stream()]
+    fdone = [torch.cuda.Event(), torch.cuda.Event()]
+    tdone = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def run(n):
+        for k in range(n):
+            i = k % 2
+            sF.wait_event(tdone[i])
+            plans[i].execute_fold(bufs[k % len(bufs)], stream=sF)
+            fdone[i].record(sF)
+            sT[i].wait_event(fdone[i])
+            plans[i].execute_tail(stream=sT[i])
+            tdone[i].record(sT[i])
+
+    run(max(warmup, 2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
 
 
 def workloads_section(dev, steps, warmup, names=None):
@@ -581,6 +616,11 @@ def workloads_section(dev, steps, warmup, names=None):
         torch.cuda.synchronize()
         stages, _ = plan.stage_times(reset=True)
         plan.set_option(OPT_TIMING, 0)
+        # the same batches pipelined over two plans (fold beside the previous tail)
+        plan2 = _plan_for(name, nframes, max_det, metas)
+        plan2.autotune(xa, repeats=3)
+        pipe_ms = pipelined_ms([plan, plan2], bufs, max(steps, 20), warmup)
+        plan2.close()
         plan.execute(xa)
         recs, counts = plan.detect()
         hits = tgt = fa = outside = 0
@@ -610,6 +650,7 @@ def workloads_section(dev, steps, warmup, names=None):
             "graph_replay_ms": {"p10": float(np.percentile(replay, 10)), "median": med,
                                 "p90": float(np.percentile(replay, 90))},
             "frames_per_s": nframes / (med * 1e-3),
+            "pipelined_two_plans": {"ms_per_batch": pipe_ms, "frames_per_s": nframes / (pipe_ms * 1e-3)},
             "input_gbs": in_bytes / (med * 1e-3) / 1e9,
             "stage_ms": stages,
             "fold_algorithmic_bytes": in_bytes + part_bytes,

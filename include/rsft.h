@@ -214,6 +214,29 @@ rsft_status rsft_execute(rsft_plan_t plan, const void* d_input, int64_t batch,
                          void* stream);
 
 /*
+ * rsft_execute in two halves, for pipelining batches over several plans.
+ * rsft_execute_fold enqueues the fold stage on `stream` (window,
+ * permutation, flat window and aliasing of Algorithm 1, the only stage that
+ * reads d_input; same arguments as rsft_execute); rsft_execute_tail enqueues
+ * the rest for the batch last folded on this plan (B-point DFT and
+ * first-stage threshold, vote of Def. 3-4 and eq. a_i, compaction and
+ * estimates). A fold followed by its tail gives exactly what rsft_execute
+ * gives, and the detection and bucket calls then refer to that batch. The
+ * fold is bound by HBM bandwidth and the rest mostly by instruction issue
+ * and latency, so with two plans the fold of one batch can run beside the
+ * tail of the previous batch on the other plan. The caller orders the
+ * streams with events: a plan's tail after its own fold, and a plan's next
+ * fold after its own previous tail (the fold overwrites what the tail
+ * reads). Graph replay (RSFT_OPT_GRAPH) applies to each half separately;
+ * with RSFT_OPT_TIMING set the halves launch eagerly and record no stage
+ * times. Errors: as rsft_execute; NOT_READY from rsft_execute_tail without
+ * a preceding rsft_execute_fold on the plan (rsft_execute in between
+ * cancels a pending fold).
+ */
+rsft_status rsft_execute_fold(rsft_plan_t plan, const void* d_input, int64_t batch, void* stream);
+rsft_status rsft_execute_tail(rsft_plan_t plan, void* stream);
+
+/*
  * Choose the plan's launch shapes by timing them on d_input (same contract
  * as rsft_execute) with hipEvents on `stream`, `repeats` runs each (<= 0: 5):
  * - fold stage (the HBM-bound stage): work-group size (256 / 512 threads),

@@ -46,7 +46,7 @@ SYMBOLS = (
     "rsft_stage1_probability", "rsft_draw_sigma",
     "rsft_model_workspace_size", "rsft_model_forward", "rsft_model_forward_noalloc",
     "rsft_model_backward", "rsft_refine_workspace_size", "rsft_initial_amplitudes", "rsft_refine",
-    "rsft_model_residual",
+    "rsft_model_residual", "rsft_execute_fold", "rsft_execute_tail",
     "rsft_design_thresholds",
 )
 
@@ -182,6 +182,8 @@ def load_library(path=None):
     lib.rsft_refine.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_double,
                                 vp, vp, vp]
     lib.rsft_model_residual.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, vp, vp, vp, vp]
+    lib.rsft_execute_fold.argtypes = [vp, vp, i64, vp]
+    lib.rsft_execute_tail.argtypes = [vp, vp]
     lib.rsft_design_thresholds.argtypes = [ctypes.POINTER(DesignParams),
                                            ctypes.POINTER(DesignResult)]
     lib.rsft_draw_sigma.argtypes = [ctypes.c_uint64, ctypes.c_int32,
@@ -342,6 +344,7 @@ class Plan:
         self.rounds = int(_descs[0].get("rounds", 3))
         self.dtype = _descs[0].get("dtype", "c64")
         self.last_batch = None
+        self._folded = None
         # input elements: per frame of a uniform plan, in all of an uneven one
         seg = self.rounds if _descs[0].get("segments") else 1
         self._elems = [int(np.prod(d["shape"])) * seg for d in self.descs]
@@ -377,6 +380,21 @@ class Plan:
         _check(self._lib, self._lib.rsft_execute(self._h, ctypes.c_void_p(x.data_ptr()),
                                                  int(batch), _stream_handle(stream)))
         self.last_batch = int(batch)
+
+    def execute_fold(self, x, batch=None, stream=None):
+        """Enqueue the fold stage of `x` on `stream` (rsft_execute_fold)."""
+        if batch is None:
+            batch = x.shape[0] if self.uniform else len(self.descs)
+        self._check_input(x, batch)
+        _check(self._lib, self._lib.rsft_execute_fold(self._h, ctypes.c_void_p(x.data_ptr()),
+                                                      int(batch), _stream_handle(stream)))
+        self._folded = int(batch)
+
+    def execute_tail(self, stream=None):
+        """Enqueue the stages after the fold for the batch last folded
+        (rsft_execute_tail)."""
+        _check(self._lib, self._lib.rsft_execute_tail(self._h, _stream_handle(stream)))
+        self.last_batch = self._folded
 
     def autotune(self, x, batch=None, repeats=5, stream=None):
         """Time the fold stage's launch shapes and the two compact/estimate

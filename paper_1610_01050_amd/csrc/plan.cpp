@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -96,13 +97,15 @@ struct rsft_plan_s {
   rsft::DevPtrs ptrs{};
   // state of the last execute
   int64_t last_batch = -1;
+  int64_t folded_batch = -1;   // batch of the last rsft_execute_fold not yet followed by its tail
   // graph replay
   bool use_graph = true;
   hipStream_t capture_stream = nullptr;
   // estimate layout: 1 adds overflow workers for dense chunks (rsft_autotune)
   int est_workers = 0;
-  std::map<std::pair<const void*, int64_t>, hipGraphExec_t> graphs;
-  std::vector<std::pair<const void*, int64_t>> graph_order;
+  // captured launch sequences per (part: 0 whole, 1 fold, 2 tail; input; batch)
+  std::map<std::tuple<int, const void*, int64_t>, hipGraphExec_t> graphs;
+  std::vector<std::tuple<int, const void*, int64_t>> graph_order;
   // stage timing
   bool timing = false;
   std::vector<TimingSet> timing_sets;
@@ -803,15 +806,8 @@ rsft_status vote_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
 }
 
 // The hot path, stage by stage; `ev` (optional) brackets the stages.
-rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStream_t st,
-                    hipEvent_t* ev) {
-  const auto& q = pl->ptrs;
-  if (ev) HIP_TRY(hipEventRecord(ev[0], st));
-  {
-    const rsft_status fs = fold_stage(pl, d_input, batch, st, pl->fold);
-    if (fs != RSFT_OK) return fs;
-  }
-  if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+// the stages after the fold: DFT + threshold, vote, scan + compact/estimate
+rsft_status enqueue_tail(rsft_plan_s* pl, int64_t batch, hipStream_t st, hipEvent_t* ev) {
   {
     const rsft_status ds = dft_stage(pl, batch, st);
     if (ds != RSFT_OK) return ds;
@@ -827,6 +823,50 @@ rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStre
     if (es != RSFT_OK) return es;
   }
   if (ev) HIP_TRY(hipEventRecord(ev[4], st));
+  return RSFT_OK;
+}
+
+rsft_status enqueue(rsft_plan_s* pl, const void* d_input, int64_t batch, hipStream_t st,
+                    hipEvent_t* ev) {
+  if (ev) HIP_TRY(hipEventRecord(ev[0], st));
+  {
+    const rsft_status fs = fold_stage(pl, d_input, batch, st, pl->fold);
+    if (fs != RSFT_OK) return fs;
+  }
+  if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+  return enqueue_tail(pl, batch, st, ev);
+}
+
+// Replays the captured launch sequence of `key` on `user`, capturing it
+// from `body(stream)` first when it is not cached (at most 8 kept).
+template <class Body>
+rsft_status replay(rsft_plan_s* pl, const std::tuple<int, const void*, int64_t>& key, hipStream_t user,
+                   Body&& body) {
+  auto it = pl->graphs.find(key);
+  if (it == pl->graphs.end()) {
+    if (pl->graphs.size() >= 8) {
+      const auto old = pl->graph_order.front();
+      pl->graph_order.erase(pl->graph_order.begin());
+      (void)hipGraphExecDestroy(pl->graphs[old]);
+      pl->graphs.erase(old);
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(pl->capture_stream, hipStreamCaptureModeThreadLocal));
+    const rsft_status st = body(pl->capture_stream);
+    hipError_t e = hipStreamEndCapture(pl->capture_stream, &graph);
+    if (st != RSFT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(RSFT_ERROR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(RSFT_ERROR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    it = pl->graphs.emplace(key, exec).first;
+    pl->graph_order.push_back(key);
+  }
+  HIP_TRY(hipGraphLaunch(it->second, user));
   return RSFT_OK;
 }
 
@@ -889,6 +929,7 @@ rsft_status rsft_execute(rsft_plan_t pl, const void* d_input, int64_t batch, voi
   if (st != RSFT_OK) return st;
   hipStream_t user = static_cast<hipStream_t>(stream);
   pl->last_batch = batch;
+  pl->folded_batch = -1;
   if (batch == 0) return RSFT_OK;
   if (pl->timing) {
     if (pl->timing_sets.empty()) {
@@ -904,33 +945,33 @@ rsft_status rsft_execute(rsft_plan_t pl, const void* d_input, int64_t batch, voi
     return RSFT_OK;
   }
   if (!pl->use_graph) return enqueue(pl, d_input, batch, user, nullptr);
-  const auto key = std::make_pair(d_input, batch);
-  auto it = pl->graphs.find(key);
-  if (it == pl->graphs.end()) {
-    if (pl->graphs.size() >= 4) {
-      const auto old = pl->graph_order.front();
-      pl->graph_order.erase(pl->graph_order.begin());
-      (void)hipGraphExecDestroy(pl->graphs[old]);
-      pl->graphs.erase(old);
-    }
-    hipGraph_t graph = nullptr;
-    HIP_TRY(hipStreamBeginCapture(pl->capture_stream, hipStreamCaptureModeThreadLocal));
-    st = enqueue(pl, d_input, batch, pl->capture_stream, nullptr);
-    hipError_t e = hipStreamEndCapture(pl->capture_stream, &graph);
-    if (st != RSFT_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return st;
-    }
-    if (e != hipSuccess) return fail(RSFT_ERROR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(RSFT_ERROR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    it = pl->graphs.emplace(key, exec).first;
-    pl->graph_order.push_back(key);
-  }
-  HIP_TRY(hipGraphLaunch(it->second, user));
-  return RSFT_OK;
+  return replay(pl, std::make_tuple(0, d_input, batch), user,
+                [&](hipStream_t cs) { return enqueue(pl, d_input, batch, cs, nullptr); });
+}
+
+rsft_status rsft_execute_fold(rsft_plan_t pl, const void* d_input, int64_t batch, void* stream) {
+  if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
+  rsft_status st = check_batch(pl, d_input, batch);
+  if (st != RSFT_OK) return st;
+  hipStream_t user = static_cast<hipStream_t>(stream);
+  pl->folded_batch = batch;
+  if (batch == 0) return RSFT_OK;
+  auto body = [&](hipStream_t cs) { return fold_stage(pl, d_input, batch, cs, pl->fold); };
+  if (!pl->use_graph || pl->timing) return body(user);
+  return replay(pl, std::make_tuple(1, d_input, batch), user, body);
+}
+
+rsft_status rsft_execute_tail(rsft_plan_t pl, void* stream) {
+  if (!pl) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL plan");
+  if (pl->folded_batch < 0) return fail(RSFT_ERROR_NOT_READY, "rsft_execute_tail without a preceding rsft_execute_fold");
+  const int64_t batch = pl->folded_batch;
+  pl->folded_batch = -1;
+  pl->last_batch = batch;
+  if (batch == 0) return RSFT_OK;
+  hipStream_t user = static_cast<hipStream_t>(stream);
+  auto body = [&](hipStream_t cs) { return enqueue_tail(pl, batch, cs, nullptr); };
+  if (!pl->use_graph || pl->timing) return body(user);
+  return replay(pl, std::make_tuple(2, static_cast<const void*>(nullptr), batch), user, body);
 }
 
 rsft_status rsft_autotune(rsft_plan_t pl, const void* d_input, int64_t batch, void* stream,
