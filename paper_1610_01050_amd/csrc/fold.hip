@@ -78,8 +78,9 @@ __device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restr
     const int nch = p.descs[0].nchunks;
     f = tile / tiles_per_frame;
     const int rem = tile - f * tiles_per_frame;
-    cls = rem / nch;
-    chunk = rem - cls * nch;
+    const int grp = rem / nch;
+    chunk = rem - grp * nch;
+    cls = grp * p.descs[0].fold_cpt;
   } else {
     const int32_t* t = p.tiles + 3 * int64_t(tile);
     f = t[0];
@@ -92,6 +93,7 @@ __device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restr
   const FrameDesc& d = p.descs[p.uniform ? 0 : f];
   const int64_t rel = p.uniform ? f : 0;
   const int nl = d.fold_nl, bl = d.fold_bl, R = d.rows_per_class, rows_total = d.rows_total;
+  const int cpt = d.fold_cpt;
   const float2* __restrict__ wrow = p.wrow + d.wrow_off;
   const float2* __restrict__ wcol = p.wcol + d.wcol_off;
   const int32_t* __restrict__ rl = p.rowlist + d.rowlist_off + int64_t(cls) * R;
@@ -142,18 +144,22 @@ __device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restr
         }
     }
   } else {
-    // short rows: G row groups, each covering the whole row
+    // short rows: G row groups, each covering the whole row; the tile's
+    // cpt classes take G / cpt consecutive groups each
     const int G = P / nl;
+    const int gpc = G / cpt;
     const int g = (tid * V) / nl;
     const int col = (tid * V) - g * nl;
+    const int j = g / gpc;
+    const int32_t* __restrict__ rlj = rl + j * R;
     float cr[TG][V], ci[TG][V];
 #pragma unroll
     for (int s = 0; s < TG; ++s)
 #pragma unroll
       for (int v = 0; v < V; ++v) cr[s][v] = ci[s][v] = 0.f;
 #pragma unroll 2
-    for (int i = g; i < R; i += G) {
-      const int row = rl[i];
+    for (int i = g - j * gpc; i < R; i += gpc) {
+      const int row = rlj[i];
       float2 x[V];
       load_vec<C128, NT, V>(in, int64_t(row) * nl + col, x);
 #pragma unroll
@@ -187,19 +193,23 @@ __device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restr
   // i * N_{D-1} + j (mod the pass) holds residue (i mod B_{D-2}) B_{D-1} +
   // (j mod B_{D-1}), and residue (r1, r2) owns the slots r2 + B_{D-1} a +
   // (r1 + B_{D-2} m) N_{D-1}.
-  const int nslots = P / bl;
+  // With cpt classes per tile, class j owns the slots [j, j + 1) * P / cpt.
+  const int nslots = P / bl / cpt;
   float2* part = p.part + d.part_off + rel * d.part_stride;
   if (bl == d.fold_bin) {
-    for (int o = tid; o < TG * bl; o += THREADS) {
-      const int s = o / bl;
-      const int rho = o - s * bl;
+    for (int o = tid; o < TG * cpt * bl; o += THREADS) {
+      const int s = o / (cpt * bl);
+      const int rem = o - s * cpt * bl;
+      const int j = rem / bl;
+      const int rho = rem - j * bl;
+      const float2* rs = red + s * P + j * nslots * bl + rho;
       float sr = 0.f, si = 0.f;
       for (int k = 0; k < nslots; ++k) {
-        const float2 v = red[s * P + rho + k * bl];
+        const float2 v = rs[k * bl];
         sr += v.x;
         si += v.y;
       }
-      part[(int64_t(chunk) * T + round0 + s) * d.B + int64_t(cls) * bl + rho] = make_float2(sr, si);
+      part[(int64_t(chunk) * T + round0 + s) * d.B + int64_t(cls + j) * bl + rho] = make_float2(sr, si);
     }
   } else {
     const int bin = d.fold_bin, lw = d.fold_lw;

@@ -358,6 +358,9 @@ rsft_status build_descriptor(const rsft_params& p, rsft::FrameDesc& d, rsft_plan
   d.rows_total = int32_t(rows_total);
   d.classes = int32_t(classes);
   d.rows_per_class = int32_t(R);
+  // rows shorter than the smallest fold pass: one tile takes several
+  // classes (a group of threads each), so that a work-group reads enough
+  d.fold_cpt = (F == 1 && nl < rsft::kFoldMinP) ? int32_t(std::min<int64_t>(rsft::kFoldMinP / nl, classes)) : 1;
   if (nl >= fold_p) {
     int64_t k = 1;
     const int64_t target = 32768;  // elements per tile
@@ -580,14 +583,14 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   // fold tiles
   std::vector<int32_t> tiles;
   if (pl->uniform) {
-    pl->tiles_per_frame = int64_t(pl->descs[0].classes) * pl->descs[0].nchunks;
+    pl->tiles_per_frame = int64_t(pl->descs[0].classes / pl->descs[0].fold_cpt) * pl->descs[0].nchunks;
   } else {
     struct Tile { int64_t bytes; int32_t f, c, k; };
     std::vector<Tile> tl;
     for (int64_t i = 0; i < nframes; ++i) {
       const auto& d = pl->descs[size_t(i)];
-      const int64_t bytes = int64_t(d.rows_per_class) * std::min<int64_t>(d.chunk_cols, d.fold_nl);
-      for (int c = 0; c < d.classes; ++c)
+      const int64_t bytes = int64_t(d.rows_per_class) * std::min<int64_t>(d.chunk_cols, d.fold_nl) * d.fold_cpt;
+      for (int c = 0; c < d.classes; c += d.fold_cpt)
         for (int k = 0; k < d.nchunks; ++k) tl.push_back({bytes, int32_t(i), c, k});
     }
     // largest tiles first: the hardware dispatcher then balances the tail

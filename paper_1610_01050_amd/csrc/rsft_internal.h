@@ -41,8 +41,10 @@ struct FrameDesc {
   // flattened (fold_nl cells, fold_bl residue classes). Residue of slot q of
   // a row: ((q >> fold_lw) mod (fold_bl / fold_bin)) * fold_bin + q mod
   // fold_bin, with fold_bin = B_{D-1} and fold_lw = log2 N_{D-1} (fold_bl =
-  // fold_bin for one dimension: q mod B_{D-1})
-  int32_t fold_nl, fold_bl, fold_bin, fold_lw;
+  // fold_bin for one dimension: q mod B_{D-1}). fold_cpt: residue classes
+  // per fold tile (rows shorter than the smallest fold pass: several
+  // classes share a work-group, one group of threads per class; else 1)
+  int32_t fold_nl, fold_bl, fold_bin, fold_lw, fold_cpt;
   int32_t words;              // flag words per round = ceil(B / 32)
   int32_t cap;                // detection capacity of a frame
   int32_t n_est;              // rounds used for magnitude estimates (1..T)
@@ -137,6 +139,7 @@ struct FoldConfig {
   int nontemporal;  // 1: streaming (non-temporal) loads of the input
 };
 constexpr int kFoldMaxP = 2048;   // largest threads * vec a plan may be tuned to
+constexpr int kFoldMinP = 512;    // smallest
 
 // Launchers (fold.hip, dft.hip, vote.hip, estimate.hip). All enqueue on `stream` and return hipError_t.
 int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,

@@ -182,6 +182,55 @@ def test_uneven_batch_matches_oracle():
     plan.close()
 
 
+@pytest.mark.parametrize("threads,vec,nt", [(256, 2, 1), (256, 4, 0), (512, 2, 1), (512, 4, 0)])
+def test_fold_shapes_on_short_rows_match_oracle(threads, vec, nt):
+    """Every fold launch shape on frames whose rows are shorter than the
+    smallest fold pass, where one work-group folds several residue classes
+    (rows of 32, 64, 128 and 256 cells, up to 16 classes per tile), uneven
+    and uniform: every frame's full result against the oracle."""
+    from paper_1610_01050_amd import Plan
+    from paper_1610_01050_amd.binding import OPT_FOLD_NONTEMPORAL, OPT_FOLD_THREADS, OPT_FOLD_VEC
+    print(f"fold {threads} x {vec}, nt {nt}", flush=True)
+    cases = [((128, 32), (8, 4)), ((512, 64), (32, 8)), ((128, 128), (8, 8)),
+             ((256, 128), (16, 8)), ((64, 256), (4, 16)), ((256, 256), (16, 16))]
+    descs, frames, sigmas = [], [], []
+    for i, (sh, bk) in enumerate(cases):
+        sg = synth.draw_sigma(np.random.default_rng(470 + i), 3, sh)
+        descs.append(dict(shape=sh, buckets=bk, rounds=3, sigma=sg, pfa=1e-3, max_detections=1 << 14))
+        x, _ = make_input(sh, 4, seed=570 + i)
+        frames.append(x)
+        sigmas.append(sg)
+
+    def shaped(plan):
+        plan.set_option(OPT_FOLD_THREADS, threads)
+        plan.set_option(OPT_FOLD_VEC, vec)
+        plan.set_option(OPT_FOLD_NONTEMPORAL, nt)
+        return plan
+
+    plan = shaped(Plan.uneven(descs))
+    plan.execute(torch.from_numpy(np.concatenate([x.ravel() for x in frames])).to("cuda"))
+    recs, counts = plan.detect()
+    gbk = [b.cpu().numpy() for b in plan.buckets()]
+    gfl = [w.cpu().numpy().view(np.uint32) for w in plan.flags()]
+    plan.close()
+    refs = []
+    for f, (sh, bk) in enumerate(cases):
+        oplan = oracle_plan(sh, bk, sigmas[f], pfa=1e-3)
+        refs.append((oplan, OR.rsft(frames[f], oplan)))
+        _check_frame(f, oplan, refs[-1][1], recs, gbk[f], gfl[f])
+    # the same shapes as uniform batches of two frames
+    for f, (sh, bk) in enumerate(cases):
+        plan = shaped(Plan(sh, bk, rounds=3, sigma=sigmas[f], pfa=1e-3, max_batch=2,
+                           max_detections=1 << 14))
+        plan.execute(torch.from_numpy(np.stack([frames[f], frames[f]])).to("cuda"))
+        recs, counts = plan.detect()
+        gbk = [b.cpu().numpy() for b in plan.buckets()]
+        gfl = [w.cpu().numpy().view(np.uint32) for w in plan.flags()]
+        plan.close()
+        for g in range(2):
+            _check_frame(g, refs[f][0], refs[f][1], recs, gbk[g], gfl[g])
+
+
 def test_uneven_3d_mixed_fold_views_matches_oracle():
     """Frames whose fold rows are the last dimension (N_last = 64) or the last
     two flattened (N_last = 32 or 16), of one or two compaction chunks (so
