@@ -49,6 +49,7 @@ CASES = {
     "tiny_last_bucket": ((128, 256), (32, 2), 3, 0, "c64", 2, 3, 1e-3, 60.0),
     "wide_rows_multichunk": ((16, 65536), (8, 128), 3, 0, "c64", 1, 1, 1e-3, 60.0),
     "single_round": ((256, 512), (16, 32), 1, 1, "c64", 2, 5, 1e-3, 60.0),
+    "t3_mu2_512x256": ((512, 256), (32, 16), 3, 2, "c64", 2, 5, 1e-3, 60.0),
     "five_rounds_mu3": ((256, 256), (16, 16), 5, 3, "c64", 2, 5, 1e-3, 60.0),
     "rectangular_windows": ((256, 256), (16, 16), 3, 0, "c64", 2, 5, 1e-3, 0.0),
     "forty_db": ((1024, 256), (32, 16), 3, 0, "c64", 2, 8, 1e-3, 40.0),
@@ -135,7 +136,7 @@ def test_estimated_noise_floor_matches_oracle(name):
     ("four_dim", 1), ("five_rounds_mu3", 1), ("one_dim_4096", 1), ("one_dim_4096", 0),
     ("rows_of_32_T5_mu3", 1), ("rows_of_32_T9_mu5", 1), ("offgrid_1024x1024", 1),
     ("offgrid_1024x1024", 0), ("rows_of_4096_b128", 1), ("rows_of_128_T6_mu4", 1),
-    ("short_rows_512x64", 1)])
+    ("short_rows_512x64", 1), ("t3_mu2_512x256", 0), ("t3_mu2_512x256", 1)])
 def test_votes_bit_exact_from_oracle_flags(name, vote_words):
     """Voting, second stage and ordering are integer work: given the oracle's
     flags, the detections and their votes must match exactly (word-parallel
