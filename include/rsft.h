@@ -180,6 +180,7 @@ typedef struct {
   int32_t estimate_workers;  /* compact/estimate: 1 = overflow workers */
   int32_t vote_kernel;       /* 0 per cell, 1 candidate rows, 2 32-cell masks, 3 word-parallel masks */
   int32_t dft_two_pass;      /* 1: the DFT runs in two passes (RSFT_OPT_DFT_SPLIT) */
+  int32_t dft_threads;       /* work-group size of the one-work-group DFT (RSFT_OPT_DFT_THREADS) */
 } rsft_plan_info_t;
 
 typedef struct rsft_plan_s* rsft_plan_t;
@@ -242,8 +243,9 @@ rsft_status rsft_execute_tail(rsft_plan_t plan, void* stream);
  * - fold stage (the HBM-bound stage): work-group size (256 / 512 threads),
  *   samples per thread (4 / 2), ordinary vs non-temporal input loads; the
  *   fastest is kept and *best_ms (may be NULL) gets its average duration;
- * - DFT, where both forms apply (RSFT_OPT_DFT_SPLIT): one work-group per
- *   transform or two passes, the faster kept;
+ * - DFT: one work-group per transform at each work-group size
+ *   (RSFT_OPT_DFT_THREADS) and, where it applies, the two passes
+ *   (RSFT_OPT_DFT_SPLIT); the fastest kept;
  * - vote, where both kernels apply (RSFT_OPT_VOTE_WORDS): word-parallel
  *   masks or the enumeration of candidate cells, the faster kept;
  * - compact/estimate: without or with overflow workers (the records of
@@ -503,7 +505,12 @@ enum {
      group of output columns with the threshold), 0 = one work-group per
      (round, frame). Same results (to FP32 rounding). Default 1; chosen by
      rsft_autotune. */
-  RSFT_OPT_DFT_SPLIT = 7
+  RSFT_OPT_DFT_SPLIT = 7,
+  /* work-group size of the one-work-group-per-(round, frame) DFT: 64, 256
+     or 1024 threads (one wave suits many small transforms, sixteen a few
+     large ones). Default by the plan's largest B: 64 up to 256 buckets,
+     256 up to 1024, else 1024; chosen by rsft_autotune. Same results. */
+  RSFT_OPT_DFT_THREADS = 8
 };
 rsft_status rsft_set_option(rsft_plan_t plan, int32_t option, int64_t value);
 

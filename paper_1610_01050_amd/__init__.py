@@ -7,7 +7,7 @@ library has not been built.
 
 from .binding import (  # noqa: F401
     DETECTION_DTYPE, OPT_ESTIMATE_WORKERS, OPT_GRAPH, OPT_TIMING, OPT_VOTE_WORDS,
-    OPT_DFT_SPLIT, STAGES, SYMBOLS, Plan, RsftError,
+    OPT_DFT_SPLIT, OPT_DFT_THREADS, STAGES, SYMBOLS, Plan, RsftError,
     chebyshev_window, design_thresholds, draw_sigma, flat_window, load_library, mod_inverse,
     stage1_probability,
 )

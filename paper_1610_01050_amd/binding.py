@@ -34,6 +34,7 @@ OPT_FOLD_THREADS, OPT_FOLD_VEC, OPT_FOLD_NONTEMPORAL = 2, 3, 4
 OPT_ESTIMATE_WORKERS = 5
 OPT_VOTE_WORDS = 6
 OPT_DFT_SPLIT = 7
+OPT_DFT_THREADS = 8
 STAGES = ("fold", "dft", "vote", "estimate")
 
 # Every symbol include/rsft.h declares.
@@ -121,6 +122,7 @@ class PlanInfo(ctypes.Structure):
         ("fold_threads", ctypes.c_int32), ("fold_vec", ctypes.c_int32),
         ("fold_nontemporal", ctypes.c_int32), ("estimate_workers", ctypes.c_int32),
         ("vote_kernel", ctypes.c_int32), ("dft_two_pass", ctypes.c_int32),
+        ("dft_threads", ctypes.c_int32),
     ]
 
 
@@ -500,6 +502,7 @@ class Plan:
             "estimate_workers": out.estimate_workers,
             "vote_kernel": ("per_cell", "candidate_rows", "masks_32", "word_masks")[out.vote_kernel],
             "dft_two_pass": out.dft_two_pass,
+            "dft_threads": out.dft_threads,
         }
 
     # -- bucketized forward model of complex tones (off-grid refinement) --

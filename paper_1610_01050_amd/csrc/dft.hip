@@ -23,8 +23,6 @@ namespace rsft {
 // paper's indexing, and sets flag bits |fhat|^2 >= gamma_s with ballots.
 // ---------------------------------------------------------------------------
 
-constexpr int kDftThreads = 1024;
-constexpr int kDftWaves = kDftThreads / 64;
 constexpr int kDftItems = 2;   // output tiles per wave between barriers
 
 // LDS position of bucket index idx: one pad float after every row of the
@@ -86,7 +84,7 @@ __device__ __forceinline__ void dft_tile(const float* __restrict__ re, const flo
 
 // The DFT along one dimension of length n for all B / n lines, in place.
 // Work items are (line group, output tile) pairs in group-major order; a
-// round of kDftWaves * R items holds whole groups (the tiles per group,
+// round of kWaves * R items holds whole groups (the tiles per group,
 // ceil(n/16) <= 8, divide 16), every item of a round is computed before any
 // of its outputs is written, and rounds touch disjoint lines.
 template <int kWaves>
@@ -204,10 +202,13 @@ __device__ __forceinline__ void mode_product_r16(float* __restrict__ re, float* 
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int plane, int pad,
-                                                          int frame0, int identity,
-                                                          int nchunks_override,
-                                                          const int32_t* __restrict__ order) {
+// TH threads per work-group (64 .. 1024): one wave per transform suits small
+// B (many transforms, each short), sixteen suit large B.
+template <int TH>
+__global__ __launch_bounds__(TH) void dft_kernel(DevPtrs p, int T, int plane, int pad, int frame0, int identity,
+                                                 int nchunks_override, const int32_t* __restrict__ order) {
+  constexpr int kDftThreads = TH;
+  constexpr int kDftWaves = TH / 64;
   extern __shared__ float smem[];
   float* re = smem;
   float* im = smem + plane;
@@ -227,13 +228,10 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
   const int wave = tid >> 6;
 
 
-  // Twiddles of each dimension (concatenated; B_d <= 128, one per thread)
-  // and the column-chunk partials of this round: the loads of a group are
-  // issued before the first of them is used.
-  // (every dimension's descriptor fields are read first, then the loads are
-  // issued together; entries beyond ndim exist and are not used)
+  // Twiddles of each dimension (concatenated; B_d <= 128) and the
+  // column-chunk partials of this round. (Every dimension's descriptor
+  // fields are read first; entries beyond ndim exist and are not used.)
   int twoff[kMaxDims];
-  float2 twv[kMaxDims];
   {
     const int nd = d.ndim;
     int bd[kMaxDims];
@@ -247,16 +245,14 @@ __global__ __launch_bounds__(kDftThreads) void dft_kernel(DevPtrs p, int T, int 
 #pragma unroll
     for (int dd = 0; dd < kMaxDims; ++dd) {
       twoff[dd] = acc;
-      const bool use = dd < nd && tid < bd[dd];
-      twv[dd] = use ? p.tw[toff[dd] + tid] : make_float2(0.f, 0.f);
-      if (dd < nd) acc += bd[dd];
+      if (dd < nd) {
+        for (int i = tid; i < bd[dd]; i += kDftThreads) tws[acc + i] = p.tw[toff[dd] + i];
+        acc += bd[dd];
+      }
     }
   }
   const int nch = nchunks_override > 0 ? nchunks_override : d.nchunks;
   const float2* part = p.part + d.part_off + rel * d.part_stride + int64_t(s) * B;
-#pragma unroll
-  for (int dd = 0; dd < kMaxDims; ++dd)
-    if (dd < d.ndim && tid < d.b[dd]) tws[twoff[dd] + tid] = twv[dd];   // fields cached by now
   // groups of kGrp buckets per thread (one group when B <= 4096)
   constexpr int kGrp = 4;
   for (int g0 = 0; g0 < B; g0 += kGrp * kDftThreads) {
@@ -562,19 +558,24 @@ int launch_dft_split(const DevPtrs& p, int64_t nframes, int T, int max_b0, int m
 }
 
 int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw, int identity,
-               int nchunks_override, const int32_t* order, void* stream) {
+               int nchunks_override, const int32_t* order, int threads, void* stream) {
   if (nframes <= 0) return hipSuccess;
   const size_t shmem = size_t(2 * plane) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
-  hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), unsigned(nframes)), dim3(kDftThreads), shmem,
-                     static_cast<hipStream_t>(stream), p, T, plane, pad, 0, identity, nchunks_override,
-                     order);
+  const dim3 grid{unsigned(T), unsigned(nframes), 1u};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (threads) {
+    case 64: hipLaunchKernelGGL(dft_kernel<64>, grid, dim3(64), shmem, st, p, T, plane, pad, 0, identity, nchunks_override, order); break;
+    case 256: hipLaunchKernelGGL(dft_kernel<256>, grid, dim3(256), shmem, st, p, T, plane, pad, 0, identity, nchunks_override, order); break;
+    case 1024: hipLaunchKernelGGL(dft_kernel<1024>, grid, dim3(1024), shmem, st, p, T, plane, pad, 0, identity, nchunks_override, order); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 static int launch_dft_frame(const DevPtrs& p, int64_t frame, int T, int plane, int pad, int sum_tw,
                             hipStream_t st) {
   const size_t shmem = size_t(2 * plane) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
-  hipLaunchKernelGGL(dft_kernel, dim3(unsigned(T), 1u), dim3(kDftThreads), shmem, st, p, T, plane,
+  hipLaunchKernelGGL(dft_kernel<1024>, dim3(unsigned(T), 1u), dim3(1024), shmem, st, p, T, plane,
                      pad, int(frame), 1, 1, static_cast<const int32_t*>(nullptr));
   return hipGetLastError();
 }

@@ -78,6 +78,7 @@ struct rsft_plan_s {
   int global_gains = 0;            // some frame's sum of L_d exceeds the estimate's LDS copy
   int split_ok = 1;                // every frame suits the two-pass DFT
   int dft_split = 1;               // RSFT_OPT_DFT_SPLIT: use it (where it applies)
+  int dft_threads = 1024;          // RSFT_OPT_DFT_THREADS: the one-work-group DFT's size
   int split_b0 = 0, split_g1 = 0, split_g2 = 0;   // its launch extents
   int vote_words = 1;              // RSFT_OPT_VOTE_WORDS: prefer the word-parallel vote
   int tab_words = 0;               // LDS words of its per-round table (largest frame)
@@ -563,6 +564,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
     pl->sum_tw_max = std::max(pl->sum_tw_max, sum_tw);
   }
   choose_vote_path(pl);
+  pl->dft_threads = pl->maxB <= 256 ? 64 : pl->maxB <= 1024 ? 256 : 1024;
   // chunks per frame are a power of two (N is); few of them: several frames
   // per scan work-group
   if (pl->uniform && pl->descs[0].cchunks <= 128) pl->scan_fpb = 256 / pl->descs[0].cchunks;
@@ -796,7 +798,7 @@ rsft_status dft_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
                                       pl->sum_tw_max, static_cast<float2*>(pl->d_inter.ptr), order, st));
   } else {
     LAUNCH_TRY(rsft::launch_dft(pl->ptrs, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0,
-                                order, st));
+                                order, pl->dft_threads, st));
   }
   return RSFT_OK;
 }
@@ -1018,22 +1020,36 @@ rsft_status rsft_autotune(rsft_plan_t pl, const void* d_input, int64_t batch, vo
       }
   if (st != RSFT_OK) return st;
   pl->fold = best;
-  // DFT: one work-group per transform, or the two-pass kernels; the fold
-  // of d_input leaves the partial buckets both read
-  if (pl->split_ok) {
+  // DFT: one work-group per transform at each work-group size, and the
+  // two-pass kernels where they apply; the fold of d_input leaves the
+  // partial buckets all of them read
+  {
     if ((st = fold_stage(pl, d_input, batch, s, pl->fold)) != RSFT_OK) return st;
-    float dft_ms[2] = {0.f, 0.f};
-    for (int v = 0; v < 2; ++v) {
-      pl->dft_split = v;
+    float best_ms = 0.f;
+    int best_split = 0, best_threads = pl->dft_threads;
+    bool have = false;
+    for (int v = 0; v < 4; ++v) {
+      const int threads = v == 0 ? 64 : v == 1 ? 256 : 1024;
+      if (v == 3 && !pl->split_ok) break;
+      pl->dft_split = v == 3 ? 1 : 0;
+      if (v < 3) pl->dft_threads = threads;
       if ((st = dft_stage(pl, batch, s)) != RSFT_OK) return st;
       HIP_TRY(hipEventRecord(e0, s));
       for (int r = 0; r < repeats && st == RSFT_OK; ++r) st = dft_stage(pl, batch, s);
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
       if (st != RSFT_OK) return st;
-      HIP_TRY(hipEventElapsedTime(&dft_ms[v], e0, e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (!have || ms < best_ms) {
+        have = true;
+        best_ms = ms;
+        best_split = pl->dft_split;
+        if (v < 3) best_threads = threads;
+      }
     }
-    pl->dft_split = dft_ms[1] <= dft_ms[0] ? 1 : 0;
+    pl->dft_split = best_split;
+    pl->dft_threads = best_threads;
   }
   // estimate layout: one execute of d_input leaves its flags and detected-
   // cell bitmap; scan + compact/estimate (which only read those) are then
@@ -1418,6 +1434,7 @@ rsft_status rsft_plan_info(rsft_plan_t pl, int64_t frame, rsft_plan_info_t* out)
   out->estimate_workers = pl->est_workers;
   out->vote_kernel = pl->vote_path;
   out->dft_two_pass = pl->split_ok && pl->dft_split ? 1 : 0;
+  out->dft_threads = pl->dft_threads;
   return RSFT_OK;
 }
 
@@ -1445,6 +1462,12 @@ rsft_status rsft_set_option(rsft_plan_t pl, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, "RSFT_OPT_VOTE_WORDS must be 0 or 1");
       pl->vote_words = int(value);
       choose_vote_path(pl);
+      drop_graphs(pl);
+      return RSFT_OK;
+    case RSFT_OPT_DFT_THREADS:
+      if (value != 64 && value != 256 && value != 1024)
+        return fail(RSFT_ERROR_INVALID_ARGUMENT, "RSFT_OPT_DFT_THREADS must be 64, 256 or 1024");
+      pl->dft_threads = int(value);
       drop_graphs(pl);
       return RSFT_OK;
     case RSFT_OPT_DFT_SPLIT:

@@ -146,9 +146,11 @@ int launch_fold(const DevPtrs& p, const void* input, int dtype, int64_t nframes,
                 int64_t tiles_per_frame, int64_t ntiles, int round0, int rounds,
                 int T, const FoldConfig& cfg, void* stream);
 // order (may be NULL): frame of each grid row, e.g. the frames of an uneven
-// batch by decreasing bucket count so that the largest transforms start first
+// batch by decreasing bucket count so that the largest transforms start
+// first; threads: work-group size, 64, 256 or 1024
 int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int sum_tw,
-               int identity_relabel, int nchunks_override, const int32_t* order, void* stream);
+               int identity_relabel, int nchunks_override, const int32_t* order, int threads,
+               void* stream);
 // The same transform in two passes (frames of D >= 2 whose trailing
 // dimensions hold at most kSplitMaxSlab buckets, KNOWN noise floor): pass 1
 // over slab groups into `inter` (bucket layout), pass 2 over column groups

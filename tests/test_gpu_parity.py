@@ -64,8 +64,8 @@ CASES = {
 }
 
 
-def _run_case(name, per_frame=False, noise="known", vote_words=1, dft_split=1):
-    from paper_1610_01050_amd import OPT_DFT_SPLIT, OPT_VOTE_WORDS
+def _run_case(name, per_frame=False, noise="known", vote_words=1, dft_split=1, dft_threads=None):
+    from paper_1610_01050_amd import OPT_DFT_SPLIT, OPT_DFT_THREADS, OPT_VOTE_WORDS
     shape, buckets, T, mu, dtype, batch, K, pfa, atten = CASES[name]
     print(f"case {name} per_frame={per_frame} noise={noise} vote_words={vote_words}", flush=True)
     npdt = np.complex128 if dtype == "c128" else np.complex64
@@ -82,6 +82,8 @@ def _run_case(name, per_frame=False, noise="known", vote_words=1, dft_split=1):
                  noise_mode=noise, max_detections=1 << 18)
     plan.set_option(OPT_VOTE_WORDS, vote_words)
     plan.set_option(OPT_DFT_SPLIT, dft_split)
+    if dft_threads is not None:
+        plan.set_option(OPT_DFT_THREADS, dft_threads)
     xd = torch.from_numpy(np.stack(frames)).to("cuda")
     if per_frame:
         plan.execute_per_frame(xd)
@@ -110,6 +112,29 @@ def test_single_workgroup_dft_matches_oracle(name):
     """The DFT stage with one work-group per (round, frame) instead of the
     two passes (RSFT_OPT_DFT_SPLIT = 0), the rest unchanged."""
     plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name, dft_split=0)
+    for f, ref in enumerate(refs):
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
+    plan.close()
+
+
+@pytest.mark.parametrize("threads", [64, 256, 1024])
+@pytest.mark.parametrize("name", ["ongrid_256x256_c128", "offgrid_1024x1024", "cube_256x128x32",
+                                  "one_dim_4096", "four_dim", "tiny_last_bucket"])
+def test_dft_work_group_sizes_match_oracle(name, threads):
+    """The one-work-group DFT at each work-group size (RSFT_OPT_DFT_THREADS:
+    one, four or sixteen waves per transform)."""
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case(name, dft_split=0, dft_threads=threads)
+    for f, ref in enumerate(refs):
+        _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
+    plan.close()
+
+
+@pytest.mark.parametrize("threads", [64, 256])
+def test_dft_work_group_sizes_estimated_noise_match_oracle(threads):
+    """The estimated noise floor (radix selection of the lower median in the
+    DFT kernel) with one and four waves per transform."""
+    plan, oplan, frames, refs, recs, counts, gbk, gfl = _run_case("short_rows_512x64", noise="estimated",
+                                                                  dft_split=0, dft_threads=threads)
     for f, ref in enumerate(refs):
         _check_frame(f, oplan, ref, recs, gbk[f], gfl[f])
     plan.close()
