@@ -389,10 +389,12 @@ __global__ __launch_bounds__(TH) void dft_kernel(DevPtrs p, int T, int plane, in
 // transform is spread over many small work-groups instead of one.
 //   pass 1: work-group (frame, round, slab group). A slab is the S = B / B_0
 //           buckets of one index along dimension 0; a group of G slabs
-//           (G S <= kSplitElems) sums its column-chunk partials into LDS and
+//           (G S <= kSplitGroup, or one slab when S is larger) sums its
+//           column-chunk partials into LDS and
 //           is transformed along dimensions 1 .. D-1 (the same mode
 //           products), then written in transform order to `inter`.
-//   pass 2: work-group (frame, round, column group). It owns C = min(S, 32)
+//   pass 2: work-group (frame, round, column group) of 1024 threads when the
+//           plan's largest B_0 is >= 64, else 256. It owns C = min(S, 32)
 //           consecutive trailing output positions J' (the paper's indexing)
 //           for every index along dimension 0: it loads the transform
 //           columns K' = tau J' (per dimension, tau_{s,d} j_d mod B_d), the
@@ -404,7 +406,6 @@ __global__ __launch_bounds__(TH) void dft_kernel(DevPtrs p, int T, int plane, in
 
 constexpr int kSplitThreads = 256;
 constexpr int kSplitWaves = kSplitThreads / 64;
-constexpr int kSplitElems = 4096;     // buckets per pass-1 work-group (at most)
 
 __device__ __forceinline__ int64_t split_frame(const int32_t* order, int64_t slot) {
   return order ? int64_t(order[slot]) : slot;
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(kSplitThreads) void dft_pass1_kernel(DevPtrs p, int
   const FrameDesc& d = desc_of(p, f);
   const int nd = d.ndim, B = d.B, b0 = d.b[0];
   const int S = B / b0;
-  const int G = S >= kSplitElems ? 1 : (kSplitElems / S < b0 ? kSplitElems / S : b0);
+  const int G = S >= kSplitGroup ? 1 : (kSplitGroup / S < b0 ? kSplitGroup / S : b0);
   const int groups = b0 / G;
   if (int(blockIdx.x) >= groups) return;
   const int E = G * S;                          // buckets of this work-group
@@ -469,8 +470,13 @@ __global__ __launch_bounds__(kSplitThreads) void dft_pass1_kernel(DevPtrs p, int
   for (int e = tid; e < E; e += kSplitThreads) out[e] = make_float2(re[lds_at(e, nls)], im[lds_at(e, nls)]);
 }
 
-__global__ __launch_bounds__(kSplitThreads) void dft_pass2_kernel(DevPtrs p, int T, const float2* __restrict__ inter,
-                                                                  const int32_t* __restrict__ order) {
+// TH2 threads: 1024 for B_0 >= 64 (the column group's B_0-point DFTs keep
+// sixteen waves busy), else 256.
+template <int TH2>
+__global__ __launch_bounds__(TH2) void dft_pass2_kernel(DevPtrs p, int T, const float2* __restrict__ inter,
+                                                        const int32_t* __restrict__ order) {
+  constexpr int kSplit2Threads = TH2;
+  constexpr int kSplit2Waves = TH2 / 64;
   extern __shared__ float smem[];
   const int64_t f = split_frame(order, blockIdx.z);
   const int s = blockIdx.y;
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(kSplitThreads) void dft_pass2_kernel(DevPtrs p, int
   const int64_t rel = rel_of(p, f);
   if (tid < b0) tws[tid] = p.tw[d.tw_off[0] + tid];
   const float2* src = inter + d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
-  for (int e = tid; e < E; e += kSplitThreads) {
+  for (int e = tid; e < E; e += kSplit2Threads) {
     const int k0 = e >> cs;
     const int jp = c0 + (e & (C - 1));         // trailing output position J'
     int kp = 0;                                 // its transform column K'
@@ -507,16 +513,16 @@ __global__ __launch_bounds__(kSplitThreads) void dft_pass2_kernel(DevPtrs p, int
   }
   __syncthreads();
   if (b0 >= 16)
-    mode_product_r16<kSplitWaves>(re, im, tws, b0, cs, C, cs);
+    mode_product_r16<kSplit2Waves>(re, im, tws, b0, cs, C, cs);
   else
-    mode_product<kSplitWaves>(re, im, tws, b0, cs, C, cs);
+    mode_product<kSplit2Waves>(re, im, tws, b0, cs, C, cs);
   const int64_t fb = d.bucket_off + rel * d.bucket_stride + int64_t(s) * B;
   float2* bout = p.buckets + fb;
   float* pout = p.powers + fb;
   uint32_t* fout = p.flags + d.flag_off + rel * d.flag_stride + int64_t(s) * d.words;
   const double gamma = d.gamma[s];
   const int t0 = d.tau[s][0];
-  for (int e00 = wave * 64; e00 < E; e00 += kSplitThreads) {
+  for (int e00 = wave * 64; e00 < E; e00 += kSplit2Threads) {
     const int e = e00 + lane;
     bool flag = false;
     int j = 0;
@@ -544,16 +550,20 @@ __global__ __launch_bounds__(kSplitThreads) void dft_pass2_kernel(DevPtrs p, int
 }
 
 int launch_dft_split(const DevPtrs& p, int64_t nframes, int T, int max_b0, int max_groups1, int max_groups2,
-                     int sum_tw, float2* inter, const int32_t* order, void* stream) {
+                     int max_e1, int sum_tw, float2* inter, const int32_t* order, void* stream) {
   if (nframes <= 0) return hipSuccess;
-  if (nframes > 65535 || T > 65535) return hipErrorInvalidValue;
+  if (nframes > 65535 || T > 65535 || max_e1 > kSplitMaxSlab) return hipErrorInvalidValue;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t sh1 = size_t(4 * kSplitElems) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
+  // two planes of at most 2 E floats (E buckets plus at most one pad each)
+  const size_t sh1 = size_t(4 * max_e1) * sizeof(float) + size_t(sum_tw) * sizeof(float2);
   hipLaunchKernelGGL(dft_pass1_kernel, dim3(unsigned(max_groups1), unsigned(T), unsigned(nframes)),
                      dim3(kSplitThreads), sh1, st, p, T, inter, order);
   const size_t sh2 = size_t(2 * (max_b0 * 32 + max_b0)) * sizeof(float) + size_t(max_b0) * sizeof(float2);
-  hipLaunchKernelGGL(dft_pass2_kernel, dim3(unsigned(max_groups2), unsigned(T), unsigned(nframes)),
-                     dim3(kSplitThreads), sh2, st, p, T, static_cast<const float2*>(inter), order);
+  const dim3 grid2{unsigned(max_groups2), unsigned(T), unsigned(nframes)};
+  if (max_b0 >= 64)
+    hipLaunchKernelGGL(dft_pass2_kernel<1024>, grid2, dim3(1024), sh2, st, p, T, static_cast<const float2*>(inter), order);
+  else
+    hipLaunchKernelGGL(dft_pass2_kernel<256>, grid2, dim3(256), sh2, st, p, T, static_cast<const float2*>(inter), order);
   return hipGetLastError();
 }
 

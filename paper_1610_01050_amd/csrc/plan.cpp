@@ -79,7 +79,7 @@ struct rsft_plan_s {
   int split_ok = 1;                // every frame suits the two-pass DFT
   int dft_split = 1;               // RSFT_OPT_DFT_SPLIT: use it (where it applies)
   int dft_threads = 1024;          // RSFT_OPT_DFT_THREADS: the one-work-group DFT's size
-  int split_b0 = 0, split_g1 = 0, split_g2 = 0;   // its launch extents
+  int split_b0 = 0, split_g1 = 0, split_g2 = 0, split_e1 = 0;   // its launch extents
   int vote_words = 1;              // RSFT_OPT_VOTE_WORDS: prefer the word-parallel vote
   int tab_words = 0;               // LDS words of its per-round table (largest frame)
   int vote_path = rsft::kVoteCells;
@@ -547,15 +547,17 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
       if (nl < 128 || nl > 4096 || tw > 16384) pl->words_ok = 0;
       else pl->tab_words = std::max(pl->tab_words, int(tw));
       // two-pass DFT extents: pass-1 groups of G slabs (S = B / B_0 buckets
-      // each, G S <= kSplitMaxSlab), pass-2 groups of min(S, 32) columns
+      // each, G S <= kSplitGroup, or one slab of up to kSplitMaxSlab),
+      // pass-2 groups of min(S, 32) columns
       const int b0 = d.b[0];
       const int S = d.B / b0;
       if (d.ndim < 2 || S > rsft::kSplitMaxSlab || d.noise_mode != RSFT_NOISE_KNOWN) {
         pl->split_ok = 0;
       } else {
-        const int G = std::min(rsft::kSplitMaxSlab / S, b0);
+        const int G = S >= rsft::kSplitGroup ? 1 : std::min(rsft::kSplitGroup / S, b0);
         pl->split_b0 = std::max(pl->split_b0, b0);
         pl->split_g1 = std::max(pl->split_g1, b0 / G);
+        pl->split_e1 = std::max(pl->split_e1, G * S);
         pl->split_g2 = std::max(pl->split_g2, S / std::min(S, 32));
       }
     }
@@ -795,7 +797,8 @@ rsft_status dft_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   const int32_t* order = pl->uniform ? nullptr : static_cast<const int32_t*>(pl->d_dft_order.ptr);
   if (pl->split_ok && pl->dft_split) {
     LAUNCH_TRY(rsft::launch_dft_split(pl->ptrs, batch, pl->T, pl->split_b0, pl->split_g1, pl->split_g2,
-                                      pl->sum_tw_max, static_cast<float2*>(pl->d_inter.ptr), order, st));
+                                      pl->split_e1, pl->sum_tw_max, static_cast<float2*>(pl->d_inter.ptr),
+                                      order, st));
   } else {
     LAUNCH_TRY(rsft::launch_dft(pl->ptrs, batch, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, 0, 0,
                                 order, pl->dft_threads, st));

@@ -155,10 +155,13 @@ int launch_dft(const DevPtrs& p, int64_t nframes, int T, int plane, int pad, int
 // dimensions hold at most kSplitMaxSlab buckets, KNOWN noise floor): pass 1
 // over slab groups into `inter` (bucket layout), pass 2 over column groups
 // with relabel, threshold and outputs. max_b0: largest B_0; max_groups1 / 2:
-// most slab / column groups of a frame; sum_tw: largest sum_d B_d.
+// most slab / column groups of a frame; max_e1: most buckets of a pass-1
+// group (G slabs of S buckets, G S <= kSplitGroup or G = 1); sum_tw:
+// largest sum_d B_d.
 constexpr int kSplitMaxSlab = 4096;
+constexpr int kSplitGroup = 1024;
 int launch_dft_split(const DevPtrs& p, int64_t nframes, int T, int max_b0, int max_groups1, int max_groups2,
-                     int sum_tw, float2* inter, const int32_t* order, void* stream);
+                     int max_e1, int sum_tw, float2* inter, const int32_t* order, void* stream);
 // vote paths: per cell (any shape), rows of 64..4096 cells (T <= 4), rows of
 // exactly 32 cells (bit-parallel masks), rows of 128..4096 cells (word-
 // parallel masks, any T)
