@@ -89,10 +89,11 @@ struct rsft_plan_s {
   int64_t ntiles_uneven = 0;     // uneven plans
   int64_t nchunk_list = 0;       // uneven plans with frames of different chunk counts
   int64_t nvote_list = 0;        // the same for the word-parallel vote's chunk groups
+  int exp_blocks = 0;            // the most kVoteExpWords blocks of bucket-row masks of a frame
   int scan_fpb = 1;              // frames per scan work-group
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles, d_chunk_list,
-      d_dft_order, d_vote_tab, d_vote_list, d_inter;
+      d_dft_order, d_vote_tab, d_vote_list, d_inter, d_vote_exp;
   DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
       d_offsets, d_records, d_scan_done, d_chunk_items, d_item_counts, d_item_offsets;
   rsft::DevPtrs ptrs{};
@@ -461,7 +462,8 @@ void free_plan(rsft_plan_s* pl) {
   if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
   DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
                           &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_chunk_list,
-                          &pl->d_dft_order, &pl->d_vote_tab, &pl->d_vote_list, &pl->d_inter, &pl->d_part,
+                          &pl->d_dft_order, &pl->d_vote_tab, &pl->d_vote_list, &pl->d_inter, &pl->d_vote_exp,
+                          &pl->d_part,
                           &pl->d_buckets, &pl->d_powers, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
                           &pl->d_scan_done, &pl->d_chunk_items, &pl->d_item_counts, &pl->d_item_offsets};
@@ -643,11 +645,13 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
 
   // word-parallel vote: per descriptor and round, M_s[b][w] with bit x of
   // word w set when cell 32 w + x of a row lies in bucket column b, i.e.
-  // the preimages x = [sigma_inv u] of u in [b L, (b + 1) L) (Def. 4); and
-  // for uneven plans whose frames differ in chunk count, the list of
+  // the preimages x = [sigma_inv u] of u in [b L, (b + 1) L) (Def. 4); per
+  // frame the workspace of its bucket-row masks, [T][B / B_last][W] words;
+  // and for uneven plans whose frames differ in chunk count, the list of
   // (frame, first chunk) groups of kVoteCpw chunks
   std::vector<uint32_t> vote_tab;
   std::vector<int32_t> vote_list;
+  int64_t vexp_off = 0;
   if (pl->words_ok) {
     for (auto& d : pl->descs) {
       const int D = d.ndim;
@@ -655,6 +659,11 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
       const uint32_t W = nl / 32;
       const uint32_t bl = uint32_t(d.b[D - 1]);
       const int lsl = d.lshift[D - 1];
+      const int64_t ew = int64_t(d.B / int32_t(bl)) * W;
+      d.vexp_off = vexp_off;
+      d.vexp_stride = int64_t(d.T) * ew;
+      vexp_off += (pl->uniform ? pl->max_frames : 1) * d.vexp_stride;
+      pl->exp_blocks = std::max(pl->exp_blocks, int((ew + rsft::kVoteExpWords - 1) / rsft::kVoteExpWords));
       d.vtab_off = int64_t(vote_tab.size());
       vote_tab.resize(vote_tab.size() + size_t(d.T) * bl * W, 0u);
       uint32_t* t0 = vote_tab.data() + d.vtab_off;
@@ -694,6 +703,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = alloc(pl->d_part, size_t(part_off) * sizeof(float2))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_buckets, size_t(bucket_off) * sizeof(float2))) != RSFT_OK) return st;
   if (pl->split_ok && (st = alloc(pl->d_inter, size_t(bucket_off) * sizeof(float2))) != RSFT_OK) return st;
+  if (pl->words_ok && (st = alloc(pl->d_vote_exp, size_t(vexp_off) * sizeof(uint32_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_powers, size_t(bucket_off) * sizeof(float))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_flags, size_t(flag_off) * sizeof(uint32_t))) != RSFT_OK) return st;
   if ((st = alloc(pl->d_bitmap, size_t(bitmap_off) * sizeof(uint32_t))) != RSFT_OK) return st;
@@ -738,6 +748,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.chunk_list = static_cast<const int32_t*>(pl->d_chunk_list.ptr);
   q.vote_tab = static_cast<const uint32_t*>(pl->d_vote_tab.ptr);
   q.vote_list = static_cast<const int32_t*>(pl->d_vote_list.ptr);
+  q.vote_exp = static_cast<uint32_t*>(pl->d_vote_exp.ptr);
   return RSFT_OK;
 }
 
@@ -809,7 +820,7 @@ rsft_status dft_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
 // Reverse mapping, accumulation and second stage for the whole batch.
 rsft_status vote_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   LAUNCH_TRY(rsft::launch_vote(pl->ptrs, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask,
-                               pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, st));
+                               pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, pl->exp_blocks, st));
   return RSFT_OK;
 }
 
@@ -1108,7 +1119,7 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
     const auto& d = pl->descs[size_t(pl->uniform ? 0 : f)];
     for (int r = 0; r < pl->T; ++r) LAUNCH_TRY(rsft::launch_plain_fold(q, d_input, pl->dtype, f, r, d.B, s));
     LAUNCH_TRY(rsft::launch_plain_dft(q, f, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, s));
-    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, int(f), 0, 0, pl->tab_words, s));
+    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, int(f), 0, 0, pl->tab_words, pl->exp_blocks, s));
   }
   if (batch > 0) {
     const rsft_status es = estimate_stage(pl, batch, s);
@@ -1337,7 +1348,7 @@ rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* strea
   for (int64_t f = 0; f < batch; ++f) words += size_t(pl->descs[size_t(pl->uniform ? 0 : f)].flag_stride);
   HIP_TRY(hipMemcpyAsync(pl->d_flags.ptr, d_flags, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   const auto& q = pl->ptrs;
-  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, s));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, pl->exp_blocks, s));
   return estimate_stage(pl, batch, s);
 }
 

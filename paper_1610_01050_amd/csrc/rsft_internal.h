@@ -77,6 +77,7 @@ struct FrameDesc {
   int32_t segments;                    // 1: round s reads segment s (input [T][N] per frame)
   int32_t pad0;
   int64_t vtab_off;                    // uint32 [T][B_last][N_last / 32]: word-parallel vote tables
+  int64_t vexp_off, vexp_stride;       // uint32 [T][B / B_last][N_last / 32]: bucket-row masks
 };
 
 // A detection as the estimate stores it on the device: 32 bytes instead of
@@ -130,6 +131,9 @@ struct DevPtrs {
   // first chunk) groups of kVoteCpw chunks; (-1, -1) pads
   const uint32_t* vote_tab;
   const int32_t* vote_list;
+  // word-parallel vote: per frame and round the cell mask of every bucket
+  // row (FrameDesc::vexp_off), written by its first kernel, read by its second
+  uint32_t* vote_exp;
 };
 
 // Launch configuration of the fold stage, chosen per plan.
@@ -167,14 +171,16 @@ int launch_dft_split(const DevPtrs& p, int64_t nframes, int T, int max_b0, int m
 // parallel masks, any T)
 constexpr int kVoteCells = 0, kVoteRows = 1, kVoteMasks32 = 2, kVoteWords = 3;
 constexpr int kVoteCpw = 4;   // compaction chunks per work-group of the word-parallel vote
+constexpr int kVoteExpWords = 1024;   // bucket-row mask words per work-group of its first kernel
 // nlist > 0: one work-group per chunk_list entry (whole batch, frame0 = 0);
 // the word-parallel vote instead takes vote_list (nvlist > 0: one work-group
 // per (frame, first chunk) entry, groups of kVoteCpw chunks). tab_words: LDS
 // words of that vote's per-round table, the largest B_last * N_last / 32 of
-// the plan
+// the plan; exp_blocks: the most kVoteExpWords blocks of bucket-row masks
+// (B / B_last * N_last / 32 words per round) of a frame
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
                 int max_words, int dims_mask, int vote_path, int frame0, int64_t nlist, int64_t nvlist,
-                int tab_words, void* stream);
+                int tab_words, int exp_blocks, void* stream);
 // items: 1 also lists the estimate's overflow items (plans with overflow
 // workers); fpb: frames per work-group (1, or 256 / chunks per frame in a
 // uniform plan of at most 128 chunks per frame)

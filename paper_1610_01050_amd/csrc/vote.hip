@@ -364,21 +364,25 @@ __global__ __launch_bounds__(kVoteThreads) void vote_rows_kernel(DevPtrs p, int 
 // x]_{N_last} >> log2 L_last in round s (Def. 3), and the cells of column b
 // are the L_last preimages x = [sigma_inv u] for u in [b L, (b+1) L)
 // (Def. 4). The plan holds per descriptor the tables M_s[b][w] (bit x of
-// word w set when cell 32 w + x lies in column b). Per round a work-group
-// copies that round's table and flags into LDS, then each thread ORs, for
-// the 128 cells (four words) it owns in each of its kVoteCpw chunks, the
-// table rows of the flagged columns of the row's B_last-bit flag window:
-// one 16-byte LDS read per flagged bucket instead of one bucket lookup per
-// cell. The T round masks are combined by a bit-sliced counter of NB bits
-// and compared with mu (NB = 0: mu = T, a plain AND), giving the same bits
-// as the per-cell sum of eq. a_i. One work-group per group of kVoteCpw
-// consecutive compaction chunks of a frame (so the table copies are shared
-// by kVoteCpw chunks); each thread writes its four bitmap words per chunk
-// with one store.
+// word w set when cell 32 w + x lies in column b). The leading coordinates
+// of a row fix its bucket row r_s (the leading bucket indices) and the
+// column part of the mapping does not depend on them, so every row that
+// maps to bucket row r in round s has the same round-s mask
+//   E_s[r][w] = OR over the flagged columns b of bucket row r of M_s[b][w].
+// There are B / B_last bucket rows against N / N_last cell rows (L_d times
+// fewer per leading dimension), so the masks are built once per (frame,
+// round) by vote_expand_kernel, and vote_words_kernel reads, for the 128
+// cells (four words) a thread owns in each of its kVoteCpw chunks, the T
+// masks E_s[r_s(row)] and combines them by a bit-sliced counter of NB bits
+// compared with mu (NB = 0: mu = T, a plain AND): the same bits as the
+// per-cell sum of eq. a_i. One work-group per group of kVoteCpw consecutive
+// compaction chunks of a frame; each thread writes its four bitmap words per
+// chunk with one store.
 constexpr int kWordsPerVoteThread = 4;
+static_assert(kVoteExpWords == kVoteThreads * kWordsPerVoteThread, "one expand block per work-group");
 
 // Loads of round s's table pieces and flag words of this thread (see
-// vote_words_kernel), all issued before any is used.
+// vote_expand_kernel), all issued before any is used.
 template <int kTabPer, int kFlagPer>
 __device__ __forceinline__ void vote_prefetch(uint4 (&tnext)[kTabPer], uint32_t (&fnext)[kFlagPer],
                                               const uint32_t* gtab, const uint32_t* fl, int s, uint32_t ntab,
@@ -397,12 +401,74 @@ __device__ __forceinline__ void vote_prefetch(uint4 (&tnext)[kTabPer], uint32_t 
   }
 }
 
-template <int D, int NB, int kTabPer>
-__global__ __launch_bounds__(kVoteThreads) void vote_words_kernel(DevPtrs p, int T, int mu, int frame0,
-                                                                 int use_list, int tab_words) {
+// One work-group per (block of kVoteExpWords mask words, round, frame): the
+// round's table M_s and flag words in LDS, then each thread ORs, for its
+// four words of one bucket row, the table rows of that bucket row's flagged
+// columns (one 16-byte LDS read per flagged bucket).
+template <int kTabPer>
+__global__ __launch_bounds__(kVoteThreads) void vote_expand_kernel(DevPtrs p, int frame0, int tab_words) {
   extern __shared__ uint32_t smem[];
-  uint32_t* tab = smem;                       // [B_last][W] words of the current round
-  uint32_t* rflags = smem + tab_words;        // the current round's flag words
+  uint32_t* tab = smem;                       // [B_last][W] words of the round
+  uint32_t* rflags = smem + tab_words;        // the round's flag words
+  const int64_t f = frame0 + int64_t(blockIdx.z);
+  const int s = int(blockIdx.y);
+  const FrameDesc& d = desc_of(p, f);
+  const int D = d.ndim;
+  const uint32_t nl = uint32_t(d.n[D - 1]);
+  const uint32_t bl = uint32_t(d.b[D - 1]);
+  const uint32_t W = nl >> 5;
+  const uint32_t total = (uint32_t(d.B) / bl) * W;          // mask words of the round
+  const uint32_t blk0 = blockIdx.x * uint32_t(kVoteExpWords);
+  if (blk0 >= total || s >= d.T) return;
+  const int64_t rel = rel_of(p, f);
+  const int words = d.words;
+  const uint32_t ntab = bl * W;
+  const uint32_t npiece = ntab >> 2;
+  constexpr int kFlagPer = kMaxBuckets / 32 / kVoteThreads;
+  uint4 tv[kTabPer];
+  uint32_t fv[kFlagPer];
+  vote_prefetch<kTabPer, kFlagPer>(tv, fv, p.vote_tab + d.vtab_off, p.flags + d.flag_off + rel * d.flag_stride, s,
+                                   ntab, npiece, words);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kTabPer; ++k) {
+    const uint32_t i = uint32_t(tid) + uint32_t(k) * kVoteThreads;
+    if (i < npiece) reinterpret_cast<uint4*>(tab)[i] = tv[k];
+  }
+#pragma unroll
+  for (int k = 0; k < kFlagPer; ++k) {
+    const int i = tid + k * kVoteThreads;
+    if (i < words) rflags[i] = fv[k];
+  }
+  __syncthreads();
+  const uint32_t q = blk0 + uint32_t(tid) * uint32_t(kWordsPerVoteThread);
+  if (q >= total) return;
+  const uint32_t w0 = q & (W - 1u);                          // W >= 4, a power of two
+  const uint32_t rowpart = (q / W) * bl;                     // first bucket of the bucket row
+  uint32_t m0 = 0u, m1 = 0u, m2 = 0u, m3 = 0u;
+  // the bucket row's B_last flags: whole words when B_last >= 32, else a
+  // field (rowpart is a multiple of B_last: the window never straddles)
+  const int nw = bl >= 32u ? int(bl >> 5) : 1;
+  for (int kw = 0; kw < nw; ++kw) {
+    uint32_t win = rflags[(rowpart >> 5) + uint32_t(kw)];
+    if (bl < 32u) win = (win >> (rowpart & 31u)) & ((1u << bl) - 1u);
+    while (win) {
+      const uint32_t b = uint32_t(kw) * 32u + uint32_t(__ffs(win) - 1);
+      win &= win - 1u;
+      const uint4 v = *reinterpret_cast<const uint4*>(tab + b * W + w0);
+      m0 |= v.x;
+      m1 |= v.y;
+      m2 |= v.z;
+      m3 |= v.w;
+    }
+  }
+  uint32_t* e = p.vote_exp + d.vexp_off + rel * d.vexp_stride + int64_t(s) * total + q;
+  *reinterpret_cast<uint4*>(e) = make_uint4(m0, m1, m2, m3);
+}
+
+template <int D, int NB>
+__global__ __launch_bounds__(kVoteThreads) void vote_words_kernel(DevPtrs p, int T, int mu, int frame0,
+                                                                 int use_list) {
   __shared__ uint32_t wcount[kVoteCpw][kVoteThreads / 64];
   constexpr int kW = kWordsPerVoteThread;
   constexpr int kAcc = NB > 0 ? NB : 1;
@@ -424,7 +490,6 @@ __global__ __launch_bounds__(kVoteThreads) void vote_words_kernel(DevPtrs p, int
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int words = d.words;
   uint32_t nm[D], ls[D], bs[D], ns[D];
 #pragma unroll
   for (int dd = 0; dd < D; ++dd) {
@@ -435,10 +500,10 @@ __global__ __launch_bounds__(kVoteThreads) void vote_words_kernel(DevPtrs p, int
   }
   const uint32_t nl = nm[D - 1] + 1u;
   const uint32_t bl = uint32_t(d.b[D - 1]);
+  const uint32_t lbl = uint32_t(__builtin_ctz(bl));
   const uint32_t W = nl >> 5;
-  const uint32_t ntab = bl * W;
-  const uint32_t* fl = p.flags + d.flag_off + rel * d.flag_stride;
-  const uint32_t* gtab = p.vote_tab + d.vtab_off;
+  const uint32_t ew = (uint32_t(d.B) >> lbl) * W;            // mask words per round
+  const uint32_t* E = p.vote_exp + d.vexp_off + rel * d.vexp_stride;
   const int q0 = tid * kW;                                  // first word of this thread in a chunk
   const uint32_t w0 = uint32_t(q0) & (W - 1u);              // their word offset in the row (W >= 4)
   bool active[kVoteCpw];
@@ -457,32 +522,12 @@ __global__ __launch_bounds__(kVoteThreads) void vote_words_kernel(DevPtrs p, int
 #pragma unroll
     for (int q = 0; q < kVoteCpw * kW; ++q) acc[a][q] = NB > 0 ? 0u : ~0u;
 
-  // Round s's table and flags are loaded into registers while round s - 1
-  // is being voted (kTabPer 16-byte pieces per thread cover the plan's
-  // largest table, kFlagPer flag words B = 16384 buckets), then stored to
-  // LDS once every thread is done with the previous round.
-  constexpr int kFlagPer = kMaxBuckets / 32 / kVoteThreads;
-  const uint32_t npiece = ntab >> 2;
-  uint4 tnext[kTabPer];
-  uint32_t fnext[kFlagPer];
-  vote_prefetch<kTabPer, kFlagPer>(tnext, fnext, gtab, fl, 0, ntab, npiece, words);
   for (int s = 0; s < T; ++s) {
-    __syncthreads();                                        // readers of the previous round are done
-#pragma unroll
-    for (int k = 0; k < kTabPer; ++k) {
-      const uint32_t i = uint32_t(tid) + uint32_t(k) * kVoteThreads;
-      if (i < npiece) reinterpret_cast<uint4*>(tab)[i] = tnext[k];
-    }
-#pragma unroll
-    for (int k = 0; k < kFlagPer; ++k) {
-      const int i = tid + k * kVoteThreads;
-      if (i < words) rflags[i] = fnext[k];
-    }
-    __syncthreads();
-    if (s + 1 < T) vote_prefetch<kTabPer, kFlagPer>(tnext, fnext, gtab, fl, s + 1, ntab, npiece, words);
+    // the round's mask words of the rows of all chunks, loaded before use
+    uint4 v[kVoteCpw];
 #pragma unroll
     for (int k = 0; k < kVoteCpw; ++k) {
-      uint32_t m0 = 0u, m1 = 0u, m2 = 0u, m3 = 0u;
+      v[k] = make_uint4(0u, 0u, 0u, 0u);
       if (active[k]) {
         uint32_t rowpart = 0u;
 #pragma unroll
@@ -490,24 +535,12 @@ __global__ __launch_bounds__(kVoteThreads) void vote_words_kernel(DevPtrs p, int
           const uint32_t cd = uint32_t(iw[k] >> ns[dd]) & nm[dd];
           rowpart |= (((uint32_t(d.sigma[s][dd]) * cd) & nm[dd]) >> ls[dd]) << bs[dd];
         }
-        // the row's B_last flags: whole words when B_last >= 32, else a
-        // field (rowpart is a multiple of B_last: the window never straddles)
-        const int nw = bl >= 32u ? int(bl >> 5) : 1;
-        for (int kw = 0; kw < nw; ++kw) {
-          uint32_t win = rflags[(rowpart >> 5) + uint32_t(kw)];
-          if (bl < 32u) win = (win >> (rowpart & 31u)) & ((1u << bl) - 1u);
-          while (win) {
-            const uint32_t b = uint32_t(kw) * 32u + uint32_t(__ffs(win) - 1);
-            win &= win - 1u;
-            const uint4 v = *reinterpret_cast<const uint4*>(tab + b * W + w0);
-            m0 |= v.x;
-            m1 |= v.y;
-            m2 |= v.z;
-            m3 |= v.w;
-          }
-        }
+        v[k] = *reinterpret_cast<const uint4*>(E + int64_t(s) * ew + (rowpart >> lbl) * W + w0);
       }
-      const uint32_t m[kW] = {m0, m1, m2, m3};
+    }
+#pragma unroll
+    for (int k = 0; k < kVoteCpw; ++k) {
+      const uint32_t m[kW] = {v[k].x, v[k].y, v[k].z, v[k].w};
 #pragma unroll
       for (int q = 0; q < kW; ++q) {
         if constexpr (NB == 0) {
@@ -561,25 +594,21 @@ __global__ __launch_bounds__(kVoteThreads) void vote_words_kernel(DevPtrs p, int
   }
 }
 
-// counters of NB bits hold counts up to T; NB = 0: mu = T (a plain AND);
-// TP table pieces of 16 bytes per thread
-template <int D, int TP>
-static void launch_vote_words(dim3 grid, size_t shmem, hipStream_t st, const DevPtrs& p, int T, int mu,
-                              int frame0, int use_list, int tab_words) {
-  const size_t sh = size_t(tab_words) * 4 + shmem;
-  if (mu == T) hipLaunchKernelGGL((vote_words_kernel<D, 0, TP>), grid, dim3(kVoteThreads), sh, st, p, T, mu, frame0, use_list, tab_words);
-  else if (T <= 3) hipLaunchKernelGGL((vote_words_kernel<D, 2, TP>), grid, dim3(kVoteThreads), sh, st, p, T, mu, frame0, use_list, tab_words);
-  else if (T <= 7) hipLaunchKernelGGL((vote_words_kernel<D, 3, TP>), grid, dim3(kVoteThreads), sh, st, p, T, mu, frame0, use_list, tab_words);
-  else hipLaunchKernelGGL((vote_words_kernel<D, 7, TP>), grid, dim3(kVoteThreads), sh, st, p, T, mu, frame0, use_list, tab_words);
+// counters of NB bits hold counts up to T; NB = 0: mu = T (a plain AND)
+template <int D>
+static void launch_vote_words(dim3 grid, hipStream_t st, const DevPtrs& p, int T, int mu, int frame0,
+                              int use_list) {
+  if (mu == T) hipLaunchKernelGGL((vote_words_kernel<D, 0>), grid, dim3(kVoteThreads), 0, st, p, T, mu, frame0, use_list);
+  else if (T <= 3) hipLaunchKernelGGL((vote_words_kernel<D, 2>), grid, dim3(kVoteThreads), 0, st, p, T, mu, frame0, use_list);
+  else if (T <= 7) hipLaunchKernelGGL((vote_words_kernel<D, 3>), grid, dim3(kVoteThreads), 0, st, p, T, mu, frame0, use_list);
+  else hipLaunchKernelGGL((vote_words_kernel<D, 7>), grid, dim3(kVoteThreads), 0, st, p, T, mu, frame0, use_list);
 }
 
 template <int D>
 static void launch_vote_d(const DevPtrs& p, dim3 grid, size_t shmem, hipStream_t st, int T, int mu,
-                          int frame0, int use_list, bool rows, bool masks, bool wordsp, int tab_words) {
+                          int frame0, int use_list, bool rows, bool masks, bool wordsp) {
   if (wordsp) {
-    if (tab_words <= 4 * 2 * kVoteThreads) launch_vote_words<D, 2>(grid, shmem, st, p, T, mu, frame0, use_list, tab_words);
-    else if (tab_words <= 4 * 8 * kVoteThreads) launch_vote_words<D, 8>(grid, shmem, st, p, T, mu, frame0, use_list, tab_words);
-    else launch_vote_words<D, 16>(grid, shmem, st, p, T, mu, frame0, use_list, tab_words);
+    launch_vote_words<D>(grid, st, p, T, mu, frame0, use_list);
     return;
   }
   if (masks) {   // counters of NB bits hold counts up to T
@@ -602,12 +631,27 @@ static void launch_vote_d(const DevPtrs& p, dim3 grid, size_t shmem, hipStream_t
 
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks, int max_words,
                 int dims_mask, int vote_path, int frame0, int64_t nlist, int64_t nvlist, int tab_words,
-                void* stream) {
+                int exp_blocks, void* stream) {
   if (nframes <= 0) return hipSuccess;
   const bool wordsp = vote_path == kVoteWords;
-  // the word-parallel vote stages one round's flags; the others all rounds'
-  const size_t shmem = size_t(wordsp ? 1 : T) * size_t(max_words) * sizeof(uint32_t);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (wordsp) {
+    // bucket-row masks of every (frame, round): the round's table and flags
+    // in LDS (kTabPer 16-byte table pieces per thread cover the plan's largest)
+    if (nframes > 65535 || T > 65535 || exp_blocks <= 0) return hipErrorInvalidValue;
+    const dim3 eg{unsigned(exp_blocks), unsigned(T), unsigned(nframes)};
+    const size_t esh = (size_t(tab_words) + size_t(max_words)) * sizeof(uint32_t);
+    if (tab_words <= 4 * 2 * kVoteThreads)
+      hipLaunchKernelGGL(vote_expand_kernel<2>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words);
+    else if (tab_words <= 4 * 8 * kVoteThreads)
+      hipLaunchKernelGGL(vote_expand_kernel<8>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words);
+    else if (tab_words <= 4 * 16 * kVoteThreads)
+      hipLaunchKernelGGL(vote_expand_kernel<16>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words);
+    else
+      return hipErrorInvalidValue;
+  }
+  // the other paths stage all rounds' flags
+  const size_t shmem = wordsp ? 0 : size_t(T) * size_t(max_words) * sizeof(uint32_t);
   // the word-parallel vote takes its own list of chunk groups
   const int64_t list_len = wordsp ? nvlist : nlist;
   const int use_list = list_len > 0 ? 1 : 0;
@@ -616,10 +660,10 @@ int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunk
   const dim3 grid = use_list ? dim3{unsigned(list_len), 1u, 1u} : dim3{unsigned(gx), unsigned(nframes), 1u};
   const bool rows = vote_path == kVoteRows && T <= 4;
   const bool masks = vote_path == kVoteMasks32;
-  if (dims_mask & 1) launch_vote_d<1>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp, tab_words);
-  if (dims_mask & 2) launch_vote_d<2>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp, tab_words);
-  if (dims_mask & 4) launch_vote_d<3>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp, tab_words);
-  if (dims_mask & 8) launch_vote_d<4>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp, tab_words);
+  if (dims_mask & 1) launch_vote_d<1>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp);
+  if (dims_mask & 2) launch_vote_d<2>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp);
+  if (dims_mask & 4) launch_vote_d<3>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp);
+  if (dims_mask & 8) launch_vote_d<4>(p, grid, shmem, st, T, mu, frame0, use_list, rows, masks, wordsp);
   return hipGetLastError();
 }
 

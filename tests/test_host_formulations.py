@@ -9,9 +9,11 @@ its plain definition (no GPU, no shared code with the HIP path).
   mu} (Def. 3, eq. a_i) cell by cell.
 * The word-parallel vote of rows of 128..4096 cells: per round a table
   M_s[b][w] built by scattering each column's preimages x = [sigma^-1 u]
-  (Def. 4), the OR of the flagged columns' table rows over four words at a
-  time, and the rounds combined by AND (mu = T) or a bit-sliced counter.
-  Must equal the same per-cell sum.
+  (Def. 4); per bucket row r (leading bucket indices) the mask E_s[r] = OR
+  of the flagged columns' table rows, built once for all cell rows that map
+  to r; each cell row then gathers E_s[r_s(row)] four words at a time, and
+  the rounds are combined by AND (mu = T) or a bit-sliced counter. Must
+  equal the same per-cell sum.
 * Segmented scan of many small frames in one 256-wide block: each frame's
   exclusive chunk offsets, records and overflow items (records beyond the
   first 1024 of a chunk that fit the frame's capacity, in items of 256) must
@@ -97,8 +99,8 @@ def test_mask32_vote_equals_per_cell_sum(shape, buckets, T, mu, p):
 
 
 def votes_words(shape, buckets, sigma, flags, mu):
-    """The word-parallel form for rows of 128..4096 cells (four words per
-    thread, tables rebuilt per round)."""
+    """The word-parallel form for rows of 128..4096 cells: per round the
+    bucket-row masks, then four words per thread gathered from them."""
     D, T = len(shape), len(sigma)
     nl, bl = shape[-1], buckets[-1]
     W = nl // 32
@@ -114,18 +116,20 @@ def votes_words(shape, buckets, sigma, flags, mu):
         for u in range(nl):                     # scatter the preimages
             x = (sinv * u) % nl
             tab[u // L, x // 32] |= np.uint64(1 << (x % 32))
-        for g in range(0, nwords, 4):           # one thread: four words of one row
+        nrows = int(np.prod(buckets)) // bl     # bucket rows
+        E = np.zeros((nrows, W), dtype=np.uint64)
+        for r in range(nrows):                  # expand: once per bucket row
+            for b in range(bl):
+                if flags[s][r * bl + b]:
+                    E[r] |= tab[b]
+        for g in range(0, nwords, 4):           # gather: four words of one cell row
             coords = np.unravel_index(g * 32, shape)
-            rowpart = 0
+            r = 0
             for d in range(D - 1):
                 Ld = shape[d] // buckets[d]
-                rowpart = rowpart * buckets[d] + ((sig[d] * coords[d]) % shape[d]) // Ld
-            rowpart *= bl
+                r = r * buckets[d] + ((sig[d] * coords[d]) % shape[d]) // Ld
             w0 = g % W
-            m = np.zeros(4, dtype=np.uint64)
-            for b in range(bl):
-                if flags[s][rowpart + b]:
-                    m |= tab[b, w0:w0 + 4]
+            m = E[r, w0:w0 + 4]
             for q in range(4):
                 if nb == 0:
                     acc[0, g + q] &= m[q]
