@@ -90,10 +90,11 @@ struct rsft_plan_s {
   int64_t nchunk_list = 0;       // uneven plans with frames of different chunk counts
   int64_t nvote_list = 0;        // the same for the word-parallel vote's chunk groups
   int exp_blocks = 0;            // the most kVoteExpWords blocks of bucket-row masks of a frame
+  int64_t nexp_list = 0;         // uneven plans: (frame, block) entries of those masks
   int scan_fpb = 1;              // frames per scan work-group
   // device arrays
   DeviceBuffer d_descs, d_wrow, d_wcol, d_rowlist, d_tw, d_gains, d_win, d_flat, d_tiles, d_chunk_list,
-      d_dft_order, d_vote_tab, d_vote_list, d_inter, d_vote_exp;
+      d_dft_order, d_vote_tab, d_vote_list, d_inter, d_vote_exp, d_vote_exp_list;
   DeviceBuffer d_part, d_buckets, d_powers, d_flags, d_bitmap, d_chunk_counts, d_chunk_offsets, d_counts,
       d_offsets, d_records, d_scan_done, d_chunk_items, d_item_counts, d_item_offsets;
   rsft::DevPtrs ptrs{};
@@ -463,7 +464,7 @@ void free_plan(rsft_plan_s* pl) {
   DeviceBuffer* bufs[] = {&pl->d_descs, &pl->d_wrow, &pl->d_wcol, &pl->d_rowlist, &pl->d_tw,
                           &pl->d_gains, &pl->d_win, &pl->d_flat, &pl->d_tiles, &pl->d_chunk_list,
                           &pl->d_dft_order, &pl->d_vote_tab, &pl->d_vote_list, &pl->d_inter, &pl->d_vote_exp,
-                          &pl->d_part,
+                          &pl->d_vote_exp_list, &pl->d_part,
                           &pl->d_buckets, &pl->d_powers, &pl->d_flags, &pl->d_bitmap, &pl->d_chunk_counts,
                           &pl->d_chunk_offsets, &pl->d_counts, &pl->d_offsets, &pl->d_records,
                           &pl->d_scan_done, &pl->d_chunk_items, &pl->d_item_counts, &pl->d_item_offsets};
@@ -650,7 +651,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   // and for uneven plans whose frames differ in chunk count, the list of
   // (frame, first chunk) groups of kVoteCpw chunks
   std::vector<uint32_t> vote_tab;
-  std::vector<int32_t> vote_list;
+  std::vector<int32_t> vote_list, vote_exp_list;
   int64_t vexp_off = 0;
   if (pl->words_ok) {
     for (auto& d : pl->descs) {
@@ -676,6 +677,19 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
         }
       }
     }
+    if (!pl->uniform) {
+      // mask blocks of every frame, largest frames first
+      for (int64_t k = 0; k < nframes; ++k) {
+        const int32_t i = dft_order[size_t(k)];
+        const auto& d = pl->descs[size_t(i)];
+        const int64_t ew = int64_t(d.B / d.b[d.ndim - 1]) * (d.n[d.ndim - 1] / 32);
+        for (int64_t b = 0; b * rsft::kVoteExpWords < ew; ++b) {
+          vote_exp_list.push_back(i);
+          vote_exp_list.push_back(int32_t(b));
+        }
+      }
+      pl->nexp_list = int64_t(vote_exp_list.size() / 2);
+    }
     if (!pl->uniform && pl->nchunk_list > 0) {
       for (int64_t i = 0; i < nframes; ++i)
         for (int32_t c = 0; c < pl->descs[size_t(i)].cchunks; c += rsft::kVoteCpw) {
@@ -690,6 +704,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   if ((st = upload(pl->d_descs, pl->descs)) != RSFT_OK) return st;
   if ((st = upload(pl->d_vote_tab, vote_tab)) != RSFT_OK) return st;
   if ((st = upload(pl->d_vote_list, vote_list)) != RSFT_OK) return st;
+  if ((st = upload(pl->d_vote_exp_list, vote_exp_list)) != RSFT_OK) return st;
   if ((st = upload(pl->d_wrow, ht.wrow)) != RSFT_OK) return st;
   if ((st = upload(pl->d_wcol, ht.wcol)) != RSFT_OK) return st;
   if ((st = upload(pl->d_rowlist, ht.rowlist)) != RSFT_OK) return st;
@@ -749,6 +764,7 @@ rsft_status create_plan(const rsft_params* frames, int64_t nframes, rsft_plan_s*
   q.vote_tab = static_cast<const uint32_t*>(pl->d_vote_tab.ptr);
   q.vote_list = static_cast<const int32_t*>(pl->d_vote_list.ptr);
   q.vote_exp = static_cast<uint32_t*>(pl->d_vote_exp.ptr);
+  q.vote_exp_list = static_cast<const int32_t*>(pl->d_vote_exp_list.ptr);
   return RSFT_OK;
 }
 
@@ -820,7 +836,7 @@ rsft_status dft_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
 // Reverse mapping, accumulation and second stage for the whole batch.
 rsft_status vote_stage(rsft_plan_s* pl, int64_t batch, hipStream_t st) {
   LAUNCH_TRY(rsft::launch_vote(pl->ptrs, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask,
-                               pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, pl->exp_blocks, st));
+                               pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, pl->exp_blocks, pl->nexp_list, st));
   return RSFT_OK;
 }
 
@@ -1119,7 +1135,7 @@ rsft_status rsft_execute_per_frame(rsft_plan_t pl, const void* d_input, int64_t 
     const auto& d = pl->descs[size_t(pl->uniform ? 0 : f)];
     for (int r = 0; r < pl->T; ++r) LAUNCH_TRY(rsft::launch_plain_fold(q, d_input, pl->dtype, f, r, d.B, s));
     LAUNCH_TRY(rsft::launch_plain_dft(q, f, pl->T, pl->dft_plane, pl->dft_pad, pl->sum_tw_max, s));
-    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, int(f), 0, 0, pl->tab_words, pl->exp_blocks, s));
+    LAUNCH_TRY(rsft::launch_vote(q, 1, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, int(f), 0, 0, pl->tab_words, pl->exp_blocks, 0, s));
   }
   if (batch > 0) {
     const rsft_status es = estimate_stage(pl, batch, s);
@@ -1348,7 +1364,7 @@ rsft_status rsft_vote_flags(rsft_plan_t pl, const uint32_t* d_flags, void* strea
   for (int64_t f = 0; f < batch; ++f) words += size_t(pl->descs[size_t(pl->uniform ? 0 : f)].flag_stride);
   HIP_TRY(hipMemcpyAsync(pl->d_flags.ptr, d_flags, words * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   const auto& q = pl->ptrs;
-  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, pl->exp_blocks, s));
+  LAUNCH_TRY(rsft::launch_vote(q, batch, pl->T, pl->mu, pl->max_cchunks, pl->max_words, pl->dims_mask, pl->vote_path, 0, pl->nchunk_list, pl->nvote_list, pl->tab_words, pl->exp_blocks, pl->nexp_list, s));
   return estimate_stage(pl, batch, s);
 }
 

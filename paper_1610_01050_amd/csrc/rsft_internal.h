@@ -132,8 +132,11 @@ struct DevPtrs {
   const uint32_t* vote_tab;
   const int32_t* vote_list;
   // word-parallel vote: per frame and round the cell mask of every bucket
-  // row (FrameDesc::vexp_off), written by its first kernel, read by its second
+  // row (FrameDesc::vexp_off), written by its first kernel, read by its
+  // second; for uneven plans the first kernel's work, [n][2] (frame, block
+  // of kVoteExpWords mask words), largest frames first
   uint32_t* vote_exp;
+  const int32_t* vote_exp_list;
 };
 
 // Launch configuration of the fold stage, chosen per plan.
@@ -177,10 +180,12 @@ constexpr int kVoteExpWords = 1024;   // bucket-row mask words per work-group of
 // per (frame, first chunk) entry, groups of kVoteCpw chunks). tab_words: LDS
 // words of that vote's per-round table, the largest B_last * N_last / 32 of
 // the plan; exp_blocks: the most kVoteExpWords blocks of bucket-row masks
-// (B / B_last * N_last / 32 words per round) of a frame
+// (B / B_last * N_last / 32 words per round) of a frame; nexp_list > 0: one
+// work-group of the masks per vote_exp_list entry and round (whole batch,
+// frame0 = 0)
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks,
                 int max_words, int dims_mask, int vote_path, int frame0, int64_t nlist, int64_t nvlist,
-                int tab_words, int exp_blocks, void* stream);
+                int tab_words, int exp_blocks, int64_t nexp_list, void* stream);
 // items: 1 also lists the estimate's overflow items (plans with overflow
 // workers); fpb: frames per work-group (1, or 256 / chunks per frame in a
 // uniform plan of at most 128 chunks per frame)

@@ -401,16 +401,27 @@ __device__ __forceinline__ void vote_prefetch(uint4 (&tnext)[kTabPer], uint32_t 
   }
 }
 
-// One work-group per (block of kVoteExpWords mask words, round, frame): the
-// round's table M_s and flag words in LDS, then each thread ORs, for its
-// four words of one bucket row, the table rows of that bucket row's flagged
-// columns (one 16-byte LDS read per flagged bucket).
+// One work-group per (block of kVoteExpWords mask words, round, frame), or
+// per (vote_exp_list entry, round): the round's table M_s and flag words in
+// LDS, then each thread ORs, for its four words of one bucket row, the table
+// rows of that bucket row's flagged columns (one 16-byte LDS read per
+// flagged bucket).
 template <int kTabPer>
-__global__ __launch_bounds__(kVoteThreads) void vote_expand_kernel(DevPtrs p, int frame0, int tab_words) {
+__global__ __launch_bounds__(kVoteThreads) void vote_expand_kernel(DevPtrs p, int frame0, int tab_words,
+                                                                   int use_list) {
   extern __shared__ uint32_t smem[];
   uint32_t* tab = smem;                       // [B_last][W] words of the round
   uint32_t* rflags = smem + tab_words;        // the round's flag words
-  const int64_t f = frame0 + int64_t(blockIdx.z);
+  int64_t f;
+  uint32_t blk;
+  if (use_list) {
+    const int32_t* e = p.vote_exp_list + 2 * int64_t(blockIdx.x);
+    f = e[0];
+    blk = uint32_t(e[1]);
+  } else {
+    f = frame0 + int64_t(blockIdx.z);
+    blk = blockIdx.x;
+  }
   const int s = int(blockIdx.y);
   const FrameDesc& d = desc_of(p, f);
   const int D = d.ndim;
@@ -418,7 +429,7 @@ __global__ __launch_bounds__(kVoteThreads) void vote_expand_kernel(DevPtrs p, in
   const uint32_t bl = uint32_t(d.b[D - 1]);
   const uint32_t W = nl >> 5;
   const uint32_t total = (uint32_t(d.B) / bl) * W;          // mask words of the round
-  const uint32_t blk0 = blockIdx.x * uint32_t(kVoteExpWords);
+  const uint32_t blk0 = blk * uint32_t(kVoteExpWords);
   if (blk0 >= total || s >= d.T) return;
   const int64_t rel = rel_of(p, f);
   const int words = d.words;
@@ -631,22 +642,25 @@ static void launch_vote_d(const DevPtrs& p, dim3 grid, size_t shmem, hipStream_t
 
 int launch_vote(const DevPtrs& p, int64_t nframes, int T, int mu, int max_cchunks, int max_words,
                 int dims_mask, int vote_path, int frame0, int64_t nlist, int64_t nvlist, int tab_words,
-                int exp_blocks, void* stream) {
+                int exp_blocks, int64_t nexp_list, void* stream) {
   if (nframes <= 0) return hipSuccess;
   const bool wordsp = vote_path == kVoteWords;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (wordsp) {
     // bucket-row masks of every (frame, round): the round's table and flags
     // in LDS (kTabPer 16-byte table pieces per thread cover the plan's largest)
-    if (nframes > 65535 || T > 65535 || exp_blocks <= 0) return hipErrorInvalidValue;
-    const dim3 eg{unsigned(exp_blocks), unsigned(T), unsigned(nframes)};
+    const int el = nexp_list > 0 ? 1 : 0;
+    if (nframes > 65535 || T > 65535 || exp_blocks <= 0 || (el && (frame0 != 0 || nexp_list >= (int64_t(1) << 31))))
+      return hipErrorInvalidValue;
+    const dim3 eg = el ? dim3{unsigned(nexp_list), unsigned(T), 1u}
+                       : dim3{unsigned(exp_blocks), unsigned(T), unsigned(nframes)};
     const size_t esh = (size_t(tab_words) + size_t(max_words)) * sizeof(uint32_t);
     if (tab_words <= 4 * 2 * kVoteThreads)
-      hipLaunchKernelGGL(vote_expand_kernel<2>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words);
+      hipLaunchKernelGGL(vote_expand_kernel<2>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words, el);
     else if (tab_words <= 4 * 8 * kVoteThreads)
-      hipLaunchKernelGGL(vote_expand_kernel<8>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words);
+      hipLaunchKernelGGL(vote_expand_kernel<8>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words, el);
     else if (tab_words <= 4 * 16 * kVoteThreads)
-      hipLaunchKernelGGL(vote_expand_kernel<16>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words);
+      hipLaunchKernelGGL(vote_expand_kernel<16>, eg, dim3(kVoteThreads), esh, st, p, frame0, tab_words, el);
     else
       return hipErrorInvalidValue;
   }
