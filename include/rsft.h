@@ -496,8 +496,11 @@ enum {
   RSFT_OPT_ESTIMATE_WORKERS = 5,
   /* vote kernel for plans whose frames all have rows (last dimension) of
      128..4096 cells and B_last * N_last / 32 <= 16384: 1 = word-parallel
-     masks (default), 0 = enumeration of the candidate cells of flagged
-     buckets (T <= 4; larger T keeps the masks). Same detections either way. */
+     masks (default: per frame and round the cell mask of each bucket row,
+     then T mask words gathered per 32 cells; the plan holds T (B / B_last)
+     N_last / 32 words per frame for the masks), 0 = enumeration of the
+     candidate cells of flagged buckets (T <= 4; larger T keeps the masks).
+     Same detections either way. */
   RSFT_OPT_VOTE_WORDS = 6,
   /* DFT stage for plans whose frames all have D >= 2, B / B_0 <= 4096 and
      the KNOWN noise floor: 1 = two passes over many small work-groups (the
