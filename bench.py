@@ -849,6 +849,21 @@ def main():
         copy_ms.append(c0.elapsed_time(c1))
     copy_gbs = 2 * xa.numel() * 8 / (float(np.median(copy_ms[1:])) * 1e-3) / 1e9
     log(f"copy (negation, 2 GiB moved): {copy_gbs:.0f} GB/s")
+    # measured read bandwidth: torch's sum over rows of 1024 floats of the same
+    # 1 GiB (reads it all, writes 1 MiB), the read-only reference of the fold
+    rows = torch.view_as_real(xa).view(-1, 1024)
+    rsum = torch.empty(rows.shape[0], device=dev)
+    read_ms = []
+    for _ in range(6):
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        torch.sum(rows, dim=1, out=rsum)
+        c1.record()
+        torch.cuda.synchronize()
+        read_ms.append(c0.elapsed_time(c1))
+    del rows, rsum
+    read_gbs = xa.numel() * 8 / (float(np.median(read_ms[1:])) * 1e-3) / 1e9
+    log(f"read (row sums of the 1 GiB input): {read_gbs:.0f} GB/s")
     sigma = synth.shared_sigma(WORKLOAD)
     plan = Plan(shape, buckets, rounds=T, sigma=sigma, window_atten_db=cfg["atten_db"],
                 pfa=pfa, dtype="c64", max_batch=FRAMES, max_detections=1 << 16)
@@ -924,6 +939,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "fold",
                      "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
+                     "measured_read_gbs": read_gbs, "frac_of_measured_read": achieved / read_gbs,
                      "algorithmic_bytes_per_launch": fold_bytes,
                      "avg_launch_ms": fold_ms},
         "stage_ms": stages,
