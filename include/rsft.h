@@ -196,8 +196,10 @@ typedef struct rsft_plan_s* rsft_plan_t;
  *                 frame occupies prod N_d elements). Shapes, sigma, windows
  *                 and Pfa may differ per frame; rounds, mu and dtype may not.
  * Builds the windows, permuted weight tables, thresholds and DFT tables on
- * the host in FP64 and uploads them (one blocking copy). *out is set to NULL
- * on failure. Errors: INVALID_ARGUMENT, NOT_POW2, BAD_SIGMA, UNSUPPORTED
+ * the host in FP64 and uploads them (one blocking copy). Launch shapes
+ * start from the defaults, or from the choices of an earlier rsft_autotune
+ * in this process on a plan of the same signature (see rsft_autotune).
+ * *out is set to NULL on failure. Errors: INVALID_ARGUMENT, NOT_POW2, BAD_SIGMA, UNSUPPORTED
  * (B_d > 128 in some dimension, B > 16384 buckets per frame, N_d > 2^30,
  * N >= 2^40), OUT_OF_MEMORY, DEVICE.
  */
@@ -253,8 +255,14 @@ rsft_status rsft_execute_tail(rsft_plan_t plan, void* stream);
  *   groups); the workers are kept when at least 3% faster. How dense the
  *   detections are depends on the data, hence timing on the caller's input.
  * The choices are reported by rsft_plan_info and leave the results
- * unchanged (bit for bit for the vote and the estimate layout). Synchronizes the stream;
- * afterwards the plan holds the results of an execute of d_input.
+ * unchanged (bit for bit for the vote and the estimate layout). They are
+ * also kept for the life of the process under the plan's signature (device,
+ * batch capacity, rounds, mu, dtype, segment mode, and every frame's shape,
+ * buckets and noise mode): rsft_plan starts a later plan of the same
+ * signature from them (thread-safe; RSFT_OPT_* settings made after
+ * rsft_plan override them as usual). Synchronizes the stream;
+ * afterwards the plan holds the results of an execute of d_input (a
+ * pending rsft_execute_fold is cancelled, as by rsft_execute).
  * Errors: as rsft_execute.
  */
 rsft_status rsft_autotune(rsft_plan_t plan, const void* d_input, int64_t batch, void* stream,

@@ -399,10 +399,11 @@ class Plan:
         self.last_batch = self._folded
 
     def autotune(self, x, batch=None, repeats=5, stream=None):
-        """Time the fold stage's launch shapes and the two compact/estimate
-        layouts on `x` and keep the fastest (rsft_autotune); returns the
-        fold's average duration in ms. The plan then holds the results of an
-        execute of `x`."""
+        """Time the launch shapes of every stage on `x` and keep the fastest
+        (rsft_autotune: fold shape, DFT form and size, vote kernel, estimate
+        layout; a later plan of the same signature starts from them);
+        returns the fold's average duration in ms. The plan then holds the
+        results of an execute of `x`."""
         if batch is None:
             batch = x.shape[0] if self.uniform else len(self.descs)
         self._check_input(x, batch)
@@ -410,6 +411,9 @@ class Plan:
         _check(self._lib, self._lib.rsft_autotune(self._h, ctypes.c_void_p(x.data_ptr()), int(batch),
                                                   _stream_handle(stream), int(repeats),
                                                   ctypes.byref(best)))
+        if batch > 0:
+            self.last_batch = int(batch)
+            self._folded = None
         return best.value
 
     def execute_per_frame(self, x, batch=None, stream=None):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -922,6 +923,51 @@ rsft_status drain_timing(rsft_plan_s* pl, TimingSet& ts) {
 
 extern "C" {
 
+namespace {
+
+// Launch shapes chosen by rsft_autotune, kept for the life of the process
+// per plan signature: a later plan of the same signature starts from them.
+struct TunedShapes {
+  rsft::FoldConfig fold;
+  int dft_split, dft_threads, vote_words, est_workers;
+};
+std::mutex g_tuned_mu;
+std::map<std::string, TunedShapes> g_tuned;
+
+// Device, batch layout, rounds, mu, dtype, segment mode and every frame's
+// shape, buckets and noise mode: what the tuned launch shapes depend on
+// (sigma, windows and Pfa do not change them).
+std::string plan_signature(const rsft_plan_s* pl) {
+  std::string k = std::to_string(pl->device) + ";" + std::to_string(pl->uniform) + ";" +
+                  std::to_string(pl->max_frames) + ";" + std::to_string(pl->T) + ";" + std::to_string(pl->mu) +
+                  ";" + std::to_string(pl->dtype) + ";" + std::to_string(pl->segments);
+  for (const auto& d : pl->descs) {
+    k += ";" + std::to_string(d.noise_mode);
+    for (int dd = 0; dd < d.ndim; ++dd) k += "," + std::to_string(d.n[dd]) + "/" + std::to_string(d.b[dd]);
+  }
+  return k;
+}
+
+void remember_tuning(const rsft_plan_s* pl) {
+  const TunedShapes t{pl->fold, pl->dft_split, pl->dft_threads, pl->vote_words, pl->est_workers};
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
+  g_tuned[plan_signature(pl)] = t;
+}
+
+void apply_remembered_tuning(rsft_plan_s* pl) {
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
+  const auto it = g_tuned.find(plan_signature(pl));
+  if (it == g_tuned.end()) return;
+  pl->fold = it->second.fold;
+  pl->dft_split = it->second.dft_split;
+  pl->dft_threads = it->second.dft_threads;
+  pl->vote_words = it->second.vote_words;
+  choose_vote_path(pl);
+  pl->est_workers = it->second.est_workers;
+}
+
+}  // namespace
+
 rsft_status rsft_plan(const rsft_params* frames, int64_t nframes, rsft_plan_t* out) {
   if (out) *out = nullptr;
   if (!frames || !out || nframes < 1) return fail(RSFT_ERROR_INVALID_ARGUMENT, "NULL argument or nframes < 1");
@@ -954,6 +1000,7 @@ rsft_status rsft_plan(const rsft_params* frames, int64_t nframes, rsft_plan_t* o
     free_plan(pl);
     return st;
   }
+  apply_remembered_tuning(pl);
   *out = pl;
   return RSFT_OK;
 }
@@ -1016,6 +1063,7 @@ rsft_status rsft_autotune(rsft_plan_t pl, const void* d_input, int64_t batch, vo
   if (st != RSFT_OK) return st;
   if (batch == 0) return RSFT_OK;
   if (repeats <= 0) repeats = 5;
+  pl->folded_batch = -1;   // the timed folds overwrite a pending fold's partial buckets
   hipStream_t s = static_cast<hipStream_t>(stream);
   struct Events {  // released on every return path
     hipEvent_t e[2] = {nullptr, nullptr};
@@ -1120,6 +1168,7 @@ rsft_status rsft_autotune(rsft_plan_t pl, const void* d_input, int64_t batch, vo
   }
   pl->est_workers = est_ms[1] < 0.97f * est_ms[0] ? 1 : 0;
   drop_graphs(pl);   // captured graphs hold the previous launch shape
+  remember_tuning(pl);
   if (best_ms) *best_ms = double(best_t);
   return RSFT_OK;
 }
