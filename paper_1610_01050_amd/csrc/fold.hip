@@ -157,18 +157,34 @@ __device__ __forceinline__ void fold_tile(const FoldArgs& p, const void* __restr
     for (int s = 0; s < TG; ++s)
 #pragma unroll
       for (int v = 0; v < V; ++v) cr[s][v] = ci[s][v] = 0.f;
-#pragma unroll 2
-    for (int i = g - j * gpc; i < R; i += gpc) {
-      const int row = rlj[i];
-      float2 x[V];
-      load_vec<C128, NT, V>(in, int64_t(row) * nl + col, x);
+    // kRows rows of the group at a time: their row indices, then their
+    // samples and row weights, are loaded together before any is used
+    constexpr int kRows = 4;
+    for (int i0 = g - j * gpc; i0 < R; i0 += kRows * gpc) {
+      int row[kRows];
 #pragma unroll
-      for (int s = 0; s < TG; ++s) {
-        const float2 w = wrow[int64_t(round0 + s) * rows_total + row];
+      for (int k = 0; k < kRows; ++k) {
+        const int i = i0 + k * gpc;
+        row[k] = rlj[i < R ? i : i0];
+      }
+      float2 x[kRows][V];
+      float2 w[kRows][TG];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          cr[s][v] = fmaf(w.x, x[v].x, fmaf(-w.y, x[v].y, cr[s][v]));
-          ci[s][v] = fmaf(w.x, x[v].y, fmaf(w.y, x[v].x, ci[s][v]));
+      for (int k = 0; k < kRows; ++k) {
+        load_vec<C128, NT, V>(in, int64_t(row[k]) * nl + col, x[k]);
+#pragma unroll
+        for (int s = 0; s < TG; ++s) w[k][s] = wrow[int64_t(round0 + s) * rows_total + row[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        if (i0 + k * gpc < R) {
+#pragma unroll
+          for (int s = 0; s < TG; ++s)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              cr[s][v] = fmaf(w[k][s].x, x[k][v].x, fmaf(-w[k][s].y, x[k][v].y, cr[s][v]));
+              ci[s][v] = fmaf(w[k][s].x, x[k][v].y, fmaf(w[k][s].y, x[k][v].x, ci[s][v]));
+            }
         }
       }
     }
