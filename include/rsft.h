@@ -243,8 +243,9 @@ rsft_status rsft_execute_tail(rsft_plan_t plan, void* stream);
  * Choose the plan's launch shapes by timing them on d_input (same contract
  * as rsft_execute) with hipEvents on `stream`, `repeats` runs each (<= 0: 5):
  * - fold stage (the HBM-bound stage): work-group size (256 / 512 threads),
- *   samples per thread (4 / 2), ordinary vs non-temporal input loads; the
- *   fastest is kept and *best_ms (may be NULL) gets its average duration;
+ *   samples per thread (4 / 2), ordinary vs non-temporal input loads, each
+ *   timed in two passes; the fastest is kept and *best_ms (may be NULL)
+ *   gets its average duration in its faster pass;
  * - DFT: one work-group per transform at each work-group size
  *   (RSFT_OPT_DFT_THREADS) and, where it applies, the two passes
  *   (RSFT_OPT_DFT_SPLIT); the fastest kept;

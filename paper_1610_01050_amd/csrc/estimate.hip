@@ -286,19 +286,37 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M, G>& e, int T, 
     for (int k = 0; k < 4; ++k) votes += int((wd[k] >> sh[k]) & 1u);
   }
   // neighbour `code` against the cell: it must lie strictly below the cell's
-  // magnitude when its row-major index is lower, at most equal when higher
+  // magnitude when its row-major index is lower, at most equal when higher.
+  // Row-major order is decided by the first dimension whose offset is not
+  // zero: offset -1 gives a lower index unless the cell is at 0 (it wraps to
+  // N_d - 1), offset +1 a higher one unless the cell is at N_d - 1 (it wraps
+  // to 0). N_d >= 2, so a neighbour other than the cell itself differs from
+  // it. (The digits of `code` are compile-time constants where the loops
+  // over the neighbourhood are unrolled.)
+  bool below_m[D], below_p[D];
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) {
+    below_m[dd] = cell[dd] != 0u;
+    below_p[dd] = cell[dd] == e.nm[dd];
+  }
   auto visit = [&](int code, float p0, float pc, bool& peak) {
-    unsigned long long nflat = 0ull;
+    int od[D];
     int c = code;
 #pragma unroll
     for (int dd = D - 1; dd >= 0; --dd) {
-      const int o = c % 3 - 1;
+      od[dd] = c % 3 - 1;
       c /= 3;
-      const uint32_t nb = (cell[dd] + uint32_t(o) + e.nm[dd] + 1u) & e.nm[dd];
-      nflat |= (unsigned long long)nb << e.ns[dd];
     }
-    if (nflat == flat) return;       // a dimension of length <= 2 wraps onto the cell
-    if (nflat < flat) {
+    bool decided = false, lower = false;
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd) {
+      if (!decided && od[dd] != 0) {
+        lower = od[dd] < 0 ? below_m[dd] : below_p[dd];
+        decided = true;
+      }
+    }
+    if (!decided) return;            // the cell itself
+    if (lower) {
       if (!(p0 > pc)) peak = false;
     } else {
       if (!(p0 >= pc)) peak = false;
