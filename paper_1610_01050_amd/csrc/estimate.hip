@@ -50,7 +50,7 @@ struct EstFrame {
   static constexpr int kM = M > 0 ? M : 1;
   uint32_t nm[D], lm[D], ls[D], bs[D], ns[D];
   const float* ig[D];              // inverse flat-window gains per dimension (global)
-  const float* igs;                // the same in LDS (dimension d at goff[d]) when in_lds
+  const float* igs;                // their squares in LDS (dimension d at goff[d]) when they fit
   uint32_t goff[D];
   int mu, T;
   uint32_t sig_est[kM][D];
@@ -63,18 +63,23 @@ struct EstFrame {
   int B;
 };
 
-// The inverse flat-window gain of dimension d at offset idx inside a
-// bucket: from the LDS copy, or (G: plans with a frame whose sum of L_d
-// exceeds kGainLds) from global memory.
+// The squared inverse flat-window gain of dimension d at offset idx inside
+// a bucket (magnitudes are handled squared): from the LDS copy, which holds
+// the squares, or (G: plans with a frame whose sum of L_d exceeds kGainLds)
+// from global memory.
 template <int D, int M, bool G>
-__device__ __forceinline__ float inv_gain(const EstFrame<D, M, G>& e, int dd, uint32_t idx) {
-  if constexpr (G) return e.ig[dd][idx];
-  else return e.igs[e.goff[dd] + idx];
+__device__ __forceinline__ float inv_gain_sq(const EstFrame<D, M, G>& e, int dd, uint32_t idx) {
+  if constexpr (G) {
+    const float ig = e.ig[dd][idx];
+    return ig * ig;
+  } else {
+    return e.igs[e.goff[dd] + idx];
+  }
 }
 
-// load_frame also copies the frame's inverse gains to `sgain` (LDS) when
-// they fit (all threads of the work-group call it; a barrier follows the
-// copy).
+// load_frame also copies the frame's squared inverse gains to `sgain`
+// (LDS) when they fit (all threads of the work-group call it; a barrier
+// follows the copy).
 template <int D, int M, bool G>
 __device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d, int64_t rel,
                                            EstFrame<D, M, G>& e, float* sgain) {
@@ -95,7 +100,10 @@ __device__ __forceinline__ void load_frame(const DevPtrs& p, const FrameDesc& d,
   if constexpr (!G) {
 #pragma unroll
     for (int dd = 0; dd < D; ++dd)
-      for (uint32_t k = threadIdx.x; k <= e.lm[dd]; k += kEstThreads) sgain[e.goff[dd] + k] = e.ig[dd][k];
+      for (uint32_t k = threadIdx.x; k <= e.lm[dd]; k += kEstThreads) {
+        const float ig = e.ig[dd][k];
+        sgain[e.goff[dd] + k] = ig * ig;
+      }
   }
   __syncthreads();
   e.mu = d.mu;
@@ -195,8 +203,7 @@ __device__ __forceinline__ float neighbour_power_dyn(const EstFrame<D, M, G>& e,
       const int o = c % 3 - 1;
       c /= 3;
       const uint32_t u = (u0[q][dd] + e.sig_est[q][dd] * uint32_t(o)) & e.nm[dd];
-      const float ig = inv_gain(e, dd, u & e.lm[dd]);
-      gg *= ig * ig;
+      gg *= inv_gain_sq(e, dd, u & e.lm[dd]);
       jf |= (u >> e.ls[dd]) << e.bs[dd];
     }
     v[q] = e.pw_est[q][jf] * gg;
@@ -225,8 +232,7 @@ __device__ __forceinline__ float neighbour_power_any(const EstFrame<D, M, G>& e,
       c /= 3;
       const uint32_t sg = uint32_t(e.sig[s * kMaxDims + dd]);
       const uint32_t u = (sg * cell[dd] + sg * uint32_t(o)) & e.nm[dd];
-      const float ig = inv_gain(e, dd, u & e.lm[dd]);
-      gg *= ig * ig;
+      gg *= inv_gain_sq(e, dd, u & e.lm[dd]);
       jf |= (u >> e.ls[dd]) << e.bs[dd];
     }
     const float x = e.pw[int64_t(s) * e.B + jf] * gg;
@@ -351,8 +357,7 @@ __device__ __forceinline__ void write_record(const EstFrame<D, M, G>& e, int T, 
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
           const uint32_t u = (u0 + sg * uint32_t(o - 1)) & e.nm[dd];
-          const float ig = inv_gain(e, dd, u & e.lm[dd]);
-          g[q][dd][o] = ig * ig;
+          g[q][dd][o] = inv_gain_sq(e, dd, u & e.lm[dd]);
           jb[q][dd][o] = (u >> e.ls[dd]) << e.bs[dd];
         }
       }
