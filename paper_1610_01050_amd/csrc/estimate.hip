@@ -442,11 +442,17 @@ __device__ __forceinline__ void estimate_list(const DevPtrs& p, const FrameDesc&
   }
 }
 
-// Waves per SIMD the register allocation aims at: five where the record's
-// registers fit in 96 VGPRs, fewer for the larger neighbourhoods (D = 4 keeps
-// its neighbourhood in 81 KB of LDS: one work-group per compute unit).
+// Waves per SIMD the register allocation aims at, as many as fit without
+// spilling (the gathers are latency-bound, so more waves hide more of
+// them): six for 2-D records of up to three rounds (80 VGPRs), four for 3-D
+// ones (128), fewer for more rounds; D = 4 keeps its neighbourhood in 81 KB
+// of LDS (one work-group per compute unit).
 constexpr int est_waves(int D, int M) {
-  return M == kEstAny ? (D >= 4 ? 1 : 2) : D <= 1 || (D == 2 && M <= 3) ? 5 : D == 2 ? 4 : D == 3 ? 2 : 1;
+  return M == kEstAny ? (D >= 4 ? 1 : 2)
+         : D <= 1     ? 5
+         : D == 2     ? (M <= 3 ? 6 : 4)
+         : D == 3     ? (M <= 3 ? 4 : 2)
+                      : 1;
 }
 
 // estimate_list for a frame of `ne` estimation rounds, 1 <= ne <= MMAX
